@@ -1,0 +1,206 @@
+/*
+ * planb.h -- C ABI of an MI355X (gfx950) library for batched IPv6
+ * longest-prefix-match lookup on a linearized B+-tree of elementary intervals.
+ *
+ * Method: "PlanB: Efficient Software IPv6 Lookup with Linearized B+-Tree"
+ * (arXiv 2604.14650).  Section references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ *  - An IPv6 address or prefix is a planb_addr_t {hi, lo}: hi holds address
+ *    bytes 0..7 read as a big-endian integer, lo bytes 8..15.  In memory it is
+ *    two little-endian uint64 words, hi first: 16 bytes.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are GPU memory
+ *    of the current HIP device (hipMalloc, or a torch CUDA tensor).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Lookup calls only enqueue work: results are valid after the stream is
+ *    synchronised.  They never allocate or synchronise, so they can be
+ *    captured into a HIP graph.
+ *  - Functions returning int give PLANB_OK (0) or a negative planb_status;
+ *    functions returning a pointer give NULL on failure.  On failure
+ *    planb_last_error() returns a message for the calling thread.
+ */
+#ifndef PLANB_H
+#define PLANB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct planb_addr {
+    uint64_t hi; /* address bits 127..64 */
+    uint64_t lo; /* address bits 63..0  */
+} planb_addr_t;
+
+/* The next hop returned for an address no rule covers (no ::/0 in the FIB).
+ * It stands for the paper's "-1" of Algorithm 2 / the default route of the
+ * interval-partitioning step; it is reserved and may not be a rule's next hop. */
+#define PLANB_NO_ROUTE 0xFFFFu
+
+typedef enum planb_status {
+    PLANB_OK = 0,
+    PLANB_EINVAL = -1,  /* bad argument: length > 128, reserved next hop, NULL or misaligned pointer */
+    PLANB_EDUP = -2,    /* the same (prefix, length) given twice after masking host bits */
+    PLANB_ENOMEM = -3,  /* host or device allocation failed */
+    PLANB_EDEVICE = -4, /* a HIP call or kernel launch failed */
+    PLANB_ERANGE = -5   /* a size exceeds what the structure or call supports */
+} planb_status_t;
+
+/* Opaque handle of one built FIB: owns the device copies of the key array
+ * (the linearized B+-tree) and of the next-hop array, plus any learned model. */
+typedef struct planb_fib planb_fib_t;
+
+/* Build-time parameters.  Zero-initialise and set what you need. */
+typedef struct planb_params {
+    uint32_t fanout;        /* b: children per internal node, 8, 16 or 32 (0 -> 16).
+                               A node holds k = b-1 keys plus one sentinel slot:
+                               b 16-byte slots, so nodes are 128/256/512 bytes. */
+    uint32_t keys_per_lane; /* lookup tuning, see planb_set_tuning (0 -> default) */
+    int32_t lds_levels;     /* lookup tuning, see planb_set_tuning (-1 or 0 -> default) */
+    uint32_t flags;         /* PLANB_FLAG_* */
+} planb_params_t;
+
+/* Merge neighbouring elementary intervals that resolve to the same next hop.
+ * Off by default: the paper does not merge; merging changes no result. */
+#define PLANB_FLAG_MERGE_EQUAL_NH 1u
+
+/*
+ * planb_build -- the pre-computation of Section 3 ("From 2D Prefixes to 1D
+ * Intervals", "1D Search with Linearized B+-Tree", Algorithm 2), on the host,
+ * then one upload to the device.
+ *   prefixes  host, n records; host bits beyond each length are ignored (masked)
+ *   lengths   host, n prefix lengths 0..128
+ *   next_hops host, n values 0..0xFFFE (0xFFFF is PLANB_NO_ROUTE and rejected)
+ *   n         may be 0: every lookup then returns PLANB_NO_ROUTE
+ * Steps: mask; range conversion [P, P + 2^(128-L)) in 129-bit arithmetic (an
+ * end of 2^128 produces no boundary); sort the 2n boundary events (address,
+ * END before START, START by ascending length); one sweep with a stack of next
+ * hops yields the elementary intervals (an interval at address 0 always exists,
+ * with ::/0's next hop or PLANB_NO_ROUTE); the interval starts fill the leaves
+ * of a fanout-b tree whose internal separators are the minima of the child
+ * subtrees.  The inputs are copied; the caller keeps ownership.
+ * Errors: NULL with PLANB_EINVAL (length > 128, next hop 0xFFFF, NULL array
+ * with n > 0), PLANB_EDUP, PLANB_ENOMEM, PLANB_EDEVICE.
+ */
+planb_fib_t* planb_build(const planb_addr_t* prefixes, const uint8_t* lengths,
+                         const uint16_t* next_hops, size_t n);
+planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths,
+                            const uint16_t* next_hops, size_t n, const planb_params_t* params);
+
+/*
+ * planb_lookup -- batched search of Algorithm 1 / Listing 1 (Section 3, "Search
+ * on Linearized B+-Tree", "Vectorization", "Batching", "Branch-Free Traversal")
+ * on the GPU.  For each address x, descends the tree: at every level the node's
+ * keys <= x are counted and the count selects the child; at the leaf the count
+ * gives the predecessor interval, whose next hop is written.
+ *   addrs  device, n records, 16-byte aligned
+ *   out    device, n uint16 next hops, 2-byte aligned
+ *   n      0 is a no-op; must be < 2^40
+ * Returns PLANB_OK, PLANB_EINVAL (NULL fib / NULL or misaligned pointer with
+ * n > 0), PLANB_ERANGE, PLANB_EDEVICE (launch failed).
+ */
+int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n,
+                 uint16_t* out, void* stream);
+
+/* Same descent, but writes the index (0..m-1) of the elementary interval that
+ * holds each address instead of its next hop.  out: device, n uint32. */
+int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n,
+                       uint32_t* out, void* stream);
+
+/* Releases the handle and its device memory.  It first waits for all work
+ * enqueued on the device (hipDeviceSynchronize), so lookups in flight that use
+ * the handle finish on the old structure (Section 3, "Dynamic FIB Update":
+ * free after in-flight lookups complete).  NULL is ignored. */
+void planb_free(planb_fib_t* fib);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* planb_last_error(void);
+
+/* planb_status of the last failure on the calling thread (0 if none); useful
+ * after a call that returns NULL.  Reset by planb_build* calls. */
+int planb_last_status(void);
+
+/* m, the number of elementary intervals (Section 3: at most 2n + 1). */
+size_t planb_num_intervals(const planb_fib_t* fib);
+
+/* Copies min(m, cap) interval starts and next hops to host memory and returns
+ * how many were written (or a negative status).  Either array may be NULL. */
+long long planb_export_intervals(const planb_fib_t* fib, planb_addr_t* starts,
+                                 uint16_t* next_hops, size_t cap);
+
+#define PLANB_MAX_LEVELS 16
+
+/* Shape of a built tree (all node counts and offsets in nodes of `slots` keys). */
+typedef struct planb_info {
+    uint64_t intervals;                 /* m */
+    uint32_t fanout;                    /* b */
+    uint32_t slots;                     /* key slots per node (b: k keys + 1 sentinel) */
+    uint32_t depth;                     /* D: levels including the leaf level */
+    uint32_t keys_per_lane;             /* current lookup tuning */
+    int32_t lds_levels;
+    uint32_t lookups_per_group;
+    uint64_t level_nodes[PLANB_MAX_LEVELS];      /* allocated nodes per level */
+    uint64_t level_offset[PLANB_MAX_LEVELS + 1]; /* first node of each level */
+    uint64_t key_bytes;                 /* device bytes of the key array */
+    uint64_t value_bytes;               /* device bytes of the next-hop array */
+} planb_info_t;
+
+int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
+
+/*
+ * Lookup tuning of a built FIB (does not change any result):
+ *   keys_per_lane      each lane compares this many keys of a node, so
+ *                      b / keys_per_lane lanes of a wavefront cooperate on one
+ *                      lookup; a power of two dividing b, with 1 <= b/kpl <= 16
+ *   lds_levels         how many top levels each workgroup stages in LDS
+ *                      (0..depth; -1 = the deepest that fits 64 KiB)
+ *   lookups_per_group  independent lookups each lane group keeps in flight (1, 2 or 4)
+ * Returns PLANB_EINVAL for an unsupported combination.
+ */
+int planb_set_tuning(planb_fib_t* fib, uint32_t keys_per_lane, int32_t lds_levels,
+                     uint32_t lookups_per_group);
+
+/*
+ * Pure layout arithmetic (Section 3, "Search on Linearized B+-Tree" closed
+ * forms and "Parameter Tuning"), no allocation: for m keys, fanout b and
+ * `slots` key slots per node, fills info->depth (smallest D with
+ * (b-1) * b^(D-1) >= m), level_nodes and level_offset.  trimmed = 0 keeps every
+ * internal node of a complete b-ary tree (the paper's layout, where level d
+ * starts at node (b^d - 1)/(b - 1)); trimmed = 1 drops trailing internal nodes
+ * that hold only sentinels.  Trailing all-sentinel leaves are never counted.
+ * info->key_bytes is nodes * slots * 16.
+ */
+int planb_layout(uint64_t m, uint32_t fanout, uint32_t slots, int trimmed, planb_info_t* info);
+
+/*
+ * Host-only halves of planb_build, usable without a GPU (tools, tests).
+ *
+ * planb_build_intervals -- range conversion and interval partitioning
+ * (Section 3, "From 2D Prefixes to 1D Intervals"; Algorithm 2's sweep): the
+ * same validation and steps as planb_build up to the elementary intervals.
+ * Writes min(m, cap) starts / next hops to host memory (either may be NULL)
+ * and returns m, or a negative planb_status.  flags: PLANB_FLAG_*.
+ */
+long long planb_build_intervals(const planb_addr_t* prefixes, const uint8_t* lengths,
+                                const uint16_t* next_hops, size_t n, uint32_t flags,
+                                planb_addr_t* starts, uint16_t* next_hops_out, size_t cap);
+
+/*
+ * planb_build_keys -- the linearized B+-tree key array (Section 3, "Linearized
+ * B+-Tree", "Maintaining Structural Integrity", Algorithm 2's leaf fill and
+ * separator pass) for m strictly increasing interval starts (starts[0] == 0),
+ * laid out as planb_build lays it out on the device: node-major, `fanout`
+ * 16-byte slots per node (fanout-1 keys + one sentinel 2^128-1 slot), levels
+ * top-down, trailing all-sentinel nodes dropped.  keys: host, cap_keys records;
+ * info (may be NULL) receives the shape.  Returns the number of key slots
+ * (may exceed cap_keys, then nothing is written) or a negative status.
+ */
+long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout,
+                           planb_addr_t* keys, size_t cap_keys, planb_info_t* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLANB_H */

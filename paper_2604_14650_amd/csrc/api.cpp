@@ -1,0 +1,341 @@
+// C ABI of the library (declared in include/planb.h).
+#include "api_internal.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+using namespace planb;
+
+namespace planb {
+
+thread_local std::string g_err;
+thread_local int g_status = 0;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    g_status = code;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* what)
+{
+    return fail(PLANB_EDEVICE, std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+int check_current_device(const planb_fib_t* fib)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != fib->device)
+        return fail(PLANB_EINVAL, "the FIB lives on device " + std::to_string(fib->device) +
+                                      " but device " + std::to_string(dev) + " is current");
+    return PLANB_OK;
+}
+
+int deepest_lds_levels(const Layout& lay, size_t budget)
+{
+    int L = 0;
+    while (L < (int)lay.depth && lay.offset[L + 1] * lay.b * 16ull <= budget) ++L;
+    return L;
+}
+
+void refresh_desc(planb_fib_t* f)
+{
+    TreeDesc& t = f->desc;
+    t.keys = reinterpret_cast<const uint4*>(f->d_keys);
+    t.vals = f->d_vals;
+    t.m_minus_1 = f->iv.starts.size() - 1;
+    t.depth = f->lay.depth;
+    t.lds_levels = (uint32_t)f->lds_levels;
+    t.lds_nodes = (uint32_t)f->lay.offset[f->lds_levels];
+    t.fanout = f->lay.b;
+    for (int l = 0; l < kDevMaxLevels; ++l) {
+        t.off[l] = l < (int)f->lay.depth ? (uint32_t)f->lay.offset[l] : 0;
+        t.last[l] = l < (int)f->lay.depth ? (uint32_t)(f->lay.nodes[l] - 1) : 0;
+    }
+}
+
+int validate_tuning(const planb_fib_t* f, uint32_t kpl, int32_t lds_levels, uint32_t R, int32_t* lds_out)
+{
+    const uint32_t b = f->lay.b;
+    if (kpl == 0 || (kpl & (kpl - 1)) || b % kpl || b / kpl > 32 || b / kpl < 1 ||
+        !lookup_variant_exists((int)b, (int)kpl, (int)R))
+        return fail(PLANB_EINVAL, "unsupported keys_per_lane " + std::to_string(kpl) + " / lookups_per_group " +
+                                      std::to_string(R) + " for fanout " + std::to_string(b));
+    if (lds_levels < 0) lds_levels = deepest_lds_levels(f->lay, 64 * 1024);
+    if (lds_levels > (int32_t)f->lay.depth)
+        return fail(PLANB_EINVAL, "lds_levels exceeds the tree depth");
+    const size_t bytes = f->lay.offset[lds_levels] * b * 16ull;
+    if (bytes > (size_t)max_lds_bytes())
+        return fail(PLANB_ERANGE, "the top " + std::to_string(lds_levels) + " levels need " + std::to_string(bytes) +
+                                      " bytes of LDS, more than a workgroup may allocate");
+    *lds_out = lds_levels;
+    return PLANB_OK;
+}
+
+void layout_to_info(const Layout& lay, planb_info_t* info)
+{
+    std::memset(info, 0, sizeof(*info));
+    info->intervals = lay.m;
+    info->fanout = lay.b;
+    info->slots = lay.slots;
+    info->depth = lay.depth;
+    for (uint32_t l = 0; l < lay.depth; ++l) info->level_nodes[l] = lay.nodes[l];
+    for (uint32_t l = 0; l <= lay.depth; ++l) info->level_offset[l] = lay.offset[l];
+    info->key_bytes = lay.total_nodes() * lay.slots * 16ull;
+}
+
+void clear_error()
+{
+    g_err.clear();
+    g_status = 0;
+}
+
+uint32_t default_kpl(uint32_t b) { return b == 8 ? 2 : b == 16 ? 4 : 8; }
+
+}  // namespace planb
+
+extern "C" {
+
+const char* planb_last_error(void) { return g_err.c_str(); }
+
+int planb_last_status(void) { return g_status; }
+
+planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths, const uint16_t* next_hops,
+                            size_t n, const planb_params_t* params)
+{
+    clear_error();
+    planb_params_t p{};
+    if (params) p = *params;
+    if (p.fanout == 0) p.fanout = 16;
+    if (p.fanout != 8 && p.fanout != 16 && p.fanout != 32) {
+        fail(PLANB_EINVAL, "fanout must be 8, 16 or 32");
+        return nullptr;
+    }
+    if (n > 0 && (!prefixes || !lengths || !next_hops)) {
+        fail(PLANB_EINVAL, "NULL input array with n > 0");
+        return nullptr;
+    }
+    planb_fib_t* f = new (std::nothrow) planb_fib_t();
+    if (!f) {
+        fail(PLANB_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    std::string err;
+    int rc;
+    try {
+        rc = make_intervals(reinterpret_cast<const U128*>(prefixes), lengths, next_hops, n,
+                            (p.flags & PLANB_FLAG_MERGE_EQUAL_NH) != 0, &f->iv, &err);
+    } catch (const std::bad_alloc&) {
+        rc = PLANB_ENOMEM;
+        err = "out of host memory";
+    }
+    if (rc != 0) {
+        fail(rc, err);
+        delete f;
+        return nullptr;
+    }
+    const uint64_t m = f->iv.starts.size();
+    if (m >= (1ull << 32)) {
+        fail(PLANB_ERANGE, "too many intervals for 32-bit interval indices");
+        delete f;
+        return nullptr;
+    }
+    if ((rc = plan_layout(m, p.fanout, p.fanout, true, &f->lay, &err)) != 0) {
+        fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
+        delete f;
+        return nullptr;
+    }
+    std::vector<U128> keys;
+    try {
+        fill_keys(f->iv, f->lay, &keys);
+    } catch (const std::bad_alloc&) {
+        fail(PLANB_ENOMEM, "out of host memory");
+        delete f;
+        return nullptr;
+    }
+    hipError_t e = hipGetDevice(&f->device);
+    if (e != hipSuccess) {
+        fail_hip(e, "hipGetDevice");
+        delete f;
+        return nullptr;
+    }
+    const size_t kbytes = keys.size() * sizeof(U128);
+    const size_t vbytes = ((m + 63) / 64) * 64 * sizeof(uint16_t);
+    if ((e = hipMalloc(&f->d_keys, kbytes)) != hipSuccess || (e = hipMalloc(&f->d_vals, vbytes)) != hipSuccess) {
+        fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        planb_free(f);
+        return nullptr;
+    }
+    f->key_bytes = kbytes;
+    f->value_bytes = vbytes;
+    if ((e = hipMemcpy(f->d_keys, keys.data(), kbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(f->d_vals, 0xFF, vbytes)) != hipSuccess ||
+        (e = hipMemcpy(f->d_vals, f->iv.nh.data(), m * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) {
+        fail_hip(e, "uploading the tree");
+        planb_free(f);
+        return nullptr;
+    }
+    uint32_t kpl = p.keys_per_lane ? p.keys_per_lane : default_kpl(p.fanout);
+    int32_t lds = p.lds_levels > 0 ? p.lds_levels : -1;
+    int32_t lds_ok = 0;
+    if ((rc = validate_tuning(f, kpl, lds, 2, &lds_ok)) != PLANB_OK) {
+        planb_free(f);
+        return nullptr;
+    }
+    f->kpl = kpl;
+    f->R = 2;
+    f->lds_levels = lds_ok;
+    refresh_desc(f);
+    return f;
+}
+
+planb_fib_t* planb_build(const planb_addr_t* prefixes, const uint8_t* lengths, const uint16_t* next_hops,
+                         size_t n)
+{
+    return planb_build_ex(prefixes, lengths, next_hops, n, nullptr);
+}
+
+void planb_free(planb_fib_t* fib)
+{
+    if (!fib) return;
+    (void)hipDeviceSynchronize();
+    release_learned(fib);
+    if (fib->d_keys) (void)hipFree(fib->d_keys);
+    if (fib->d_vals) (void)hipFree(fib->d_vals);
+    delete fib;
+}
+
+static int check_lookup_args(const planb_fib_t* fib, const void* addrs, size_t n, const void* out,
+                             size_t out_align)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (n == 0) return PLANB_OK;
+    if (n >= (1ull << 40)) return fail(PLANB_ERANGE, "batch too large (n must be < 2^40)");
+    if (!addrs || !out) return fail(PLANB_EINVAL, "NULL device pointer");
+    if (reinterpret_cast<uintptr_t>(addrs) % 16) return fail(PLANB_EINVAL, "addrs must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(out) % out_align) return fail(PLANB_EINVAL, "out is misaligned");
+    return check_current_device(fib);
+}
+
+int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out, void* stream)
+{
+    int rc = check_lookup_args(fib, addrs, n, out, 2);
+    if (rc != PLANB_OK || n == 0) return rc;
+    hipError_t e = launch_lookup(fib->desc, (int)fib->kpl, (int)fib->R, addrs, n, out, false,
+                                 static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
+}
+
+int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint32_t* out, void* stream)
+{
+    int rc = check_lookup_args(fib, addrs, n, out, 4);
+    if (rc != PLANB_OK || n == 0) return rc;
+    hipError_t e = launch_lookup(fib->desc, (int)fib->kpl, (int)fib->R, addrs, n, out, true,
+                                 static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
+}
+
+size_t planb_num_intervals(const planb_fib_t* fib) { return fib ? fib->iv.starts.size() : 0; }
+
+long long planb_export_intervals(const planb_fib_t* fib, planb_addr_t* starts, uint16_t* next_hops, size_t cap)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    const size_t m = std::min(cap, fib->iv.starts.size());
+    if (starts) std::memcpy(starts, fib->iv.starts.data(), m * sizeof(planb_addr_t));
+    if (next_hops) std::memcpy(next_hops, fib->iv.nh.data(), m * sizeof(uint16_t));
+    return (long long)m;
+}
+
+
+long long planb_build_intervals(const planb_addr_t* prefixes, const uint8_t* lengths, const uint16_t* next_hops,
+                                size_t n, uint32_t flags, planb_addr_t* starts, uint16_t* next_hops_out, size_t cap)
+{
+    clear_error();
+    if (n > 0 && (!prefixes || !lengths || !next_hops)) return fail(PLANB_EINVAL, "NULL input array with n > 0");
+    Intervals iv;
+    std::string err;
+    int rc;
+    try {
+        rc = make_intervals(reinterpret_cast<const U128*>(prefixes), lengths, next_hops, n,
+                            (flags & PLANB_FLAG_MERGE_EQUAL_NH) != 0, &iv, &err);
+    } catch (const std::bad_alloc&) {
+        return fail(PLANB_ENOMEM, "out of host memory");
+    }
+    if (rc != 0) return fail(rc, err);
+    const size_t m = iv.starts.size(), w = std::min(m, cap);
+    if (starts) std::memcpy(starts, iv.starts.data(), w * sizeof(planb_addr_t));
+    if (next_hops_out) std::memcpy(next_hops_out, iv.nh.data(), w * sizeof(uint16_t));
+    return (long long)m;
+}
+
+long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout, planb_addr_t* keys,
+                           size_t cap_keys, planb_info_t* info)
+{
+    clear_error();
+    if (m == 0 || !starts) return fail(PLANB_EINVAL, "need m >= 1 interval starts");
+    if (fanout != 8 && fanout != 16 && fanout != 32) return fail(PLANB_EINVAL, "fanout must be 8, 16 or 32");
+    const U128* s = reinterpret_cast<const U128*>(starts);
+    if (s[0] != U128{0, 0}) return fail(PLANB_EINVAL, "starts[0] must be 0");
+    for (size_t i = 1; i < m; ++i)
+        if (!(s[i - 1] < s[i])) return fail(PLANB_EINVAL, "starts must be strictly increasing");
+    Layout lay;
+    std::string err;
+    int rc = plan_layout(m, fanout, fanout, true, &lay, &err);
+    if (rc != 0) return fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
+    if (info) layout_to_info(lay, info);
+    const size_t slots = lay.total_nodes() * fanout;
+    if (!keys || slots > cap_keys) return (long long)slots;
+    Intervals iv;
+    iv.starts.assign(s, s + m);
+    iv.nh.assign(m, 0);
+    std::vector<U128> k;
+    try {
+        fill_keys(iv, lay, &k);
+    } catch (const std::bad_alloc&) {
+        return fail(PLANB_ENOMEM, "out of host memory");
+    }
+    std::memcpy(keys, k.data(), slots * sizeof(planb_addr_t));
+    return (long long)slots;
+}
+
+int planb_get_info(const planb_fib_t* fib, planb_info_t* info)
+{
+    if (!fib || !info) return fail(PLANB_EINVAL, "NULL argument");
+    layout_to_info(fib->lay, info);
+    info->keys_per_lane = fib->kpl;
+    info->lds_levels = fib->lds_levels;
+    info->lookups_per_group = fib->R;
+    info->key_bytes = fib->key_bytes;
+    info->value_bytes = fib->value_bytes;
+    return PLANB_OK;
+}
+
+int planb_layout(uint64_t m, uint32_t fanout, uint32_t slots, int trimmed, planb_info_t* info)
+{
+    if (!info) return fail(PLANB_EINVAL, "NULL info");
+    Layout lay;
+    std::string err;
+    int rc = plan_layout(m, fanout, slots, trimmed != 0, &lay, &err);
+    if (rc != 0) return fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
+    layout_to_info(lay, info);
+    return PLANB_OK;
+}
+
+int planb_set_tuning(planb_fib_t* fib, uint32_t keys_per_lane, int32_t lds_levels, uint32_t lookups_per_group)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    int32_t lds = 0;
+    int rc = validate_tuning(fib, keys_per_lane, lds_levels, lookups_per_group, &lds);
+    if (rc != PLANB_OK) return rc;
+    fib->kpl = keys_per_lane;
+    fib->lds_levels = lds;
+    fib->R = lookups_per_group;
+    refresh_desc(fib);
+    return PLANB_OK;
+}
+
+}  // extern "C"

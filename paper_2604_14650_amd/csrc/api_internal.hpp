@@ -1,0 +1,40 @@
+// Internal definition of the FIB handle and helpers shared by the C-ABI files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/planb.h"
+#include "builder.hpp"
+#include "device.hpp"
+#include "lookup.hpp"
+
+namespace planb {
+struct LearnedModel;  // learned position model state (learned.hip)
+}
+
+struct planb_fib {
+    planb::Intervals iv;   // host copy of the elementary intervals
+    planb::Layout lay;     // tree shape
+    void* d_keys = nullptr;
+    uint16_t* d_vals = nullptr;
+    size_t key_bytes = 0, value_bytes = 0;
+    int device = 0;
+    uint32_t kpl = 4, R = 2;
+    int32_t lds_levels = 0;
+    planb::TreeDesc desc{};
+    planb::LearnedModel* learned = nullptr;
+};
+
+namespace planb {
+
+extern thread_local std::string g_err;
+void clear_error();
+int fail(int code, const std::string& msg);
+int fail_hip(hipError_t e, const char* what);
+int check_current_device(const planb_fib_t* fib);
+void refresh_desc(planb_fib_t* f);
+void release_learned(planb_fib_t* f);  // frees the learned model, if any
+
+}  // namespace planb

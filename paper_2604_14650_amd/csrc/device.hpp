@@ -1,0 +1,46 @@
+// Device-side descriptors and small wavefront helpers shared by the lookup
+// kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace planb {
+
+constexpr int kDevMaxLevels = 16;
+
+// What a kernel needs to descend one built tree.  Passed by value (kernarg).
+struct TreeDesc {
+    const uint4* keys;       // node-major key array; node = B slots of 16 bytes
+    const uint16_t* vals;    // next hop of interval i at vals[i]
+    uint64_t m_minus_1;      // last interval index
+    uint32_t depth;          // D, levels including the leaf level
+    uint32_t lds_levels;     // top levels staged in LDS (<= depth)
+    uint32_t lds_nodes;      // nodes in those levels (= off[lds_levels])
+    uint32_t fanout;         // B (checked against the kernel's template)
+    uint32_t off[kDevMaxLevels];   // first node of each level
+    uint32_t last[kDevMaxLevels];  // last allocated node of each level
+};
+
+// 128-bit unsigned key <= x, key given as the 16-byte record {hi, lo}.
+__device__ __forceinline__ int key_le(uint4 k, uint64_t xhi, uint64_t xlo)
+{
+    const uint64_t khi = ((uint64_t)k.y << 32) | k.x;
+    const uint64_t klo = ((uint64_t)k.w << 32) | k.z;
+    return (khi < xhi) | ((khi == xhi) & (klo <= xlo));
+}
+
+// Sum of v over aligned groups of G consecutive lanes; every lane of a group
+// receives the group's total.  G <= 16 stays inside one DPP row.
+template <int G>
+__device__ __forceinline__ int group_sum(int v)
+{
+    if constexpr (G >= 2) v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    if constexpr (G >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    if constexpr (G >= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    if constexpr (G >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); // row_mirror
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    return v;
+}
+
+}  // namespace planb

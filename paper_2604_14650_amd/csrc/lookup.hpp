@@ -1,0 +1,21 @@
+// Host-side launchers of the lookup kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace planb {
+
+// Whether a (fanout, keys per lane, lookups per group) kernel is compiled in.
+bool lookup_variant_exists(int B, int kpl, int R);
+
+// Largest dynamic LDS allocation a workgroup may request on the current device.
+int max_lds_bytes();
+
+// Enqueue one plain lookup over n addresses on `stream`; out receives uint16
+// next hops, or uint32 interval indices when index_out.
+hipError_t launch_lookup(const TreeDesc& t, int kpl, int R, const void* addrs, uint64_t n, void* out,
+                         bool index_out, hipStream_t stream);
+
+}  // namespace planb

@@ -1,0 +1,256 @@
+"""Thin ctypes binding of ``libplanb.so`` (include/planb.h), same names as the C ABI.
+
+Argument marshalling only: every step of building and searching runs in the
+native library (host C++ for the build, HIP kernels for lookups).  PyTorch is
+used for device memory (``torch.Tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing this module raises at import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplanb.so")
+
+PLANB_OK = 0
+PLANB_EINVAL = -1
+PLANB_EDUP = -2
+PLANB_ENOMEM = -3
+PLANB_EDEVICE = -4
+PLANB_ERANGE = -5
+PLANB_NO_ROUTE = 0xFFFF
+PLANB_FLAG_MERGE_EQUAL_NH = 1
+PLANB_MAX_LEVELS = 16
+
+# torch bundles its own libamdhip64.so.7.  Loading torch first makes the
+# dynamic linker resolve this library's libamdhip64.so.7 to that same, already
+# loaded runtime, so torch's device pointers and stream handles are valid here.
+import torch  # noqa: E402,F401
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(or python paper_2604_14650_amd/build.py) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class planb_params_t(ctypes.Structure):
+    _fields_ = [("fanout", ctypes.c_uint32), ("keys_per_lane", ctypes.c_uint32),
+                ("lds_levels", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class planb_info_t(ctypes.Structure):
+    _fields_ = [("intervals", ctypes.c_uint64), ("fanout", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32), ("keys_per_lane", ctypes.c_uint32), ("lds_levels", ctypes.c_int32),
+                ("lookups_per_group", ctypes.c_uint32),
+                ("level_nodes", ctypes.c_uint64 * PLANB_MAX_LEVELS),
+                ("level_offset", ctypes.c_uint64 * (PLANB_MAX_LEVELS + 1)),
+                ("key_bytes", ctypes.c_uint64), ("value_bytes", ctypes.c_uint64)]
+
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("planb_build", _vp, _vp, _vp, _vp, _sz)
+_sig("planb_build_ex", _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(planb_params_t))
+_sig("planb_lookup", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
+_sig("planb_lookup_index", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
+_sig("planb_free", None, _vp)
+_sig("planb_last_error", ctypes.c_char_p)
+_sig("planb_last_status", ctypes.c_int)
+_sig("planb_num_intervals", _sz, _vp)
+_sig("planb_export_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz)
+_sig("planb_get_info", ctypes.c_int, _vp, ctypes.POINTER(planb_info_t))
+_sig("planb_set_tuning", ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint32)
+_sig("planb_build_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz, ctypes.c_uint32, _vp, _vp, _sz)
+_sig("planb_build_keys", ctypes.c_longlong, _vp, _sz, ctypes.c_uint32, _vp, _sz, ctypes.POINTER(planb_info_t))
+_sig("planb_layout", ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+     ctypes.POINTER(planb_info_t))
+
+
+class PlanbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"planb error {code}: {msg}")
+        self.code = code
+
+
+def planb_last_error() -> str:
+    return (_lib.planb_last_error() or b"").decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise PlanbError(rc, planb_last_error())
+    return rc
+
+
+def lib_handle():
+    return _lib
+
+
+class Fib:
+    """Owner of one ``planb_fib_t*``; frees it when garbage-collected."""
+
+    def __init__(self, ptr: int):
+        self.ptr = ptr
+
+    def close(self):
+        if self.ptr:
+            _lib.planb_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        if not self.ptr:
+            raise ValueError("FIB handle already freed")
+        return ctypes.c_void_p(self.ptr)
+
+
+def _host(a, dtype, shape_tail=()):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape_tail and a.shape[1:] != shape_tail:
+        raise ValueError(f"expected shape (n, {shape_tail}), got {a.shape}")
+    return a
+
+
+def planb_last_status() -> int:
+    return int(_lib.planb_last_status())
+
+
+def planb_build(prefixes, lengths, next_hops, fanout: int = 16, keys_per_lane: int = 0,
+                lds_levels: int = -1, flags: int = 0) -> Fib:
+    """prefixes: (n, 2) uint64 {hi, lo}; lengths: (n,) uint8; next_hops: (n,) uint16."""
+    p = _host(prefixes, np.uint64, (2,)) if len(lengths) else np.zeros((0, 2), np.uint64)
+    L = _host(lengths, np.uint8)
+    nh = _host(next_hops, np.uint16)
+    if not (p.shape[0] == L.shape[0] == nh.shape[0]):
+        raise ValueError("prefixes, lengths and next_hops differ in length")
+    params = planb_params_t(fanout, keys_per_lane, lds_levels, flags)
+    n = L.shape[0]
+    ptr = _lib.planb_build_ex(p.ctypes.data if n else None, L.ctypes.data if n else None,
+                              nh.ctypes.data if n else None, n, ctypes.byref(params))
+    if not ptr:
+        raise PlanbError(planb_last_status(), planb_last_error())
+    return Fib(ptr)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, what):
+    if hasattr(t, "data_ptr"):
+        if not t.is_cuda:
+            raise ValueError(f"{what} must be a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+def planb_lookup(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
+    """addrs: device tensor (n, 2) int64 (the {hi, lo} records); out: device
+    tensor (n,) int16/uint16 receiving next hops.  Asynchronous on ``stream``."""
+    if n is None:
+        n = addrs.shape[0]
+    _check(_lib.planb_lookup(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), _stream_handle(stream)))
+    return out
+
+
+def planb_lookup_index(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
+    """Like planb_lookup, but out (n,) int32 receives interval indices."""
+    if n is None:
+        n = addrs.shape[0]
+    _check(_lib.planb_lookup_index(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"),
+                                   _stream_handle(stream)))
+    return out
+
+
+def planb_num_intervals(fib: Fib) -> int:
+    return int(_lib.planb_num_intervals(fib))
+
+
+def planb_export_intervals(fib: Fib):
+    m = planb_num_intervals(fib)
+    starts = np.empty((m, 2), dtype=np.uint64)
+    nh = np.empty(m, dtype=np.uint16)
+    got = _check(_lib.planb_export_intervals(fib, starts.ctypes.data, nh.ctypes.data, m))
+    return starts[:got], nh[:got]
+
+
+def _info_dict(info: planb_info_t) -> dict:
+    D = info.depth
+    return {"intervals": info.intervals, "fanout": info.fanout, "slots": info.slots, "depth": D,
+            "keys_per_lane": info.keys_per_lane, "lds_levels": info.lds_levels,
+            "lookups_per_group": info.lookups_per_group,
+            "level_nodes": [int(info.level_nodes[i]) for i in range(D)],
+            "level_offset": [int(info.level_offset[i]) for i in range(D + 1)],
+            "key_bytes": int(info.key_bytes), "value_bytes": int(info.value_bytes)}
+
+
+def planb_get_info(fib: Fib) -> dict:
+    info = planb_info_t()
+    _check(_lib.planb_get_info(fib, ctypes.byref(info)))
+    return _info_dict(info)
+
+
+def planb_set_tuning(fib: Fib, keys_per_lane: int, lds_levels: int = -1, lookups_per_group: int = 2):
+    _check(_lib.planb_set_tuning(fib, keys_per_lane, lds_levels, lookups_per_group))
+
+
+def planb_layout(m: int, fanout: int, slots: int, trimmed: bool = True) -> dict:
+    info = planb_info_t()
+    _check(_lib.planb_layout(m, fanout, slots, 1 if trimmed else 0, ctypes.byref(info)))
+    return _info_dict(info)
+
+
+def planb_build_intervals(prefixes, lengths, next_hops, flags: int = 0):
+    """Host-only interval partitioning: returns (starts (m, 2) uint64, next hops (m,) uint16)."""
+    n = len(lengths)
+    p = _host(prefixes, np.uint64, (2,)) if n else np.zeros((0, 2), np.uint64)
+    L = _host(lengths, np.uint8)
+    nh = _host(next_hops, np.uint16)
+    args = (p.ctypes.data if n else None, L.ctypes.data if n else None, nh.ctypes.data if n else None, n, flags)
+    m = _check(_lib.planb_build_intervals(*args, None, None, 0))
+    starts = np.empty((m, 2), dtype=np.uint64)
+    out_nh = np.empty(m, dtype=np.uint16)
+    _check(_lib.planb_build_intervals(*args, starts.ctypes.data, out_nh.ctypes.data, m))
+    return starts, out_nh
+
+
+def planb_build_keys(starts, fanout: int = 16):
+    """Host-only key array of the tree over ``starts``: returns (keys (slots, 2) uint64, info)."""
+    s = _host(starts, np.uint64, (2,))
+    info = planb_info_t()
+    need = _check(_lib.planb_build_keys(s.ctypes.data, s.shape[0], fanout, None, 0, ctypes.byref(info)))
+    keys = np.empty((need, 2), dtype=np.uint64)
+    _check(_lib.planb_build_keys(s.ctypes.data, s.shape[0], fanout, keys.ctypes.data, need, None))
+    return keys, _info_dict(info)
+
+
+def exported_symbols() -> list[str]:
+    """Names of the planb_* functions the header declares, for ABI checks."""
+    return [n for n in dir(_lib) if n.startswith("planb_")]

@@ -1,0 +1,199 @@
+"""GPU parity of the plain lookup (build + planb_lookup through the C ABI)
+against the CPU oracle: next hops must be identical, address for address."""
+import numpy as np
+import pytest
+
+import planb_synth as S
+from helpers import fib_of, host_u16, oracle_trie, out_u16, say, to_dev
+from oracle.brute import lpm_bruteforce
+from oracle.trie import lpm_trie
+
+pytestmark = pytest.mark.gpu
+
+M128 = (1 << 128) - 1
+
+VARIANTS = [(8, 1, 1), (8, 2, 2), (8, 4, 4), (8, 8, 1), (16, 1, 2), (16, 2, 1), (16, 4, 2), (16, 4, 4),
+            (16, 8, 2), (16, 16, 1), (32, 1, 1), (32, 2, 2), (32, 4, 2), (32, 8, 4), (32, 16, 1)]
+
+
+def gpu_lookup(P, fib, addrs, fanout=16, kpl=None, lds=-1, R=2):
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    if kpl is not None:
+        P.planb_set_tuning(h, kpl, lds, R)
+    d = to_dev(addrs)
+    out = out_u16(addrs.shape[0])
+    P.planb_lookup(h, d, addrs.shape[0], out)
+    return host_u16(out, addrs.shape[0]), h
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2604_14650_amd import planb
+    return planb
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    fib = fib_of("tiny", 11)
+    addrs = S.tiny_traffic(fib, 1 << 20, seed=1011)
+    return fib, addrs, oracle_trie("tiny", 11).lookup(addrs)
+
+
+@pytest.mark.parametrize("fanout,kpl,R", VARIANTS)
+def test_tiny_all_addresses(P, tiny, fanout, kpl, R):
+    fib, addrs, want = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    depth = P.planb_get_info(h)["depth"]
+    d = to_dev(addrs)
+    for lds in sorted({0, -1, depth, max(0, depth - 1)}):
+        say(f"tiny fanout={fanout} kpl={kpl} R={R} lds={lds}")
+        try:
+            P.planb_set_tuning(h, kpl, lds, R)
+        except P.PlanbError:
+            continue  # more levels than fit in LDS
+        out = out_u16(addrs.shape[0])
+        P.planb_lookup(h, d, addrs.shape[0], out)
+        got = host_u16(out, addrs.shape[0])
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+
+
+def _edge_fibs():
+    base = 0x20010DB8 << 96
+    return {
+        "empty": [],
+        "default_only": [(0, 0, 42)],
+        "top_of_space": [(0, 0, 1), (0xFFFF << 112, 16, 2), (M128, 128, 3), (M128 - 1, 128, 4)],
+        "nested_shared_start": [(base, 32, 1), (base, 48, 2), (base, 64, 3), (base | (5 << 60), 68, 4),
+                                (base | (5 << 60) | 77, 128, 5)],
+        "zero_host_route": [(0, 128, 7), (1, 128, 8), (0, 1, 9)],
+    }
+
+
+def _edge_queries(rules, rng):
+    q = {0, 1, M128, M128 - 1, 1 << 127, (1 << 127) - 1}
+    for Pv, Lv, _ in rules:
+        end = Pv + (1 << (128 - Lv)) - 1
+        for v in (Pv - 1, Pv, Pv + 1, end - 1, end, end + 1):
+            if 0 <= v <= M128:
+                q.add(v)
+    q |= {int(x) << 64 | int(y) for x, y in rng.integers(0, 2**63, size=(300, 2))}
+    return S.from_ints(sorted(q))
+
+
+@pytest.mark.parametrize("fanout", [8, 16, 32])
+@pytest.mark.parametrize("name", sorted(_edge_fibs()))
+def test_edge_cases(P, fanout, name):
+    rules = _edge_fibs()[name]
+    rng = np.random.default_rng(7)
+    p = S.from_ints([r[0] for r in rules]) if rules else np.zeros((0, 2), np.uint64)
+    L = np.array([r[1] for r in rules], np.uint8)
+    nh = np.array([r[2] for r in rules], np.uint16)
+    q = _edge_queries(rules, rng)
+    want = lpm_bruteforce(p, L, nh, q)
+    fib = S.Fib(p, L, nh)
+    for kpl in (1, fanout // 2, fanout // 4):
+        if fanout // kpl > 32:
+            continue
+        say(f"edge {name} fanout={fanout} kpl={kpl}")
+        got, _ = gpu_lookup(P, fib, q, fanout, kpl, -1, 2)
+        assert np.array_equal(got, want)
+        got, _ = gpu_lookup(P, fib, q, fanout, kpl, 0, 1)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097, 123457])
+def test_ragged_batch_sizes(P, tiny, n):
+    fib, addrs, want = tiny
+    say(f"ragged n={n}")
+    got, _ = gpu_lookup(P, fib, addrs[:n])
+    assert np.array_equal(got, want[:n])
+
+
+def test_zero_length_batch_is_a_noop(P, tiny):
+    import torch
+    fib, addrs, _ = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    out = out_u16(4)
+    P.planb_lookup(h, to_dev(addrs[:4]), 0, out)
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == -1).all()
+
+
+def test_misaligned_and_null_pointers_rejected(P, tiny):
+    import torch
+    fib, addrs, _ = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    d = to_dev(addrs[:64])
+    out = out_u16(64)
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_lookup(h, d.data_ptr() + 8, 8, out)
+    assert e.value.code == P.PLANB_EINVAL
+    with pytest.raises(P.PlanbError):
+        P.planb_lookup(h, 0, 8, out)
+    with pytest.raises(P.PlanbError):
+        P.planb_lookup(h, d, 8, out.data_ptr() + 1)
+    torch.cuda.synchronize()
+
+
+def test_interval_index_output_is_consistent(P, tiny):
+    import torch
+    fib, addrs, want = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    starts, nh = P.planb_export_intervals(h)
+    n = 1 << 16
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    P.planb_lookup_index(h, to_dev(addrs[:n]), n, idx)
+    i = idx.cpu().numpy().astype(np.int64)
+    assert i.min() >= 0 and i.max() < len(starts)
+    assert np.array_equal(nh[i], want[:n])
+    # the returned interval holds the address: starts[i] <= x < starts[i + 1]
+    a = addrs[:n]
+    s_hi, s_lo = starts[i, 0], starts[i, 1]
+    assert np.all((s_hi < a[:, 0]) | ((s_hi == a[:, 0]) & (s_lo <= a[:, 1])))
+    nx = np.minimum(i + 1, len(starts) - 1)
+    last = i == len(starts) - 1
+    n_hi, n_lo = starts[nx, 0], starts[nx, 1]
+    assert np.all(last | (a[:, 0] < n_hi) | ((a[:, 0] == n_hi) & (a[:, 1] < n_lo)))
+
+
+def test_two_streams_overlapping(P, tiny):
+    import torch
+    fib, addrs, want = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    half = addrs.shape[0] // 2
+    d = to_dev(addrs)
+    out = out_u16(addrs.shape[0])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        P.planb_lookup(h, d[:half], half, out[:half], stream=s1)
+        P.planb_lookup(h, d[half:], addrs.shape[0] - half, out[half:], stream=s2)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u16(out, addrs.shape[0]), want)
+
+
+@pytest.mark.parametrize("fanout", [8, 16, 32])
+def test_backbone_4m_addresses(P, fanout):
+    fib = fib_of("backbone", 22)
+    addrs = S.backbone_traffic(fib, 1 << 22, seed=2022)
+    want = oracle_trie("backbone", 22).lookup(addrs)
+    say(f"backbone fanout={fanout}")
+    got, _ = gpu_lookup(P, fib, addrs, fanout)
+    assert np.array_equal(got, want)
+
+
+def test_large_fib_with_host_routes(P):
+    fib = fib_of("large", 33)
+    addrs = S.zipf_traffic(fib, 1 << 22, seed=3033)
+    want = oracle_trie("large", 33).lookup(addrs)
+    for fanout in (8, 16, 32):
+        say(f"large fanout={fanout}")
+        got, _ = gpu_lookup(P, fib, addrs, fanout)
+        assert np.array_equal(got, want)
+
+
+def test_brute_force_agrees_on_a_sample(P, tiny):
+    fib, addrs, want = tiny
+    got, _ = gpu_lookup(P, fib, addrs[:3000])
+    assert np.array_equal(got, lpm_bruteforce(fib.prefixes, fib.lengths, fib.next_hops, addrs[:3000]))

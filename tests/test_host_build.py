@@ -1,0 +1,258 @@
+"""Host-side steps of the build, checked on the CPU (no GPU needed).
+
+* elementary intervals (range conversion + sweep) against the brute-force
+  oracle's LPM at every interval's first and last address;
+* interval invariants (partition of the address space, m <= 2n + 1, every rule
+  boundary present);
+* the paper's worked range-conversion example;
+* build errors (length > 128, reserved next hop, duplicates after masking);
+* layout arithmetic against the paper's capacity numbers and closed forms;
+* the key array: sentinel slots, leaves in order, separators = subtree minima,
+  and a host re-run of the count-based descent == textbook predecessor search.
+"""
+import bisect
+import ipaddress
+import os
+
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings, strategies as st
+
+import planb_synth as S
+from oracle.brute import NO_ROUTE, lpm_bruteforce, lpm_one, rules_of
+from paper_2604_14650_amd import planb as P
+from test_oracle_pins import fibs, fib_arrays, GOLDEN
+
+M128 = (1 << 128) - 1
+
+
+def ints(a):
+    return [S.to_int(r) for r in a]
+
+
+def check_intervals(rules, merge=False):
+    p, L, nh = fib_arrays(rules)
+    starts, inh = P.planb_build_intervals(p, L, nh, flags=P.PLANB_FLAG_MERGE_EQUAL_NH if merge else 0)
+    s = ints(starts)
+    m = len(s)
+    assert s[0] == 0
+    assert all(s[i] < s[i + 1] for i in range(m - 1))
+    assert m <= 2 * len(rules) + 1
+    if not merge:
+        bounds = set()
+        for Pv, Lv, _ in rules:
+            bounds.add(Pv)
+            e = Pv + (1 << (128 - Lv))
+            if e <= M128:
+                bounds.add(e)
+        assert bounds <= set(s)
+    else:
+        assert all(inh[i] != inh[i + 1] for i in range(m - 1))
+    for i in range(m):
+        last = (s[i + 1] - 1) if i + 1 < m else M128
+        assert lpm_one(s[i], rules) == inh[i]
+        assert lpm_one(last, rules) == inh[i]
+    return s, inh
+
+
+@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(fibs(max_rules=14), st.booleans())
+def test_intervals_match_oracle(rules, merge):
+    check_intervals(rules, merge)
+
+
+def test_intervals_on_tiny_workload():
+    fib = S.make_fib(S.TINY, 11)
+    rules = rules_of(fib.prefixes, fib.lengths, fib.next_hops)
+    s, inh = check_intervals(rules)
+    # every rule boundary splits the space once: nothing merged away
+    assert len(s) <= 2 * len(rules) + 1
+    # random addresses: predecessor interval's next hop == LPM
+    a = S.tiny_traffic(fib, 2000, seed=5)
+    want = lpm_bruteforce(fib.prefixes, fib.lengths, fib.next_hops, a)
+    got = [inh[bisect.bisect_right(s, x) - 1] for x in ints(a)]
+    assert list(want) == got
+
+
+def test_worked_example_boundaries():
+    with open(os.path.join(GOLDEN, "range_conversion.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            net, first, last = line.split()
+            net = ipaddress.IPv6Network(net)
+            first = int(ipaddress.IPv6Address(first))
+            last = int(ipaddress.IPv6Address(last))
+            p, L, nh = fib_arrays([(int(net.network_address), net.prefixlen, 3)])
+            starts, inh = P.planb_build_intervals(p, L, nh)
+            assert ints(starts) == [0, first, last + 1]
+            assert list(inh) == [NO_ROUTE, 3, NO_ROUTE]
+
+
+def test_top_of_space_has_no_end_boundary():
+    rules = [(0, 0, 1), (0xFFFF << 112, 16, 2), (M128, 128, 3)]
+    s, inh = check_intervals(rules)
+    assert s == [0, 0xFFFF << 112, M128]
+    assert list(inh) == [1, 2, 3]
+
+
+def test_host_bits_are_masked():
+    p = S.from_ints([(0x20010DB8 << 96) | 0xABCDEF])
+    starts, _ = P.planb_build_intervals(p, np.array([32], np.uint8), np.array([5], np.uint16))
+    assert ints(starts) == [0, 0x20010DB8 << 96, 0x20010DB9 << 96]
+
+
+def test_empty_fib_is_one_no_route_interval():
+    starts, inh = P.planb_build_intervals(np.zeros((0, 2), np.uint64), np.zeros(0, np.uint8),
+                                          np.zeros(0, np.uint16))
+    assert ints(starts) == [0] and list(inh) == [NO_ROUTE]
+
+
+@pytest.mark.parametrize("lengths,nhs,code", [
+    ([129], [1], P.PLANB_EINVAL),
+    ([32], [0xFFFF], P.PLANB_EINVAL),
+])
+def test_build_rejects_bad_rules(lengths, nhs, code):
+    p = S.from_ints([0x2001 << 112] * len(lengths))
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_build_intervals(p, np.array(lengths, np.uint8), np.array(nhs, np.uint16))
+    assert e.value.code == code
+
+
+def test_build_rejects_duplicates_after_masking():
+    p = S.from_ints([0x2001 << 112, (0x2001 << 112) | 77])
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_build_intervals(p, np.array([16, 16], np.uint8), np.array([1, 2], np.uint16))
+    assert e.value.code == P.PLANB_EDUP
+
+
+# ---------------------------------------------------------------- layout pins
+def _golden_layout():
+    d = {}
+    with open(os.path.join(GOLDEN, "layout_capacity.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                k, v = line.split("=")
+                d[k] = float(v) if "." in v else int(v)
+    return d
+
+
+def test_layout_matches_paper_capacity_numbers():
+    g = _golden_layout()
+    b, k, kb = g["fanout"], g["keys_per_node"], g["key_bytes"]
+    MiB = 1 << 20
+    lay = P.planb_layout(g["keys_a"], b, k, trimmed=False)
+    assert lay["depth"] == g["internal_levels_a"] + 1
+    assert lay["level_nodes"][-1] == g["leaves_a"]
+    assert lay["level_offset"][-2] == g["internal_nodes_a"]
+    assert g["leaves_a"] * k == g["keys_a"]
+    leaf_bytes = g["leaves_a"] * k * kb
+    internal_bytes = lay["level_offset"][-2] * k * kb
+    assert round(leaf_bytes / MiB, 1) == g["leaf_mib_a"]
+    assert round(internal_bytes / MiB, 2) == g["internal_mib_a"]
+    # two intervals per prefix -> bytes per prefix
+    assert round((leaf_bytes + internal_bytes) / (g["keys_a"] / 2)) == g["bytes_per_prefix_a"]
+    # one more key no longer fits five internal levels
+    assert P.planb_layout(g["keys_a"] + 1, b, k, trimmed=False)["depth"] == g["internal_levels_a"] + 2
+    lay_b = P.planb_layout(g["keys_b"], b, k, trimmed=False)
+    assert lay_b["depth"] == g["internal_levels_b"] + 1 == g["accesses_b"]
+    assert round(lay_b["level_nodes"][-1] * k * kb / MiB) == g["leaf_mib_b"]
+    assert round(lay_b["level_offset"][-2] * k * kb / MiB) == g["internal_mib_b"]
+    # root keys at 0..7, the children's first key at index 8
+    assert lay["level_offset"][0] * k == g["root_first_key"]
+    assert lay["level_offset"][1] * k - 1 == g["root_last_key"]
+    assert lay["level_offset"][1] * k == g["children_first_key"]
+
+
+@pytest.mark.parametrize("b", [3, 9, 16, 17])
+def test_level_start_and_child_start_closed_forms(b):
+    """level_start(d) = k (b^d - 1)/(b - 1) and child_start(d, j, c) =
+    level_start(d+1) + (j b + c) k; Listing 1's recurrence i' = (k+1) i + (c+1) k
+    reaches the same index from node start i = level_start(d) + j k."""
+    k = b - 1
+    lay = P.planb_layout(k * b ** 5, b, k, trimmed=False)
+    for d in range(lay["depth"]):
+        assert lay["level_offset"][d] * k == k * (b ** d - 1) // (b - 1)
+    for d in range(4):
+        ls1 = lay["level_offset"][d + 1] * k
+        for j in (0, 1, b ** d - 1):
+            i = lay["level_offset"][d] * k + j * k
+            for c in range(b):
+                assert (k + 1) * i + (c + 1) * k == ls1 + (j * b + c) * k
+
+
+@pytest.mark.parametrize("m,b", [(1, 16), (15, 16), (16, 16), (1000, 8), (4096, 16), (70000, 32)])
+def test_trimmed_layout_depth(m, b):
+    lay = P.planb_layout(m, b, b, trimmed=True)
+    k = b - 1
+    D = lay["depth"]
+    assert k * b ** (D - 1) >= m and (D == 1 or k * b ** (D - 2) < m)
+    leaves = -(-m // k)
+    assert lay["level_nodes"][-1] == leaves
+    for l in range(D - 1):
+        assert lay["level_nodes"][l] == -(-leaves // b ** (D - 1 - l))
+
+
+# ------------------------------------------------------------- key array
+def _descend(keys, info, x):
+    """Count-based descent over the host key array (the semantics the kernel
+    implements): c = #{slots <= x}, child q*b + c clamped, leaf idx q*k + c - 1."""
+    b = info["fanout"]
+    D = info["depth"]
+    off, nodes = info["level_offset"], info["level_nodes"]
+    q = 0
+    for l in range(D):
+        base = (off[l] + q) * b
+        c = sum(1 for s in range(b) if keys[base + s] <= x)
+        if l + 1 < D:
+            q = min(q * b + c, nodes[l + 1] - 1)
+        else:
+            return min(q * (b - 1) + c - 1, info["intervals"] - 1)
+
+
+@pytest.mark.parametrize("b", [8, 16, 32])
+@pytest.mark.parametrize("m", [1, 2, 7, 15, 16, 17, 300, 4000])
+def test_key_array_structure_and_descent(b, m):
+    rng = np.random.default_rng(m * 100 + b)
+    vals = sorted(set(int(v) for v in rng.integers(1, 2**62, size=m - 1)) | {0})
+    vals = sorted(set(vals) | {0})
+    while len(vals) < m:
+        vals.append(vals[-1] + 1)
+    vals = [v << 64 | (v * 7 & 0xFFFF) for v in vals[:m]]
+    vals[0] = 0
+    starts = S.from_ints(vals)
+    keys_arr, info = P.planb_build_keys(starts, b)
+    keys = ints(keys_arr)
+    D, off, nodes = info["depth"], info["level_offset"], info["level_nodes"]
+    k = b - 1
+    assert len(keys) == off[D] * b
+    for q in range(off[D]):
+        assert keys[q * b + k] == M128  # sentinel slot
+    leaf_keys = [keys[(off[D - 1] + i // k) * b + i % k] for i in range(m)]
+    assert leaf_keys == vals
+
+    def subtree_min(l, q):
+        while l < D - 1:
+            l, q = l + 1, q * b
+        return keys[(off[D - 1] + q) * b] if q < nodes[D - 1] else M128
+
+    for l in range(D - 1):
+        for q in range(nodes[l]):
+            for j in range(1, b):
+                child = q * b + j
+                want = subtree_min(l + 1, child) if child < nodes[l + 1] else M128
+                assert keys[(off[l] + q) * b + j - 1] == want
+    probes = [0, 1, M128, M128 - 1] + vals + [v - 1 for v in vals[1:]] + [v + 1 for v in vals]
+    probes += [int(x) << 64 for x in rng.integers(0, 2**62, size=200)]
+    for x in probes:
+        assert _descend(keys, info, x) == bisect.bisect_right(vals, x) - 1
+
+
+def test_descent_with_top_key_equal_to_sentinel():
+    vals = [0, 5, M128]
+    keys_arr, info = P.planb_build_keys(S.from_ints(vals), 8)
+    keys = ints(keys_arr)
+    for x, want in [(0, 0), (4, 0), (5, 1), (M128 - 1, 1), (M128, 2)]:
+        assert _descend(keys, info, x) == want
