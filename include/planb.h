@@ -56,10 +56,17 @@ typedef struct planb_fib planb_fib_t;
 typedef struct planb_params {
     uint32_t fanout;        /* b: children per internal node, 8, 16 or 32 (0 -> 16).
                                A node holds k = b-1 keys plus one sentinel slot:
-                               b 16-byte slots, so nodes are 128/256/512 bytes. */
-    uint32_t keys_per_lane; /* lookup tuning, see planb_set_tuning (0 -> default) */
-    int32_t lds_levels;     /* lookup tuning, see planb_set_tuning (-1 or 0 -> default) */
+                               b key slots per node. */
+    uint32_t keys_per_lane; /* initial lookup tuning, see planb_tuning_t (0 -> default) */
+    int32_t lds_levels;     /* initial lookup tuning, see planb_tuning_t (0 -> default) */
     uint32_t flags;         /* PLANB_FLAG_* */
+    uint32_t key_bits;      /* stored key width: 0 = automatic, 128 = always the full
+                               16-byte key, 64 = only the high 64 bits (8-byte slots).
+                               64 is exact, and chosen automatically, exactly when every
+                               interval start has a zero low word -- e.g. when no
+                               prefix is longer than /64 (the paper's own key width,
+                               Section 3 "Parameter Tuning"); asking for 64 otherwise
+                               fails with PLANB_EINVAL. */
 } planb_params_t;
 
 /* Merge neighbouring elementary intervals that resolve to the same next hop.
@@ -138,9 +145,7 @@ typedef struct planb_info {
     uint32_t fanout;                    /* b */
     uint32_t slots;                     /* key slots per node (b: k keys + 1 sentinel) */
     uint32_t depth;                     /* D: levels including the leaf level */
-    uint32_t keys_per_lane;             /* current lookup tuning */
-    int32_t lds_levels;
-    uint32_t lookups_per_group;
+    uint32_t key_bits;                  /* 128 or 64, see planb_params_t */
     uint64_t level_nodes[PLANB_MAX_LEVELS];      /* allocated nodes per level */
     uint64_t level_offset[PLANB_MAX_LEVELS + 1]; /* first node of each level */
     uint64_t key_bytes;                 /* device bytes of the key array */
@@ -150,17 +155,26 @@ typedef struct planb_info {
 int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
 
 /*
- * Lookup tuning of a built FIB (does not change any result):
+ * Launch shape of the lookup kernels for one built FIB (changes no result):
  *   keys_per_lane      each lane compares this many keys of a node, so
  *                      b / keys_per_lane lanes of a wavefront cooperate on one
- *                      lookup; a power of two dividing b, with 1 <= b/kpl <= 16
+ *                      lookup; a power of two dividing b, b/keys_per_lane <= 32
  *   lds_levels         how many top levels each workgroup stages in LDS
  *                      (0..depth; -1 = the deepest that fits 64 KiB)
  *   lookups_per_group  independent lookups each lane group keeps in flight (1, 2 or 4)
- * Returns PLANB_EINVAL for an unsupported combination.
+ *   block_threads      workgroup size, 512 or 1024
  */
-int planb_set_tuning(planb_fib_t* fib, uint32_t keys_per_lane, int32_t lds_levels,
-                     uint32_t lookups_per_group);
+typedef struct planb_tuning {
+    uint32_t keys_per_lane;
+    int32_t lds_levels;
+    uint32_t lookups_per_group;
+    uint32_t block_threads;
+} planb_tuning_t;
+
+/* Returns PLANB_EINVAL for an unsupported combination, PLANB_ERANGE when the
+ * LDS levels exceed what a workgroup may allocate. */
+int planb_set_tuning(planb_fib_t* fib, const planb_tuning_t* tuning);
+int planb_get_tuning(const planb_fib_t* fib, planb_tuning_t* tuning);
 
 /*
  * Pure layout arithmetic (Section 3, "Search on Linearized B+-Tree" closed

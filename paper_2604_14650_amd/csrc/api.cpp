@@ -35,17 +35,18 @@ int check_current_device(const planb_fib_t* fib)
     return PLANB_OK;
 }
 
-int deepest_lds_levels(const Layout& lay, size_t budget)
+int deepest_lds_levels(const Layout& lay, size_t key_bytes, size_t budget)
 {
     int L = 0;
-    while (L < (int)lay.depth && lay.offset[L + 1] * lay.b * 16ull <= budget) ++L;
+    while (L < (int)lay.depth && lay.offset[L + 1] * lay.b * key_bytes <= budget) ++L;
     return L;
 }
 
 void refresh_desc(planb_fib_t* f)
 {
     TreeDesc& t = f->desc;
-    t.keys = reinterpret_cast<const uint4*>(f->d_keys);
+    t.keys = f->d_keys;
+    t.key_bytes = f->key_bytes_per_slot;
     t.vals = f->d_vals;
     t.m_minus_1 = f->iv.starts.size() - 1;
     t.depth = f->lay.depth;
@@ -58,20 +59,24 @@ void refresh_desc(planb_fib_t* f)
     }
 }
 
-int validate_tuning(const planb_fib_t* f, uint32_t kpl, int32_t lds_levels, uint32_t R, int32_t* lds_out)
+int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning* out, int32_t* lds_out)
 {
-    const uint32_t b = f->lay.b;
-    if (kpl == 0 || (kpl & (kpl - 1)) || b % kpl || b / kpl > 32 || b / kpl < 1 ||
-        !lookup_variant_exists((int)b, (int)kpl, (int)R))
-        return fail(PLANB_EINVAL, "unsupported keys_per_lane " + std::to_string(kpl) + " / lookups_per_group " +
-                                      std::to_string(R) + " for fanout " + std::to_string(b));
-    if (lds_levels < 0) lds_levels = deepest_lds_levels(f->lay, 64 * 1024);
-    if (lds_levels > (int32_t)f->lay.depth)
-        return fail(PLANB_EINVAL, "lds_levels exceeds the tree depth");
-    const size_t bytes = f->lay.offset[lds_levels] * b * 16ull;
+    const uint32_t b = f->lay.b, kpl = tu.keys_per_lane, R = tu.lookups_per_group, bs = tu.block_threads;
+    if (kpl == 0 || (kpl & (kpl - 1)) || b % kpl || b / kpl > 32 || (bs != 512 && bs != 1024) ||
+        !lookup_variant_exists((int)b, (int)kpl, (int)R, (int)bs))
+        return fail(PLANB_EINVAL, "unsupported tuning: keys_per_lane " + std::to_string(kpl) +
+                                      ", lookups_per_group " + std::to_string(R) + ", block_threads " +
+                                      std::to_string(bs) + " for fanout " + std::to_string(b));
+    int32_t lds_levels = tu.lds_levels;
+    if (lds_levels < 0) lds_levels = deepest_lds_levels(f->lay, f->key_bytes_per_slot, 64 * 1024);
+    if (lds_levels > (int32_t)f->lay.depth) return fail(PLANB_EINVAL, "lds_levels exceeds the tree depth");
+    const size_t bytes = f->lay.offset[lds_levels] * b * (size_t)f->key_bytes_per_slot;
     if (bytes > (size_t)max_lds_bytes())
         return fail(PLANB_ERANGE, "the top " + std::to_string(lds_levels) + " levels need " + std::to_string(bytes) +
                                       " bytes of LDS, more than a workgroup may allocate");
+    out->kpl = (int)kpl;
+    out->R = (int)R;
+    out->block = (int)bs;
     *lds_out = lds_levels;
     return PLANB_OK;
 }
@@ -85,6 +90,7 @@ void layout_to_info(const Layout& lay, planb_info_t* info)
     info->depth = lay.depth;
     for (uint32_t l = 0; l < lay.depth; ++l) info->level_nodes[l] = lay.nodes[l];
     for (uint32_t l = 0; l <= lay.depth; ++l) info->level_offset[l] = lay.offset[l];
+    info->key_bits = 128;
     info->key_bytes = lay.total_nodes() * lay.slots * 16ull;
 }
 
@@ -157,13 +163,34 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
         delete f;
         return nullptr;
     }
+    bool all_lo_zero = true;
+    for (const U128& k : f->iv.starts) all_lo_zero &= (k.lo == 0);
+    if (p.key_bits != 0 && p.key_bits != 64 && p.key_bits != 128) {
+        fail(PLANB_EINVAL, "key_bits must be 0, 64 or 128");
+        delete f;
+        return nullptr;
+    }
+    if (p.key_bits == 64 && !all_lo_zero) {
+        fail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
+        delete f;
+        return nullptr;
+    }
+    const bool narrow = p.key_bits == 64 || (p.key_bits == 0 && all_lo_zero);
+    f->key_bytes_per_slot = narrow ? 8 : 16;
+    std::vector<uint64_t> keys_hi;
+    if (narrow) {
+        keys_hi.resize(keys.size());
+        for (size_t i = 0; i < keys.size(); ++i) keys_hi[i] = keys[i].hi;
+        std::vector<U128>().swap(keys);
+    }
     hipError_t e = hipGetDevice(&f->device);
     if (e != hipSuccess) {
         fail_hip(e, "hipGetDevice");
         delete f;
         return nullptr;
     }
-    const size_t kbytes = keys.size() * sizeof(U128);
+    const void* host_keys = narrow ? (const void*)keys_hi.data() : (const void*)keys.data();
+    const size_t kbytes = narrow ? keys_hi.size() * sizeof(uint64_t) : keys.size() * sizeof(U128);
     const size_t vbytes = ((m + 63) / 64) * 64 * sizeof(uint16_t);
     if ((e = hipMalloc(&f->d_keys, kbytes)) != hipSuccess || (e = hipMalloc(&f->d_vals, vbytes)) != hipSuccess) {
         fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -172,22 +199,23 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
     }
     f->key_bytes = kbytes;
     f->value_bytes = vbytes;
-    if ((e = hipMemcpy(f->d_keys, keys.data(), kbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+    if ((e = hipMemcpy(f->d_keys, host_keys, kbytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(f->d_vals, 0xFF, vbytes)) != hipSuccess ||
         (e = hipMemcpy(f->d_vals, f->iv.nh.data(), m * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) {
         fail_hip(e, "uploading the tree");
         planb_free(f);
         return nullptr;
     }
-    uint32_t kpl = p.keys_per_lane ? p.keys_per_lane : default_kpl(p.fanout);
-    int32_t lds = p.lds_levels > 0 ? p.lds_levels : -1;
+    planb_tuning_t tu{};
+    tu.keys_per_lane = p.keys_per_lane ? p.keys_per_lane : default_kpl(p.fanout);
+    tu.lds_levels = p.lds_levels > 0 ? p.lds_levels : -1;
+    tu.lookups_per_group = 2;
+    tu.block_threads = 512;
     int32_t lds_ok = 0;
-    if ((rc = validate_tuning(f, kpl, lds, 2, &lds_ok)) != PLANB_OK) {
+    if ((rc = validate_tuning(f, tu, &f->tune, &lds_ok)) != PLANB_OK) {
         planb_free(f);
         return nullptr;
     }
-    f->kpl = kpl;
-    f->R = 2;
     f->lds_levels = lds_ok;
     refresh_desc(f);
     return f;
@@ -225,8 +253,7 @@ int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, ui
 {
     int rc = check_lookup_args(fib, addrs, n, out, 2);
     if (rc != PLANB_OK || n == 0) return rc;
-    hipError_t e = launch_lookup(fib->desc, (int)fib->kpl, (int)fib->R, addrs, n, out, false,
-                                 static_cast<hipStream_t>(stream));
+    hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, false, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
 
@@ -234,8 +261,7 @@ int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t
 {
     int rc = check_lookup_args(fib, addrs, n, out, 4);
     if (rc != PLANB_OK || n == 0) return rc;
-    hipError_t e = launch_lookup(fib->desc, (int)fib->kpl, (int)fib->R, addrs, n, out, true,
-                                 static_cast<hipStream_t>(stream));
+    hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, true, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
 
@@ -306,9 +332,7 @@ int planb_get_info(const planb_fib_t* fib, planb_info_t* info)
 {
     if (!fib || !info) return fail(PLANB_EINVAL, "NULL argument");
     layout_to_info(fib->lay, info);
-    info->keys_per_lane = fib->kpl;
-    info->lds_levels = fib->lds_levels;
-    info->lookups_per_group = fib->R;
+    info->key_bits = fib->key_bytes_per_slot * 8;
     info->key_bytes = fib->key_bytes;
     info->value_bytes = fib->value_bytes;
     return PLANB_OK;
@@ -325,16 +349,26 @@ int planb_layout(uint64_t m, uint32_t fanout, uint32_t slots, int trimmed, planb
     return PLANB_OK;
 }
 
-int planb_set_tuning(planb_fib_t* fib, uint32_t keys_per_lane, int32_t lds_levels, uint32_t lookups_per_group)
+int planb_set_tuning(planb_fib_t* fib, const planb_tuning_t* tuning)
 {
-    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (!fib || !tuning) return fail(PLANB_EINVAL, "NULL argument");
     int32_t lds = 0;
-    int rc = validate_tuning(fib, keys_per_lane, lds_levels, lookups_per_group, &lds);
+    LookupTuning lt;
+    int rc = validate_tuning(fib, *tuning, &lt, &lds);
     if (rc != PLANB_OK) return rc;
-    fib->kpl = keys_per_lane;
+    fib->tune = lt;
     fib->lds_levels = lds;
-    fib->R = lookups_per_group;
     refresh_desc(fib);
+    return PLANB_OK;
+}
+
+int planb_get_tuning(const planb_fib_t* fib, planb_tuning_t* tuning)
+{
+    if (!fib || !tuning) return fail(PLANB_EINVAL, "NULL argument");
+    tuning->keys_per_lane = (uint32_t)fib->tune.kpl;
+    tuning->lds_levels = fib->lds_levels;
+    tuning->lookups_per_group = (uint32_t)fib->tune.R;
+    tuning->block_threads = (uint32_t)fib->tune.block;
     return PLANB_OK;
 }
 

@@ -21,7 +21,8 @@ struct planb_fib {
     uint16_t* d_vals = nullptr;
     size_t key_bytes = 0, value_bytes = 0;
     int device = 0;
-    uint32_t kpl = 4, R = 2;
+    uint32_t key_bytes_per_slot = 16;  // 16 (128-bit keys) or 8 (hi word only)
+    planb::LookupTuning tune;
     int32_t lds_levels = 0;
     planb::TreeDesc desc{};
     planb::LearnedModel* learned = nullptr;

@@ -9,9 +9,13 @@ namespace planb {
 
 constexpr int kDevMaxLevels = 16;
 
+// A 16-byte address record {hi, lo} as a native vector (for streaming loads).
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
 // What a kernel needs to descend one built tree.  Passed by value (kernarg).
 struct TreeDesc {
-    const uint4* keys;       // node-major key array; node = B slots of 16 bytes
+    const void* keys;        // node-major key array; node = B slots of key_bytes
+    uint32_t key_bytes;      // 16: full 128-bit keys {hi, lo}; 8: the hi word only (every key's lo is 0)
     const uint16_t* vals;    // next hop of interval i at vals[i]
     uint64_t m_minus_1;      // last interval index
     uint32_t depth;          // D, levels including the leaf level
@@ -22,13 +26,30 @@ struct TreeDesc {
     uint32_t last[kDevMaxLevels];  // last allocated node of each level
 };
 
-// 128-bit unsigned key <= x, key given as the 16-byte record {hi, lo}.
-__device__ __forceinline__ int key_le(uint4 k, uint64_t xhi, uint64_t xlo)
-{
-    const uint64_t khi = ((uint64_t)k.y << 32) | k.x;
-    const uint64_t klo = ((uint64_t)k.w << 32) | k.z;
-    return (khi < xhi) | ((khi == xhi) & (klo <= xlo));
-}
+// Key formats.  Wide: the 16-byte record {hi, lo}, compared as a 128-bit
+// unsigned integer.  Narrow: only hi is stored, which a tree uses when every
+// key's lo word is zero; then key <= x exactly when key.hi <= x.hi.
+template <bool WIDE>
+struct KeyFmt;
+
+template <>
+struct KeyFmt<true> {
+    using T = uint4;
+    static __device__ __forceinline__ int le(uint4 k, uint64_t xhi, uint64_t xlo)
+    {
+        const uint64_t khi = ((uint64_t)k.y << 32) | k.x;
+        const uint64_t klo = ((uint64_t)k.w << 32) | k.z;
+        return (khi < xhi) | ((khi == xhi) & (klo <= xlo));
+    }
+};
+
+template <>
+struct KeyFmt<false> {
+    using T = uint64_t;
+    static __device__ __forceinline__ int le(uint64_t k, uint64_t xhi, uint64_t) { return k <= xhi; }
+};
+
+__device__ __forceinline__ int key_le(uint4 k, uint64_t xhi, uint64_t xlo) { return KeyFmt<true>::le(k, xhi, xlo); }
 
 // Sum of v over aligned groups of G consecutive lanes; every lane of a group
 // receives the group's total.  G <= 16 stays inside one DPP row.

@@ -27,26 +27,29 @@
 
 namespace planb {
 
-constexpr int kBlock = 512;
-
-template <int B, int KPL, int R>
-__global__ void __launch_bounds__(kBlock)
-lookup_kernel(TreeDesc t, const uint4* __restrict__ addrs, uint64_t n, void* __restrict__ out,
-              int index_out)
+template <int B, int KPL, int R, bool WIDE, int BS>
+__global__ void __launch_bounds__(BS)
+lookup_kernel(TreeDesc t, const uint4* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
 {
+    using KF = KeyFmt<WIDE>;
+    using K = typename KF::T;
     constexpr int G = B / KPL;    // lanes per lookup
     constexpr int LPW = 64 / G;   // lookups per wavefront per step
-    extern __shared__ uint4 lds_keys[];
+    extern __shared__ uint4 lds_raw[];
+    const K* lds_keys = reinterpret_cast<const K*>(lds_raw);
+    const K* gkeys = static_cast<const K*>(t.keys);
 
-    const uint32_t lds_slots = t.lds_nodes * B;
-    for (uint32_t i = threadIdx.x; i < lds_slots; i += blockDim.x) lds_keys[i] = t.keys[i];
+    // stage the top levels (the first lds_nodes nodes of the array) in 16-byte units
+    const uint32_t units = t.lds_nodes * (uint32_t)(B * sizeof(K) / 16);
+    const uint4* src = static_cast<const uint4*>(t.keys);
+    for (uint32_t i = threadIdx.x; i < units; i += BS) lds_raw[i] = src[i];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int grp = lane / G;
     const int j = lane % G;
-    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    const uint64_t wave = (uint64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (BS / 64);
     constexpr uint64_t per_step = (uint64_t)LPW * R;
 
     for (uint64_t base = wave * per_step; base < n; base += nwaves * per_step) {
@@ -54,38 +57,38 @@ lookup_kernel(TreeDesc t, const uint4* __restrict__ addrs, uint64_t n, void* __r
         uint32_t q[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            uint64_t i = base + (uint64_t)r * LPW + grp;
-            uint4 a = addrs[i < n ? i : n - 1];
-            xhi[r] = ((uint64_t)a.y << 32) | a.x;
-            xlo[r] = ((uint64_t)a.w << 32) | a.z;
+            const uint64_t i = base + (uint64_t)r * LPW + grp;
+            const u64x2 a = __builtin_nontemporal_load(reinterpret_cast<const u64x2*>(addrs) + (i < n ? i : n - 1));
+            xhi[r] = a.x;
+            xlo[r] = a.y;
             q[r] = 0;
         }
-        // internal levels
+        // internal levels: count keys <= x, step to child q*B + count
         for (uint32_t l = 0; l + 1 < t.depth; ++l) {
             const uint32_t off = t.off[l], lim = t.last[l + 1];
             if (l < t.lds_levels) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const uint4* nd = lds_keys + (size_t)(off + q[r]) * B + j;
+                    const size_t nb = (size_t)(off + q[r]) * B + j;
                     int cnt = 0;
 #pragma unroll
-                    for (int s = 0; s < KPL; ++s) cnt += key_le(nd[s * G], xhi[r], xlo[r]);
+                    for (int s = 0; s < KPL; ++s) cnt += KF::le(lds_keys[nb + s * G], xhi[r], xlo[r]);
                     const uint32_t c = (uint32_t)group_sum<G>(cnt);
                     q[r] = min(q[r] * B + c, lim);
                 }
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const uint4* nd = t.keys + (size_t)(off + q[r]) * B + j;
+                    const size_t nb = (size_t)(off + q[r]) * B + j;
                     int cnt = 0;
 #pragma unroll
-                    for (int s = 0; s < KPL; ++s) cnt += key_le(nd[s * G], xhi[r], xlo[r]);
+                    for (int s = 0; s < KPL; ++s) cnt += KF::le(gkeys[nb + s * G], xhi[r], xlo[r]);
                     const uint32_t c = (uint32_t)group_sum<G>(cnt);
                     q[r] = min(q[r] * B + c, lim);
                 }
             }
         }
-        // leaf level: c >= 1 always (interval 0 starts at address 0)
+        // leaf level: count >= 1 always (interval 0 starts at address 0)
         const uint32_t loff = t.off[t.depth - 1];
         const bool leaf_lds = t.lds_levels >= t.depth;
 #pragma unroll
@@ -94,10 +97,10 @@ lookup_kernel(TreeDesc t, const uint4* __restrict__ addrs, uint64_t n, void* __r
             int cnt = 0;
             if (leaf_lds) {
 #pragma unroll
-                for (int s = 0; s < KPL; ++s) cnt += key_le(lds_keys[nb + s * G], xhi[r], xlo[r]);
+                for (int s = 0; s < KPL; ++s) cnt += KF::le(lds_keys[nb + s * G], xhi[r], xlo[r]);
             } else {
 #pragma unroll
-                for (int s = 0; s < KPL; ++s) cnt += key_le(t.keys[nb + s * G], xhi[r], xlo[r]);
+                for (int s = 0; s < KPL; ++s) cnt += KF::le(gkeys[nb + s * G], xhi[r], xlo[r]);
             }
             const uint32_t c = (uint32_t)group_sum<G>(cnt);
             uint64_t idx = (uint64_t)q[r] * (B - 1) + c - 1;
@@ -105,9 +108,9 @@ lookup_kernel(TreeDesc t, const uint4* __restrict__ addrs, uint64_t n, void* __r
             const uint64_t i = base + (uint64_t)r * LPW + grp;
             if (j == 0 && i < n) {
                 if (index_out)
-                    static_cast<uint32_t*>(out)[i] = (uint32_t)idx;
+                    __builtin_nontemporal_store((uint32_t)idx, static_cast<uint32_t*>(out) + i);
                 else
-                    static_cast<uint16_t*>(out)[i] = t.vals[idx];
+                    __builtin_nontemporal_store(t.vals[idx], static_cast<uint16_t*>(out) + i);
             }
         }
     }
@@ -117,38 +120,46 @@ namespace {
 
 using KernelFn = void (*)(TreeDesc, const uint4*, uint64_t, void*, int);
 
-template <int B, int KPL>
+template <int B, int KPL, bool W, int BS>
 KernelFn pick_r(int R)
 {
     switch (R) {
-    case 1: return lookup_kernel<B, KPL, 1>;
-    case 2: return lookup_kernel<B, KPL, 2>;
-    case 4: return lookup_kernel<B, KPL, 4>;
+    case 1: return lookup_kernel<B, KPL, 1, W, BS>;
+    case 2: return lookup_kernel<B, KPL, 2, W, BS>;
+    case 4: return lookup_kernel<B, KPL, 4, W, BS>;
     default: return nullptr;
     }
 }
 
-template <int B>
+template <int B, bool W, int BS>
 KernelFn pick_kpl(int kpl, int R)
 {
     switch (kpl) {
-    case 1: return pick_r<B, 1>(R);
-    case 2: return pick_r<B, 2>(R);
-    case 4: return pick_r<B, 4>(R);
-    case 8: return pick_r<B, 8>(R);
-    case 16: if constexpr (B >= 16) return pick_r<B, 16>(R); else return nullptr;
+    case 1: return pick_r<B, 1, W, BS>(R);
+    case 2: return pick_r<B, 2, W, BS>(R);
+    case 4: return pick_r<B, 4, W, BS>(R);
+    case 8: return pick_r<B, 8, W, BS>(R);
+    case 16: if constexpr (B >= 16) return pick_r<B, 16, W, BS>(R); else return nullptr;
     default: return nullptr;
     }
 }
 
-KernelFn pick(int B, int kpl, int R)
+template <bool W, int BS>
+KernelFn pick_b(int B, int kpl, int R)
 {
     switch (B) {
-    case 8: return pick_kpl<8>(kpl, R);
-    case 16: return pick_kpl<16>(kpl, R);
-    case 32: return pick_kpl<32>(kpl, R);
+    case 8: return pick_kpl<8, W, BS>(kpl, R);
+    case 16: return pick_kpl<16, W, BS>(kpl, R);
+    case 32: return pick_kpl<32, W, BS>(kpl, R);
     default: return nullptr;
     }
+}
+
+KernelFn pick(int B, int kpl, int R, bool wide, int bs)
+{
+    if (bs == 512) return wide ? pick_b<true, 512>(B, kpl, R) : pick_b<false, 512>(B, kpl, R);
+    if (bs == 1024) return wide ? pick_b<true, 1024>(B, kpl, R) : pick_b<false, 1024>(B, kpl, R);
+    return nullptr;
 }
 
 struct DevProps {
@@ -180,7 +191,7 @@ hipError_t dev_props(DevProps* p)
     return hipSuccess;
 }
 
-hipError_t occupancy(KernelFn fn, size_t lds, int* blocks)
+hipError_t occupancy(KernelFn fn, int bs, size_t lds, int* blocks)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -200,7 +211,7 @@ hipError_t occupancy(KernelFn fn, size_t lds, int* blocks)
         if (e != hipSuccess) return e;
     }
     int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, bs, lds);
     if (e != hipSuccess) return e;
     if (nb < 1) nb = 1;
     std::lock_guard<std::mutex> g(g_mu);
@@ -211,7 +222,7 @@ hipError_t occupancy(KernelFn fn, size_t lds, int* blocks)
 
 }  // namespace
 
-bool lookup_variant_exists(int B, int kpl, int R) { return pick(B, kpl, R) != nullptr; }
+bool lookup_variant_exists(int B, int kpl, int R, int bs) { return pick(B, kpl, R, true, bs) != nullptr; }
 
 int max_lds_bytes()
 {
@@ -220,25 +231,25 @@ int max_lds_bytes()
     return p.max_lds;
 }
 
-hipError_t launch_lookup(const TreeDesc& t, int kpl, int R, const void* addrs, uint64_t n, void* out,
+hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
                          bool index_out, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    KernelFn fn = pick((int)t.fanout, kpl, R);
+    KernelFn fn = pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block);
     if (!fn) return hipErrorInvalidValue;
     DevProps p;
     hipError_t e = dev_props(&p);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)t.lds_nodes * t.fanout * sizeof(uint4);
+    const size_t lds = (size_t)t.lds_nodes * t.fanout * t.key_bytes;
     if (lds > (size_t)p.max_lds) return hipErrorInvalidValue;
     int nb = 1;
-    if ((e = occupancy(fn, lds, &nb)) != hipSuccess) return e;
-    const int G = (int)t.fanout / kpl;
-    const uint64_t per_block = (uint64_t)(kBlock / 64) * (64 / G) * R;
-    uint64_t want = (n + per_block - 1) / per_block;
-    uint64_t cap = (uint64_t)p.cus * nb;
+    if ((e = occupancy(fn, tu.block, lds, &nb)) != hipSuccess) return e;
+    const int G = (int)t.fanout / tu.kpl;
+    const uint64_t per_block = (uint64_t)(tu.block / 64) * (64 / G) * tu.R;
+    const uint64_t want = (n + per_block - 1) / per_block;
+    const uint64_t cap = (uint64_t)p.cus * nb;
     const unsigned grid = (unsigned)(want < cap ? want : cap);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), lds, stream, t, static_cast<const uint4*>(addrs), n, out,
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(tu.block), lds, stream, t, static_cast<const uint4*>(addrs), n, out,
                        index_out ? 1 : 0);
     return hipGetLastError();
 }

@@ -7,15 +7,22 @@
 
 namespace planb {
 
-// Whether a (fanout, keys per lane, lookups per group) kernel is compiled in.
-bool lookup_variant_exists(int B, int kpl, int R);
+// Launch shape of the plain lookup kernel.
+struct LookupTuning {
+    int kpl = 4;      // keys each lane compares per node (B / kpl lanes per lookup)
+    int R = 2;        // lookups each lane group keeps in flight
+    int block = 512;  // threads per workgroup
+};
+
+// Whether a (fanout, keys per lane, lookups per group, block size) kernel is compiled in.
+bool lookup_variant_exists(int B, int kpl, int R, int bs);
 
 // Largest dynamic LDS allocation a workgroup may request on the current device.
 int max_lds_bytes();
 
 // Enqueue one plain lookup over n addresses on `stream`; out receives uint16
 // next hops, or uint32 interval indices when index_out.
-hipError_t launch_lookup(const TreeDesc& t, int kpl, int R, const void* addrs, uint64_t n, void* out,
+hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
                          bool index_out, hipStream_t stream);
 
 }  // namespace planb

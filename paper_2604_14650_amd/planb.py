@@ -40,13 +40,17 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 class planb_params_t(ctypes.Structure):
     _fields_ = [("fanout", ctypes.c_uint32), ("keys_per_lane", ctypes.c_uint32),
-                ("lds_levels", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("lds_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("key_bits", ctypes.c_uint32)]
+
+
+class planb_tuning_t(ctypes.Structure):
+    _fields_ = [("keys_per_lane", ctypes.c_uint32), ("lds_levels", ctypes.c_int32),
+                ("lookups_per_group", ctypes.c_uint32), ("block_threads", ctypes.c_uint32)]
 
 
 class planb_info_t(ctypes.Structure):
     _fields_ = [("intervals", ctypes.c_uint64), ("fanout", ctypes.c_uint32), ("slots", ctypes.c_uint32),
-                ("depth", ctypes.c_uint32), ("keys_per_lane", ctypes.c_uint32), ("lds_levels", ctypes.c_int32),
-                ("lookups_per_group", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
                 ("level_nodes", ctypes.c_uint64 * PLANB_MAX_LEVELS),
                 ("level_offset", ctypes.c_uint64 * (PLANB_MAX_LEVELS + 1)),
                 ("key_bytes", ctypes.c_uint64), ("value_bytes", ctypes.c_uint64)]
@@ -73,7 +77,8 @@ _sig("planb_last_status", ctypes.c_int)
 _sig("planb_num_intervals", _sz, _vp)
 _sig("planb_export_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz)
 _sig("planb_get_info", ctypes.c_int, _vp, ctypes.POINTER(planb_info_t))
-_sig("planb_set_tuning", ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint32)
+_sig("planb_set_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
+_sig("planb_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_build_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz, ctypes.c_uint32, _vp, _vp, _sz)
 _sig("planb_build_keys", ctypes.c_longlong, _vp, _sz, ctypes.c_uint32, _vp, _sz, ctypes.POINTER(planb_info_t))
 _sig("planb_layout", ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
@@ -136,14 +141,14 @@ def planb_last_status() -> int:
 
 
 def planb_build(prefixes, lengths, next_hops, fanout: int = 16, keys_per_lane: int = 0,
-                lds_levels: int = -1, flags: int = 0) -> Fib:
+                lds_levels: int = 0, flags: int = 0, key_bits: int = 0) -> Fib:
     """prefixes: (n, 2) uint64 {hi, lo}; lengths: (n,) uint8; next_hops: (n,) uint16."""
     p = _host(prefixes, np.uint64, (2,)) if len(lengths) else np.zeros((0, 2), np.uint64)
     L = _host(lengths, np.uint8)
     nh = _host(next_hops, np.uint16)
     if not (p.shape[0] == L.shape[0] == nh.shape[0]):
         raise ValueError("prefixes, lengths and next_hops differ in length")
-    params = planb_params_t(fanout, keys_per_lane, lds_levels, flags)
+    params = planb_params_t(fanout, keys_per_lane, lds_levels, flags, key_bits)
     n = L.shape[0]
     ptr = _lib.planb_build_ex(p.ctypes.data if n else None, L.ctypes.data if n else None,
                               nh.ctypes.data if n else None, n, ctypes.byref(params))
@@ -204,8 +209,7 @@ def planb_export_intervals(fib: Fib):
 def _info_dict(info: planb_info_t) -> dict:
     D = info.depth
     return {"intervals": info.intervals, "fanout": info.fanout, "slots": info.slots, "depth": D,
-            "keys_per_lane": info.keys_per_lane, "lds_levels": info.lds_levels,
-            "lookups_per_group": info.lookups_per_group,
+            "key_bits": info.key_bits,
             "level_nodes": [int(info.level_nodes[i]) for i in range(D)],
             "level_offset": [int(info.level_offset[i]) for i in range(D + 1)],
             "key_bytes": int(info.key_bytes), "value_bytes": int(info.value_bytes)}
@@ -217,8 +221,17 @@ def planb_get_info(fib: Fib) -> dict:
     return _info_dict(info)
 
 
-def planb_set_tuning(fib: Fib, keys_per_lane: int, lds_levels: int = -1, lookups_per_group: int = 2):
-    _check(_lib.planb_set_tuning(fib, keys_per_lane, lds_levels, lookups_per_group))
+def planb_set_tuning(fib: Fib, keys_per_lane: int, lds_levels: int = -1, lookups_per_group: int = 2,
+                     block_threads: int = 512):
+    t = planb_tuning_t(keys_per_lane, lds_levels, lookups_per_group, block_threads)
+    _check(_lib.planb_set_tuning(fib, ctypes.byref(t)))
+
+
+def planb_get_tuning(fib: Fib) -> dict:
+    t = planb_tuning_t()
+    _check(_lib.planb_get_tuning(fib, ctypes.byref(t)))
+    return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels,
+            "lookups_per_group": t.lookups_per_group, "block_threads": t.block_threads}
 
 
 def planb_layout(m: int, fanout: int, slots: int, trimmed: bool = True) -> dict:

@@ -16,10 +16,10 @@ VARIANTS = [(8, 1, 1), (8, 2, 2), (8, 4, 4), (8, 8, 1), (16, 1, 2), (16, 2, 1), 
             (16, 8, 2), (16, 16, 1), (32, 1, 1), (32, 2, 2), (32, 4, 2), (32, 8, 4), (32, 16, 1)]
 
 
-def gpu_lookup(P, fib, addrs, fanout=16, kpl=None, lds=-1, R=2):
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+def gpu_lookup(P, fib, addrs, fanout=16, kpl=None, lds=-1, R=2, key_bits=0, block=512):
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
     if kpl is not None:
-        P.planb_set_tuning(h, kpl, lds, R)
+        P.planb_set_tuning(h, kpl, lds, R, block)
     d = to_dev(addrs)
     out = out_u16(addrs.shape[0])
     P.planb_lookup(h, d, addrs.shape[0], out)
@@ -39,16 +39,19 @@ def tiny():
     return fib, addrs, oracle_trie("tiny", 11).lookup(addrs)
 
 
+@pytest.mark.parametrize("key_bits", [0, 128])
 @pytest.mark.parametrize("fanout,kpl,R", VARIANTS)
-def test_tiny_all_addresses(P, tiny, fanout, kpl, R):
+def test_tiny_all_addresses(P, tiny, fanout, kpl, R, key_bits):
     fib, addrs, want = tiny
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
-    depth = P.planb_get_info(h)["depth"]
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
+    info = P.planb_get_info(h)
+    assert info["key_bits"] == (key_bits or 64)  # every tiny prefix is at most /64
+    depth = info["depth"]
     d = to_dev(addrs)
-    for lds in sorted({0, -1, depth, max(0, depth - 1)}):
-        say(f"tiny fanout={fanout} kpl={kpl} R={R} lds={lds}")
+    for lds, block in sorted({(0, 512), (-1, 512), (depth, 1024), (max(0, depth - 1), 512)}):
+        say(f"tiny key_bits={key_bits} fanout={fanout} kpl={kpl} R={R} lds={lds} block={block}")
         try:
-            P.planb_set_tuning(h, kpl, lds, R)
+            P.planb_set_tuning(h, kpl, lds, R, block)
         except P.PlanbError:
             continue  # more levels than fit in LDS
         out = out_u16(addrs.shape[0])
@@ -95,11 +98,12 @@ def test_edge_cases(P, fanout, name):
     for kpl in (1, fanout // 2, fanout // 4):
         if fanout // kpl > 32:
             continue
-        say(f"edge {name} fanout={fanout} kpl={kpl}")
-        got, _ = gpu_lookup(P, fib, q, fanout, kpl, -1, 2)
-        assert np.array_equal(got, want)
-        got, _ = gpu_lookup(P, fib, q, fanout, kpl, 0, 1)
-        assert np.array_equal(got, want)
+        for key_bits in (0, 128):
+            say(f"edge {name} fanout={fanout} kpl={kpl} key_bits={key_bits}")
+            got, _ = gpu_lookup(P, fib, q, fanout, kpl, -1, 2, key_bits)
+            assert np.array_equal(got, want)
+            got, _ = gpu_lookup(P, fib, q, fanout, kpl, 0, 1, key_bits, 1024)
+            assert np.array_equal(got, want)
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097, 123457])
@@ -173,14 +177,24 @@ def test_two_streams_overlapping(P, tiny):
     assert np.array_equal(host_u16(out, addrs.shape[0]), want)
 
 
+@pytest.mark.parametrize("key_bits", [0, 128])
 @pytest.mark.parametrize("fanout", [8, 16, 32])
-def test_backbone_4m_addresses(P, fanout):
+def test_backbone_4m_addresses(P, fanout, key_bits):
     fib = fib_of("backbone", 22)
     addrs = S.backbone_traffic(fib, 1 << 22, seed=2022)
     want = oracle_trie("backbone", 22).lookup(addrs)
-    say(f"backbone fanout={fanout}")
-    got, _ = gpu_lookup(P, fib, addrs, fanout)
+    say(f"backbone fanout={fanout} key_bits={key_bits}")
+    got, _ = gpu_lookup(P, fib, addrs, fanout, key_bits=key_bits)
     assert np.array_equal(got, want)
+
+
+def test_narrow_keys_refused_when_inexact(P):
+    fib = fib_of("large", 33)  # holds /128 host routes
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, key_bits=64)
+    assert e.value.code == P.PLANB_EINVAL
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    assert P.planb_get_info(h)["key_bits"] == 128
 
 
 def test_large_fib_with_host_routes(P):
