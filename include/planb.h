@@ -189,6 +189,59 @@ int planb_get_tuning(const planb_fib_t* fib, planb_tuning_t* tuning);
 int planb_layout(uint64_t m, uint32_t fanout, uint32_t slots, int trimmed, planb_info_t* info);
 
 /*
+ * Uneven batches in one persistent launch (Section 3 "Batching": many
+ * independent lookups in flight; here a grid of compute units x resident
+ * workgroups stages the top levels in LDS once and then walks every batch).
+ */
+typedef struct planb_batch {
+    const planb_addr_t* addrs; /* device, n records, 16-byte aligned */
+    uint16_t* out;             /* device, n next hops, 2-byte aligned */
+    uint64_t n;                /* may be 0 */
+} planb_batch_t;
+
+/* batches: device array of max_batches descriptors; n_batches: device pointer
+ * to the number of valid descriptors (values above max_batches are clipped),
+ * read by the kernel, so one launch shape serves any batch list.  The total
+ * number of lookups per call must stay below 2^32.  Uses the FIB's current
+ * tuning; its LDS levels plus 4 * (max_batches + block_threads + 1) bytes must
+ * fit a workgroup's LDS (else PLANB_ERANGE). */
+int planb_lookup_batches(const planb_fib_t* fib, const planb_batch_t* batches, const uint32_t* n_batches,
+                         uint32_t max_batches, void* stream);
+
+/*
+ * The same persistent launch captured once into HIP graphs and replayed:
+ * planb_graph_create captures (copy of a pinned host descriptor buffer to the
+ * device) + (persistent batches kernel) for the FIB's current tuning, into a
+ * ring of 4 graphs.  planb_graph_launch copies the host batch list into the
+ * next ring slot's pinned buffer (waiting first, if that slot's previous
+ * replay has not finished) and replays that slot's graph on `stream`; the
+ * descriptors are read when the graph runs, the address and output buffers
+ * must stay valid until it completes.  Later tuning changes do not affect an
+ * existing graph.  planb_graph_free waits for outstanding replays.
+ */
+typedef struct planb_graph planb_graph_t;
+planb_graph_t* planb_graph_create(const planb_fib_t* fib, uint32_t max_batches);
+int planb_graph_launch(planb_graph_t* graph, const planb_batch_t* batches, uint32_t n_batches, void* stream);
+void planb_graph_free(planb_graph_t* graph);
+
+/*
+ * Lookup autotuner: times every compiled-in tuning (keys per lane, lookups per
+ * group, block size, the three deepest LDS depths that fit) on a device
+ * sample of addresses with HIP events on `stream` (one warm-up plus `reps`
+ * timed calls each, 0 -> 3), applies the fastest to the FIB and reports it.
+ * The fanout is a build parameter; compare fanouts by building each.
+ */
+typedef struct planb_autotune_result {
+    planb_tuning_t tuning;
+    float ms_per_call;
+    float glps;          /* sample lookups per second / 1e9 */
+    uint32_t candidates; /* tunings timed */
+} planb_autotune_result_t;
+
+int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint32_t reps, void* stream,
+                   planb_autotune_result_t* result);
+
+/*
  * Host-only halves of planb_build, usable without a GPU (tools, tests).
  *
  * planb_build_intervals -- range conversion and interval partitioning

@@ -1,0 +1,83 @@
+"""Autotuner: picks the fanout (a build parameter) and the lookup tuning.
+
+For each fanout it builds the FIB and lets the native planb_autotune time
+every compiled-in launch shape on a device-resident sample; the fastest
+(fanout, tuning) wins.  Results are cached in a JSON file keyed by a hash of
+the FIB, the key width requested and the sample's size bucket (log2), so a
+rerun on the same FIB skips the trials.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+
+from . import planb as P
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "planb", "autotune.json")
+
+
+def fib_fingerprint(prefixes, lengths, next_hops) -> str:
+    h = hashlib.sha1()
+    for a in (prefixes, lengths, next_hops):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, data):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(prefixes, lengths, next_hops, sample, n: int | None = None, fanouts=(8, 16, 32), key_bits: int = 0,
+         cache_path: str | None = DEFAULT_CACHE, reps: int = 3, log=None):
+    """Returns (fib handle with the best tuning applied, record dict)."""
+    n = sample.shape[0] if n is None else n
+    key = f"{fib_fingerprint(prefixes, lengths, next_hops)}:k{key_bits}:n{max(n, 1).bit_length()}:" \
+          f"f{','.join(map(str, fanouts))}"
+    cache = _load(cache_path) if cache_path else {}
+    rec = cache.get(key)
+    if rec:
+        h = P.planb_build(prefixes, lengths, next_hops, fanout=rec["fanout"], key_bits=key_bits)
+        t = rec["tuning"]
+        P.planb_set_tuning(h, t["keys_per_lane"], t["lds_levels"], t["lookups_per_group"], t["block_threads"])
+        return h, dict(rec, cached=True)
+    best = None
+    trials = {}
+    t0 = time.time()
+    for b in fanouts:
+        h = P.planb_build(prefixes, lengths, next_hops, fanout=b, key_bits=key_bits)
+        r = P.planb_autotune(h, sample, n, reps)
+        trials[str(b)] = round(r["glps"], 3)
+        if log:
+            log(f"autotune fanout {b}: {r}")
+        if best is None or r["glps"] > best[1]["glps"]:
+            if best is not None:
+                best[0].close()
+            best = (h, r, b)
+        else:
+            h.close()
+    h, r, b = best
+    rec = {"fanout": b, "key_bits": P.planb_get_info(h)["key_bits"],
+           "tuning": {k: r[k] for k in ("keys_per_lane", "lds_levels", "lookups_per_group", "block_threads")},
+           "glps": round(r["glps"], 3), "fanout_glps": trials, "sample": n,
+           "seconds": round(time.time() - t0, 2)}
+    if cache_path:
+        cache = _load(cache_path)
+        cache[key] = rec
+        _save(cache_path, cache)
+    return h, dict(rec, cached=False)

@@ -20,6 +20,18 @@ bool lookup_variant_exists(int B, int kpl, int R, int bs);
 // Largest dynamic LDS allocation a workgroup may request on the current device.
 int max_lds_bytes();
 
+struct DevProps {
+    int cus = 0;
+    int max_lds = 0;
+};
+
+// Compute units and LDS limit of the current device (cached per device).
+hipError_t dev_props(DevProps* p);
+
+// Resident workgroups per CU for kernel `fn` with `bs` threads and `lds`
+// bytes of dynamic LDS (cached); raises the kernel's LDS limit when needed.
+hipError_t occupancy(const void* fn, int bs, size_t lds, int* blocks);
+
 // Enqueue one plain lookup over n addresses on `stream`; out receives uint16
 // next hops, or uint32 interval indices when index_out.
 hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,

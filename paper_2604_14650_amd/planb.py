@@ -56,6 +56,15 @@ class planb_info_t(ctypes.Structure):
                 ("key_bytes", ctypes.c_uint64), ("value_bytes", ctypes.c_uint64)]
 
 
+class planb_batch_t(ctypes.Structure):
+    _fields_ = [("addrs", ctypes.c_void_p), ("out", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class planb_autotune_result_t(ctypes.Structure):
+    _fields_ = [("tuning", planb_tuning_t), ("ms_per_call", ctypes.c_float), ("glps", ctypes.c_float),
+                ("candidates", ctypes.c_uint32)]
+
+
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
 
@@ -81,6 +90,11 @@ _sig("planb_set_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_build_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz, ctypes.c_uint32, _vp, _vp, _sz)
 _sig("planb_build_keys", ctypes.c_longlong, _vp, _sz, ctypes.c_uint32, _vp, _sz, ctypes.POINTER(planb_info_t))
+_sig("planb_lookup_batches", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
+_sig("planb_graph_create", _vp, _vp, ctypes.c_uint32)
+_sig("planb_graph_launch", ctypes.c_int, _vp, _vp, ctypes.c_uint32, _vp)
+_sig("planb_graph_free", None, _vp)
+_sig("planb_autotune", ctypes.c_int, _vp, _vp, _sz, ctypes.c_uint32, _vp, ctypes.POINTER(planb_autotune_result_t))
 _sig("planb_layout", ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
      ctypes.POINTER(planb_info_t))
 
@@ -262,6 +276,71 @@ def planb_build_keys(starts, fanout: int = 16):
     keys = np.empty((need, 2), dtype=np.uint64)
     _check(_lib.planb_build_keys(s.ctypes.data, s.shape[0], fanout, keys.ctypes.data, need, None))
     return keys, _info_dict(info)
+
+
+def batch_array(batches):
+    """[(addrs_tensor_or_ptr, out_tensor_or_ptr, n), ...] -> ctypes array of planb_batch_t."""
+    arr = (planb_batch_t * max(1, len(batches)))()
+    for i, (a, o, n) in enumerate(batches):
+        arr[i].addrs = _dev_ptr(a, "addrs") if n else 0
+        arr[i].out = _dev_ptr(o, "out") if n else 0
+        arr[i].n = n
+    return arr
+
+
+def planb_lookup_batches(fib: Fib, batches_dev, n_batches_dev, max_batches: int, stream=None):
+    """batches_dev: device buffer of planb_batch_t records; n_batches_dev: device uint32."""
+    _check(_lib.planb_lookup_batches(fib, _dev_ptr(batches_dev, "batches"), _dev_ptr(n_batches_dev, "n_batches"),
+                                     max_batches, _stream_handle(stream)))
+
+
+class Graph:
+    """Owner of a planb_graph_t* (captured persistent batch lookups)."""
+
+    def __init__(self, fib: Fib, max_batches: int):
+        self.fib = fib  # keeps the FIB alive while the graph exists
+        self.max_batches = max_batches
+        self.ptr = _lib.planb_graph_create(fib, max_batches)
+        if not self.ptr:
+            raise PlanbError(planb_last_status(), planb_last_error())
+
+    def launch(self, batches, stream=None):
+        arr = batch_array(batches)
+        _check(_lib.planb_graph_launch(self.ptr, arr, len(batches), _stream_handle(stream)))
+
+    def close(self):
+        if self.ptr:
+            _lib.planb_graph_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def planb_graph_create(fib: Fib, max_batches: int) -> Graph:
+    return Graph(fib, max_batches)
+
+
+def planb_graph_launch(graph: Graph, batches, stream=None):
+    graph.launch(batches, stream)
+
+
+def planb_graph_free(graph: Graph):
+    graph.close()
+
+
+def planb_autotune(fib: Fib, sample, n: int | None = None, reps: int = 3, stream=None) -> dict:
+    if n is None:
+        n = sample.shape[0]
+    r = planb_autotune_result_t()
+    _check(_lib.planb_autotune(fib, _dev_ptr(sample, "sample"), n, reps, _stream_handle(stream), ctypes.byref(r)))
+    t = r.tuning
+    return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels, "lookups_per_group": t.lookups_per_group,
+            "block_threads": t.block_threads, "ms_per_call": r.ms_per_call, "glps": r.glps,
+            "candidates": r.candidates}
 
 
 def exported_symbols() -> list[str]:

@@ -1,0 +1,135 @@
+"""GPU parity of uneven batches in one persistent launch, of its HIP-graph
+replays, and of lookups after autotuning -- against the trie oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import planb_synth as S
+from helpers import fib_of, host_u16, oracle_trie, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2604_14650_amd import planb
+    return planb
+
+
+def _uneven(fib, sizes, seed):
+    addrs = S.zipf_traffic(fib, int(sum(sizes)), seed)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return addrs, offs
+
+
+def _batches(P, d, out, sizes, offs):
+    return [(d[offs[i]:], out[offs[i]:], int(sizes[i])) if sizes[i] else (0, 0, 0) for i in range(len(sizes))]
+
+
+@pytest.mark.parametrize("kind,seed", [("tiny", 11), ("large", 33)])
+def test_persistent_batches_device_descriptors(P, kind, seed):
+    import torch
+    fib = fib_of(kind, seed)
+    rng = np.random.default_rng(5)
+    sizes = np.concatenate([[0, 1, 63, 64, 65], S.log_uniform_sizes(rng, 60, 1, 1 << 16), [0]])
+    addrs, offs = _uneven(fib, sizes, 77)
+    want = oracle_trie(kind, seed).lookup(addrs)
+    d = to_dev(addrs)
+    out = torch.full((len(addrs),), -1, dtype=torch.int16, device="cuda")
+    for fanout in (8, 16, 32):
+        h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+        arr = P.batch_array(_batches(P, d, out, sizes, offs))
+        raw = np.frombuffer(bytes(arr), dtype=np.uint8)
+        desc = torch.from_numpy(raw.copy()).cuda()
+        for count in (len(sizes), 7):
+            say(f"batches {kind} fanout={fanout} count={count}")
+            out.fill_(-1)
+            cnt = torch.tensor([count], dtype=torch.int32, device="cuda")
+            P.planb_lookup_batches(h, desc, cnt, len(sizes))
+            got = host_u16(out, len(addrs))
+            upto = offs[count]
+            assert np.array_equal(got[:upto], want[:upto])
+            assert np.all(got[upto:] == 0xFFFF)  # batches beyond the count are untouched
+
+
+def test_graph_replays_with_changing_batches(P):
+    import torch
+    fib = fib_of("large", 33)
+    want_all = None
+    rng = np.random.default_rng(9)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=16)
+    g = P.Graph(h, 64)
+    trie = oracle_trie("large", 33)
+    for rep in range(6):
+        nb = [64, 13, 1, 0, 40, 64][rep]
+        sizes = S.log_uniform_sizes(rng, nb, 1, 1 << 15) if nb else np.zeros(0, np.int64)
+        addrs, offs = _uneven(fib, sizes, 100 + rep)
+        want = trie.lookup(addrs)
+        d = to_dev(addrs) if len(addrs) else None
+        out = torch.full((max(1, len(addrs)),), -1, dtype=torch.int16, device="cuda")
+        say(f"graph replay {rep} batches={nb} lookups={len(addrs)}")
+        g.launch(_batches(P, d, out, sizes, offs) if nb else [])
+        # eager work between replays
+        eager = torch.full((max(1, len(addrs)),), -1, dtype=torch.int16, device="cuda")
+        if len(addrs):
+            P.planb_lookup(h, d, len(addrs), eager)
+        torch.cuda.synchronize()
+        if len(addrs):
+            assert np.array_equal(host_u16(out, len(addrs)), want)
+            assert np.array_equal(host_u16(eager, len(addrs)), want)
+    g.close()
+
+
+def test_graph_ring_back_to_back(P):
+    import torch
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    g = P.Graph(h, 8)
+    trie = oracle_trie("tiny", 11)
+    outs, wants, keep = [], [], []
+    for rep in range(11):  # more replays than ring slots, no sync in between
+        sizes = np.array([1000 + rep, 7, 4096])
+        addrs, offs = _uneven(fib, sizes, 300 + rep)
+        d = to_dev(addrs)
+        out = torch.full((len(addrs),), -1, dtype=torch.int16, device="cuda")
+        g.launch(_batches(P, d, out, sizes, offs))
+        outs.append(out)
+        keep.append(d)
+        wants.append(trie.lookup(addrs))
+    torch.cuda.synchronize()
+    for out, want in zip(outs, wants):
+        assert np.array_equal(host_u16(out, len(want)), want)
+    g.close()
+
+
+def test_graph_rejects_too_many_batches(P):
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    g = P.Graph(h, 2)
+    with pytest.raises(P.PlanbError) as e:
+        g.launch([(0, 0, 0)] * 3)
+    assert e.value.code == P.PLANB_ERANGE
+    g.close()
+
+
+def test_autotune_keeps_results_exact(P, tmp_path):
+    import torch
+    from paper_2604_14650_amd import autotune
+    fib = fib_of("backbone", 22)
+    addrs = S.backbone_traffic(fib, 1 << 20, seed=4040)
+    want = oracle_trie("backbone", 22).lookup(addrs)
+    d = to_dev(addrs)
+    cache = str(tmp_path / "tune.json")
+    h, rec = autotune.tune(fib.prefixes, fib.lengths, fib.next_hops, d, cache_path=cache, reps=1)
+    assert not rec["cached"] and rec["fanout"] in (8, 16, 32) and rec["glps"] > 0
+    out = torch.empty(len(addrs), dtype=torch.int16, device="cuda")
+    P.planb_lookup(h, d, len(addrs), out)
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    assert P.planb_get_tuning(h) == rec["tuning"]
+    h2, rec2 = autotune.tune(fib.prefixes, fib.lengths, fib.next_hops, d, cache_path=cache)
+    assert rec2["cached"] and rec2["fanout"] == rec["fanout"]
+    P.planb_lookup(h2, d, len(addrs), out)
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    assert json.load(open(cache))
