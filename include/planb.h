@@ -242,6 +242,72 @@ int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint3
                    planb_autotune_result_t* result);
 
 /*
+ * Learned position model (an addition to the paper's method).  A
+ * 16 -> 64 -> 64 -> 1 ReLU MLP reads the 16 address bytes (most significant
+ * first) as byte/256 and predicts y ~ (interval index + 1/2) / m; W1, W2 and
+ * w3 are bfloat16, biases float32, products run on MFMA with float32
+ * accumulation.  Predicted position p = clamp(floor(y * m), 0, m - 1).  The
+ * error table splits [0, m) into equal segments by p and stores, per segment,
+ * the largest |p - i| over the first and last address of every interval and
+ * two addresses drawn uniformly inside it (4m seeded points, evaluated by the
+ * same inference kernel); training uses the same kind of points.  A learned
+ * lookup searches [p - w, p + w] of the leaf keys with w = eps + eps/2 + 16,
+ * accepts the result only if key[lo] <= x and (hi = m - 1 or key[hi + 1] > x),
+ * and otherwise runs the tree descent, so results are always those of
+ * planb_lookup.
+ */
+typedef struct planb_train_cfg {
+    uint32_t epochs;   /* passes over the 4m sample points (0 -> about 3000 steps in all) */
+    uint32_t batch;    /* points per Adam step, a multiple of 16 (0 -> 4m/32, within 64..4096) */
+    float lr;          /* peak Adam step size, cosine-decayed (0 -> 3e-3) */
+    uint32_t segments; /* error-table segments (0 -> 4096); capped at m/64 */
+    uint64_t seed;     /* initialisation and sample order */
+} planb_train_cfg_t;
+
+typedef struct planb_train_report {
+    float final_loss;        /* mean squared error over the 4m points */
+    uint32_t steps;          /* Adam steps taken */
+    float seconds;           /* wall time of planb_train */
+    uint32_t max_eps;        /* largest error bound over non-empty segments */
+    float mean_eps;          /* mean error bound over non-empty segments */
+    uint32_t empty_segments; /* segments no point predicts into (always fall back) */
+} planb_train_report_t;
+
+/* Trains the FIB's model from scratch with the hand-written kernels (forward,
+ * backward and Adam; per-workgroup gradient partials reduced in a fixed
+ * order, so a seed gives the same model every run), then builds the error
+ * table.  Synchronises `stream`.  report may be NULL. */
+int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg, void* stream, planb_train_report_t* report);
+
+/* Exact lookup through the model (see above); fallback_count (device uint32,
+ * may be NULL) is incremented by the number of addresses that fell back to the
+ * tree -- the caller zeroes it.  PLANB_EINVAL if the FIB has no trained model. */
+int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
+                         uint32_t* fallback_count, void* stream);
+
+/* Model access (tests, checkpoints).  The flat parameter vector holds W1
+ * (64 x 16, row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1):
+ * planb_model_num_params() floats.  set_params creates the model if needed,
+ * resets the Adam state and leaves every segment "empty" (always fall back)
+ * until planb_model_build_eps or planb_model_set_eps. */
+int planb_model_num_params(void);
+int planb_model_set_params(planb_fib_t* fib, const float* params, uint32_t segments);
+int planb_model_get_params(const planb_fib_t* fib, float* params);
+/* y (device, n floats): raw model output for each address. */
+int planb_model_predict(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, float* y, void* stream);
+/* grad (device, num_params floats): gradient of mean((y - t)^2) over the n
+ * device samples/targets at the current weights (no update). */
+int planb_model_grad(planb_fib_t* fib, const planb_addr_t* samples, const float* targets, size_t n, float* grad,
+                     void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with a
+ * device gradient on the float32 master weights; refreshes the bf16 copy. */
+int planb_model_adam(planb_fib_t* fib, const float* grad, float lr, void* stream);
+int planb_model_build_eps(planb_fib_t* fib, void* stream);
+/* Error table to / from host memory; 0xFFFFFFFF marks an empty segment. */
+int planb_model_get_eps(const planb_fib_t* fib, uint32_t* eps, uint32_t cap);
+int planb_model_set_eps(planb_fib_t* fib, const uint32_t* eps, uint32_t n);
+
+/*
  * Host-only halves of planb_build, usable without a GPU (tools, tests).
  *
  * planb_build_intervals -- range conversion and interval partitioning

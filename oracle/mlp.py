@@ -18,7 +18,8 @@ same rounding points here (the arithmetic in between is float64), so the two
 sides differ only by float32 accumulation order and the rare bfloat16 rounding
 decision that this order flips.
 
-Loss: mean squared error between y and the target position fraction i / m.
+Loss: mean squared error between y and a target; training uses the middle of
+the target interval's slot, (i + 1/2) / m, so that floor(y * m) = i.
 Optimiser: Adam (Kingma & Ba, 2015) on float32 master weights.
 """
 from __future__ import annotations

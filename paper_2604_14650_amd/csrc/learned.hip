@@ -1,13 +1,936 @@
-// Learned position model (filled in below).
+// Learned position model: a 16 -> 64 -> 64 -> 1 MLP on MFMA that predicts an
+// address's elementary-interval index, a per-segment error bound that turns
+// the prediction into a bounded exact search, and the hand-written training
+// kernels (forward, backward, Adam).  This is an addition to the paper's
+// method; exactness never depends on the model: every window search is
+// verified, and a failed check falls back to the tree descent of Section 3.
+//
+// Matrix layout.  Every product is v_mfma_f32_16x16x16bf16_1k on one
+// wavefront with the hidden units as rows and 16 addresses as columns
+// (A: row l%16, k = 4(l/16)+i; B: k = 4(l/16)+i, column l%16; C: row
+// 4(l/16)+i, column l%16).  Computing the transposed activations makes each
+// layer's C registers the next layer's B operand without any data movement.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
 #include "api_internal.hpp"
+#include "descent.hpp"
 
 namespace planb {
-struct LearnedModel {
-    int unused = 0;
+
+constexpr int kH = 64, kF = 16;
+constexpr int oW1 = 0, ob1 = oW1 + kH * kF, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 = ob2 + kH, ob3 = ow3 + kH;
+constexpr int kParams = ob3 + 1;  // 5313
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline uint16_t f2bf(float f)
+{
+    union {
+        float f;
+        uint32_t u;
+    } cv{f};
+    uint32_t u = cv.u;
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40);  // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+struct ModelDesc {
+    const uint16_t* wb;  // bfloat16 copy of the flat parameter vector (W1, W2, w3 are read from it)
+    const float* w;      // float32 master vector (biases are read from it)
+    const uint32_t* eps; // per-segment error bound, kEmpty = no training point predicts there
+    uint32_t segments;
 };
+
+// Per-lane MFMA A operands of the two weight matrices (40 VGPRs).
+struct MlpRegs {
+    s4 w1[4];     // W1[16mb + l%16][4g + i]
+    s4 w2[4][4];  // W2[16mb + l%16][16kb + 4g + i]
+};
+
+__device__ inline void load_regs(const uint16_t* wb, MlpRegs& R)
+{
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) R.w1[mb][i] = (short)wb[oW1 + (16 * mb + c) * kF + 4 * g + i];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) R.w2[mb][kb][i] = (short)wb[oW2 + (16 * mb + c) * kH + 16 * kb + 4 * g + i];
+}
+
+// B operand of layer 1: bytes 4g..4g+3 of the column's address, as bf16 of byte/256 (exact).
+__device__ inline s4 feature_operand(uint64_t xhi, uint64_t xlo)
+{
+    const int g = (threadIdx.x & 63) >> 4;
+    const uint64_t word = g < 2 ? xhi : xlo;
+    const int sh = (g & 1) ? 24 : 56;
+    s4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float f = (float)((word >> (sh - 8 * i)) & 0xFF) * (1.0f / 256.0f);
+        v[i] = (short)(__float_as_uint(f) >> 16);
+    }
+    return v;
+}
+
+struct Activations {
+    f4 h1[4];   // relu(layer 1), float32, C layout
+    s4 h1b[4];  // the same rounded to bf16 (layer-2 B operand)
+    f4 h2[4];   // relu(layer 2), float32, C layout
+};
+
+// Forward pass for the wavefront's 16 columns; lanes of one column must hold
+// the same address.  Returns y for column l%16 (in all four lanes of it).
+__device__ inline float mlp_forward(const MlpRegs& R, const float* sb1, const float* sb2, const float* sw3, float b3,
+                                    uint64_t xhi, uint64_t xlo, Activations& A)
+{
+    const int g = (threadIdx.x & 63) >> 4;
+    const s4 xb = feature_operand(xhi, xlo);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+        z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[mb], xb, z, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float v = fmaxf(z[i] + sb1[16 * mb + 4 * g + i], 0.f);
+            A.h1[mb][i] = v;
+            A.h1b[mb][i] = (short)f2bf(v);
+        }
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w2[mb][kb], A.h1b[kb], z, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int u = 16 * mb + 4 * g + i;
+            const float v = fmaxf(z[i] + sb2[u], 0.f);
+            A.h2[mb][i] = v;
+            part = fmaf(sw3[u], v, part);
+        }
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    return part + b3;
+}
+
+// Stage biases and w3 (as float) in LDS.
+__device__ inline void stage_small(const ModelDesc& M, float* sb1, float* sb2, float* sw3)
+{
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        sb1[i] = M.w[ob1 + i];
+        sb2[i] = M.w[ob2 + i];
+        sw3[i] = bf2f(M.wb[ow3 + i]);
+    }
+}
+
+__device__ inline uint64_t predict_position(float y, uint64_t m)
+{
+    const float pm = y * (float)m;
+    if (!(pm >= 1.0f)) return 0;  // negative, tiny or NaN
+    if (pm >= (float)m) return m - 1;
+    const uint64_t p = (uint64_t)floorf(pm);
+    return p < m ? p : m - 1;
+}
+
+// Key i of the dense interval order, read from the leaf level of the tree.
+template <int B, bool WIDE>
+__device__ inline typename KeyFmt<WIDE>::T leaf_key(const TreeDesc& t, uint64_t i)
+{
+    const auto* keys = static_cast<const typename KeyFmt<WIDE>::T*>(t.keys);
+    return keys[(size_t)(t.off[t.depth - 1] + i / (B - 1)) * B + i % (B - 1)];
+}
+
+// Plain one-lane descent (every key of each node), used for fallbacks.
+template <int B, bool WIDE>
+__device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_t xlo)
+{
+    using KF = KeyFmt<WIDE>;
+    const auto* keys = static_cast<const typename KF::T*>(t.keys);
+    uint32_t q = 0;
+    for (uint32_t l = 0; l + 1 < t.depth; ++l) {
+        const size_t nb = (size_t)(t.off[l] + q) * B;
+        uint32_t c = 0;
+#pragma unroll
+        for (int s = 0; s < B; ++s) c += KF::le(keys[nb + s], xhi, xlo);
+        q = min(q * B + c, t.last[l + 1]);
+    }
+    const size_t nb = (size_t)(t.off[t.depth - 1] + q) * B;
+    uint32_t c = 0;
+#pragma unroll
+    for (int s = 0; s < B; ++s) c += KF::le(keys[nb + s], xhi, xlo);
+    const uint64_t idx = (uint64_t)q * (B - 1) + c - 1;
+    return idx < t.m_minus_1 ? idx : t.m_minus_1;
+}
+
+constexpr int kLearnBlock = 256;
+
+// Learned lookup: 64 addresses per wavefront step (4 MFMA tiles of 16), then
+// one lane per address for the window search, verification and fallback.
+template <int B, bool WIDE>
+__global__ void __launch_bounds__(kLearnBlock)
+learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out,
+               uint32_t* __restrict__ fallbacks)
+{
+    using KF = KeyFmt<WIDE>;
+    __shared__ float sb1[kH], sb2[kH], sw3[kH];
+    stage_small(M, sb1, sb2, sw3);
+    __syncthreads();
+    MlpRegs R;
+    load_regs(M.wb, R);
+    const float b3 = M.w[ob3];
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const uint64_t m = t.m_minus_1 + 1;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
+    for (uint64_t base = wave * 64; base < n; base += nwaves * 64) {
+        float y = 0.f;
+        uint64_t xhi = 0, xlo = 0;
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+            const uint64_t i = base + 16 * tile + c;
+            const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
+            Activations A;
+            const float yt = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
+            if (g == tile) {
+                y = yt;
+                xhi = a.x;
+                xlo = a.y;
+            }
+        }
+        // this lane's address is base + 16g + c = base + l
+        const uint64_t p = predict_position(y, m);
+        const uint32_t seg = (uint32_t)(p * M.segments / m);
+        const uint32_t e0 = M.eps[seg];
+        bool ok = e0 != kEmpty;
+        // widen the bound by half plus 16: interior addresses can err a little
+        // more than the sampled points; each doubling costs one probe
+        const uint64_t e = ok ? (uint64_t)e0 + (e0 >> 1) + 16 : 0;
+        uint64_t j = 0;
+        if (ok) {
+            uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
+            ok = KF::le(leaf_key<B, WIDE>(t, lo), xhi, xlo) &&
+                 (hi == m - 1 || !KF::le(leaf_key<B, WIDE>(t, hi + 1), xhi, xlo));
+            if (ok) {  // last index in [lo, hi] whose key is <= x
+                while (lo < hi) {
+                    const uint64_t mid = (lo + hi + 1) >> 1;
+                    if (KF::le(leaf_key<B, WIDE>(t, mid), xhi, xlo)) lo = mid; else hi = mid - 1;
+                }
+                j = lo;
+            }
+        }
+        const uint64_t i = base + l;
+        const bool need = !ok && i < n;
+        if (need) j = descend_lane<B, WIDE>(t, xhi, xlo);
+        if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
+        if (fallbacks) {
+            const uint64_t mask = __ballot(need);
+            if (l == 0 && mask) atomicAdd(fallbacks, (uint32_t)__popcll(mask));
+        }
+    }
+}
+
+// Raw model output y for n addresses.
+__global__ void __launch_bounds__(kLearnBlock)
+predict_kernel(ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, float* __restrict__ y)
+{
+    __shared__ float sb1[kH], sb2[kH], sw3[kH];
+    stage_small(M, sb1, sb2, sw3);
+    __syncthreads();
+    MlpRegs R;
+    load_regs(M.wb, R);
+    const float b3 = M.w[ob3];
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
+    for (uint64_t base = wave * 16; base < n; base += nwaves * 16) {
+        const uint64_t i = base + c;
+        const u64x2 a = addrs[i < n ? i : n - 1];
+        Activations A;
+        const float yt = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
+        if (g == 0 && i < n) y[i] = yt;
+    }
+}
+
+// eps_acc[seg] = max over points of (|p - idx| + 1); 0 = no point.
+__global__ void eps_accumulate_kernel(const float* __restrict__ y, const uint32_t* __restrict__ idx, uint64_t npts,
+                                      uint64_t m, uint32_t segments, uint32_t* __restrict__ eps_acc)
+{
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = predict_position(y[k], m);
+        const uint64_t want = idx[k];
+        const uint64_t err = p > want ? p - want : want - p;
+        const uint32_t seg = (uint32_t)(p * segments / m);
+        atomicMax(eps_acc + seg, (uint32_t)min(err + 1, (uint64_t)0xFFFFFFFEu));
+    }
+}
+
+__global__ void eps_finalize_kernel(uint32_t* eps, uint32_t segments)
+{
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < segments; s += gridDim.x * blockDim.x)
+        eps[s] = eps[s] == 0 ? kEmpty : eps[s] - 1;
+}
+
+// ---------------------------------------------------------------- training
+constexpr int kTrainWaves = 4;
+
+struct TrainArgs {
+    const u64x2* samples;
+    const float* targets;
+    const uint32_t* order;  // sample k of the batch is samples[order[first + k]] (NULL: first + k)
+    uint64_t first;
+    uint32_t count;         // batch size N
+    float* partials;        // [gridDim.x][kParams]
+};
+
+// Gradient of mean((y - t)^2) over one batch; each workgroup writes the sum
+// of its tiles' contributions to its own row of `partials` (fixed order, no
+// floating-point atomics), reduced by adam_kernel.
+__global__ void __launch_bounds__(64 * kTrainWaves)
+grad_kernel(ModelDesc M, TrainArgs T)
+{
+    __shared__ float sb1[kH], sb2[kH], sw3[kH];
+    __shared__ uint16_t sD2[kTrainWaves][kH][16], sD1[kTrainWaves][kH][16], sH1[kTrainWaves][kH][16];
+    __shared__ uint16_t sXt[kTrainWaves][kF][16];
+    __shared__ float red[kH * kH];
+    stage_small(M, sb1, sb2, sw3);
+    __syncthreads();
+    MlpRegs R;
+    load_regs(M.wb, R);
+    s4 w2t[4][4];  // A operand of W2^T: W2[16kb + 4g + i][16mb + l%16]
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w2t[mb][kb][i] = (short)M.wb[oW2 + (16 * kb + 4 * g + i) * kH + 16 * mb + c];
+    const float b3 = M.w[ob3];
+    const float inv_n = 2.0f / (float)T.count;
+
+    f4 gW2[4][4], gW1[4];
+    float gb1[16], gb2[16], gw3[16], gb3 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW1[a] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW2[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gb1[k] = gb2[k] = gw3[k] = 0.f;
+
+    const uint32_t tiles = (T.count + 15) / 16;
+    for (uint32_t tile = blockIdx.x * kTrainWaves + w; tile < tiles; tile += gridDim.x * kTrainWaves) {
+        const uint32_t k = tile * 16 + c;
+        const bool valid = k < T.count;
+        const uint64_t src = T.first + (valid ? k : 0);
+        const uint64_t sidx = T.order ? T.order[src] : src;
+        const u64x2 a = T.samples[sidx];
+        const float target = T.targets[sidx];
+        Activations A;
+        const float y = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
+        const float dy = valid ? (y - target) * inv_n : 0.f;
+        // feature matrix, transposed: sXt[f][column]
+        const s4 xb = feature_operand(a.x, a.y);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sXt[w][4 * g + i][c] = (uint16_t)xb[i];
+        s4 d2b[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 4 * mb + i, u = 16 * mb + 4 * g + i;
+                const float h2 = A.h2[mb][i];
+                const float d2 = h2 > 0.f ? sw3[u] * dy : 0.f;
+                gb2[r] += d2;
+                gw3[r] = fmaf(h2, dy, gw3[r]);
+                const uint16_t q = f2bf(d2);
+                d2b[mb][i] = (short)q;
+                sD2[w][u][c] = q;
+                sH1[w][u][c] = (uint16_t)A.h1b[mb][i];
+            }
+        }
+        if (g == 0) gb3 += dy;
+        // dH1^T = W2^T dZ2^T, masked by the layer-1 ReLU
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2t[mb][kb], d2b[kb], z, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * mb + 4 * g + i;
+                const float d1 = A.h1[mb][i] > 0.f ? z[i] : 0.f;
+                gb1[4 * mb + i] += d1;
+                sD1[w][u][c] = f2bf(d1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // dW2 += dZ2^T H1 (K = the 16 samples), dW1 += dZ1^T X
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            s4 a2, a1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a2[i] = (short)sD2[w][16 * mb + c][4 * g + i];
+                a1[i] = (short)sD1[w][16 * mb + c][4 * g + i];
+            }
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                s4 bh;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bh[i] = (short)sH1[w][16 * nb + c][4 * g + i];
+                gW2[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, bh, gW2[mb][nb], 0, 0, 0);
+            }
+            s4 bx;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bx[i] = (short)sXt[w][c][4 * g + i];
+            gW1[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, bx, gW1[mb], 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // per-unit vectors: sum over the 16 columns of each row group
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            gb1[r] += __shfl_xor(gb1[r], o, 64);
+            gb2[r] += __shfl_xor(gb2[r], o, 64);
+            gw3[r] += __shfl_xor(gw3[r], o, 64);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) gb3 += __shfl_xor(gb3, o, 64);
+
+    // combine the waves in a fixed order, one parameter block at a time
+    float* dst = T.partials + (size_t)blockIdx.x * kParams;
+    // W2 (64 x 64)
+    for (int ww = 0; ww < kTrainWaves; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int idx = (16 * mb + 4 * g + i) * kH + 16 * nb + c;
+                        red[idx] = (ww == 0 ? 0.f : red[idx]) + gW2[mb][nb][i];
+                    }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) dst[oW2 + i] = red[i];
+    __syncthreads();
+    // W1 (64 x 16), b1, b2, w3, b3 packed into red[]
+    for (int ww = 0; ww < kTrainWaves; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int idx = (16 * mb + 4 * g + i) * kF + c;
+                    red[idx] = (ww == 0 ? 0.f : red[idx]) + gW1[mb][i];
+                }
+            if (c == 0) {
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int u = 16 * mb + 4 * g + i, r = 4 * mb + i;
+                        red[1024 + u] = (ww == 0 ? 0.f : red[1024 + u]) + gb1[r];
+                        red[1088 + u] = (ww == 0 ? 0.f : red[1088 + u]) + gb2[r];
+                        red[1152 + u] = (ww == 0 ? 0.f : red[1152 + u]) + gw3[r];
+                    }
+            }
+            if (l == 0) red[1216] = (ww == 0 ? 0.f : red[1216]) + gb3;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < kH * kF; i += blockDim.x) dst[oW1 + i] = red[i];
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        dst[ob1 + i] = red[1024 + i];
+        dst[ob2 + i] = red[1088 + i];
+        dst[ow3 + i] = red[1152 + i];
+    }
+    if (threadIdx.x == 0) dst[ob3] = red[1216];
+}
+
+// Sum the workgroup partials in order; optionally apply one Adam step to the
+// float32 master weights and refresh the bfloat16 copy.
+__global__ void adam_kernel(const float* __restrict__ partials, uint32_t nparts, float* __restrict__ grad_out,
+                            float* __restrict__ w, float* __restrict__ m1, float* __restrict__ m2,
+                            uint16_t* __restrict__ wb, int apply, float lr, float beta1, float beta2, float eps,
+                            float corr1, float corr2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kParams) return;
+    float gsum = 0.f;
+    for (uint32_t k = 0; k < nparts; ++k) gsum += partials[(size_t)k * kParams + p];
+    if (grad_out) grad_out[p] = gsum;
+    if (!apply) return;
+    const float a = beta1 * m1[p] + (1.f - beta1) * gsum;
+    const float b = beta2 * m2[p] + (1.f - beta2) * gsum * gsum;
+    m1[p] = a;
+    m2[p] = b;
+    const float upd = (a / corr1) / (sqrtf(b / corr2) + eps);
+    const float nw = w[p] - lr * upd;
+    w[p] = nw;
+    wb[p] = f2bf(nw);
+}
+
+// ------------------------------------------------------------- host side
+struct LearnedModel {
+    float* w = nullptr;      // master weights
+    float* m1 = nullptr;     // Adam first moment
+    float* m2 = nullptr;     // Adam second moment
+    uint16_t* wb = nullptr;  // bf16 copy
+    uint32_t* eps = nullptr;
+    uint32_t segments = 0;
+    float* partials = nullptr;
+    uint32_t max_parts = 256;
+    uint64_t adam_steps = 0;
+    bool has_eps = false;
+};
+
+namespace {
+
+template <int B, bool W>
+struct LearnedKernel {
+    static void* get() { return reinterpret_cast<void*>(learned_kernel<B, W>); }
+};
+
+void* pick_learned(int B, bool wide)
+{
+    switch (B) {
+    case 8: return wide ? LearnedKernel<8, true>::get() : LearnedKernel<8, false>::get();
+    case 16: return wide ? LearnedKernel<16, true>::get() : LearnedKernel<16, false>::get();
+    case 32: return wide ? LearnedKernel<32, true>::get() : LearnedKernel<32, false>::get();
+    default: return nullptr;
+    }
+}
+
+ModelDesc model_desc(const LearnedModel* L)
+{
+    return ModelDesc{L->wb, L->w, L->eps, L->segments};
+}
+
+int ensure_model(planb_fib_t* f, uint32_t segments)
+{
+    if (segments == 0) segments = 4096;
+    LearnedModel* L = f->learned;
+    if (L && L->segments != segments) {
+        release_learned(f);
+        L = nullptr;
+    }
+    if (L) return PLANB_OK;
+    L = new (std::nothrow) LearnedModel();
+    if (!L) return fail(PLANB_ENOMEM, "out of host memory");
+    f->learned = L;
+    L->segments = segments;
+    hipError_t e;
+    if ((e = hipMalloc(&L->w, kParams * 4)) != hipSuccess || (e = hipMalloc(&L->m1, kParams * 4)) != hipSuccess ||
+        (e = hipMalloc(&L->m2, kParams * 4)) != hipSuccess || (e = hipMalloc(&L->wb, kParams * 2)) != hipSuccess ||
+        (e = hipMalloc(&L->eps, (size_t)segments * 4)) != hipSuccess ||
+        (e = hipMalloc(&L->partials, (size_t)L->max_parts * kParams * 4)) != hipSuccess) {
+        release_learned(f);
+        return fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return PLANB_OK;
+}
+
+int upload_params(LearnedModel* L, const float* host)
+{
+    std::vector<uint16_t> b(kParams);
+    for (int i = 0; i < kParams; ++i) b[i] = f2bf(host[i]);
+    hipError_t e;
+    if ((e = hipMemcpy(L->w, host, kParams * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->wb, b.data(), kParams * 2, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(L->m1, 0, kParams * 4)) != hipSuccess || (e = hipMemset(L->m2, 0, kParams * 4)) != hipSuccess ||
+        (e = hipMemset(L->eps, 0xFF, (size_t)L->segments * 4)) != hipSuccess)
+        return fail_hip(e, "uploading model parameters");
+    L->adam_steps = 0;
+    L->has_eps = false;
+    return PLANB_OK;
+}
+
+// Seeded initialisation: W ~ U(-1/sqrt(fan_in), +1/sqrt(fan_in)), biases 0,
+// b3 = 0.5 (the middle of the position range).
+std::vector<float> init_params(uint64_t seed)
+{
+    std::mt19937_64 rng(seed);
+    std::vector<float> p(kParams, 0.f);
+    auto fill = [&](int off, int count, float bound) {
+        std::uniform_real_distribution<float> d(-bound, bound);
+        for (int i = 0; i < count; ++i) p[off + i] = d(rng);
+    };
+    fill(oW1, kH * kF, 1.0f / std::sqrt((float)kF));
+    fill(oW2, kH * kH, 1.0f / std::sqrt((float)kH));
+    fill(ow3, kH, 1.0f / std::sqrt((float)kH));
+    p[ob3] = 0.5f;
+    return p;
+}
+
+// Training / error-table points: for every interval its first and last
+// address and kInterior addresses drawn uniformly inside it (seeded), each
+// labelled with the interval index.  The interior draws give the low address
+// bytes the same spread that lookup traffic has, so the model learns that
+// they do not move the position.
+constexpr int kPointsPerInterval = 4;
+
+void boundary_points(const Intervals& iv, uint64_t seed, std::vector<U128>* pts, std::vector<uint32_t>* idx)
+{
+    using u128 = unsigned __int128;
+    const size_t m = iv.starts.size();
+    pts->resize(kPointsPerInterval * m);
+    idx->resize(kPointsPerInterval * m);
+    std::mt19937_64 rng(seed * 0x2545F4914F6CDD1Dull + 0x6A09E667F3BCC909ull);
+    auto to_u = [](U128 v) { return ((u128)v.hi << 64) | v.lo; };
+    auto from_u = [](u128 v) { return U128{(uint64_t)(v >> 64), (uint64_t)v}; };
+    for (size_t i = 0; i < m; ++i) {
+        const u128 s = to_u(iv.starts[i]);
+        const u128 last = i + 1 < m ? to_u(iv.starts[i + 1]) - 1 : ~(u128)0;
+        const u128 span = last - s;  // size - 1
+        U128* out = pts->data() + kPointsPerInterval * i;
+        out[0] = from_u(s);
+        out[1] = from_u(last);
+        for (int k = 2; k < kPointsPerInterval; ++k) {
+            const u128 r = ((u128)rng() << 64) | rng();
+            out[k] = from_u(span == ~(u128)0 ? r : s + r % (span + 1));
+        }
+        for (int k = 0; k < kPointsPerInterval; ++k) (*idx)[kPointsPerInterval * i + k] = (uint32_t)i;
+    }
+}
+
+// Segments actually used for m intervals: at most the requested count and at
+// least 64 positions per segment (narrower segments see too few points).
+uint32_t effective_segments(uint32_t requested, uint64_t m)
+{
+    const uint64_t cap = std::max<uint64_t>(1, m / 64);
+    return (uint32_t)std::min<uint64_t>(requested ? requested : 4096, cap);
+}
+
+int launch_grad(const LearnedModel* L, const TrainArgs& base, uint32_t* parts_used, hipStream_t st)
+{
+    const uint32_t tiles = (base.count + 15) / 16;
+    uint32_t grid = (tiles + kTrainWaves - 1) / kTrainWaves;
+    grid = std::max(1u, std::min(grid, L->max_parts));
+    TrainArgs T = base;
+    T.partials = L->partials;
+    hipLaunchKernelGGL(grad_kernel, dim3(grid), dim3(64 * kTrainWaves), 0, st, model_desc(L), T);
+    *parts_used = grid;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "gradient launch");
+}
+
+int launch_adam(LearnedModel* L, uint32_t parts, float* grad_out, bool apply, float lr, hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.f, c2 = 1.f;
+    if (apply) {
+        ++L->adam_steps;
+        c1 = 1.f - (float)std::pow(0.9, (double)L->adam_steps);
+        c2 = 1.f - (float)std::pow(0.999, (double)L->adam_steps);
+    }
+    hipLaunchKernelGGL(adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, st, L->partials, parts, grad_out, L->w,
+                       L->m1, L->m2, L->wb, apply ? 1 : 0, lr, b1, b2, 1e-8f, c1, c2);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "adam launch");
+}
+
+int build_eps(planb_fib_t* f, const u64x2* d_pts, const uint32_t* d_idx, uint64_t npts, float* d_y, hipStream_t st)
+{
+    LearnedModel* L = f->learned;
+    const uint64_t m = f->iv.starts.size();
+    hipLaunchKernelGGL(predict_kernel, dim3((unsigned)std::min<uint64_t>((npts + 63) / 64, 4096)), dim3(kLearnBlock), 0,
+                       st, model_desc(L), d_pts, npts, d_y);
+    hipError_t e = hipMemsetAsync(L->eps, 0, (size_t)L->segments * 4, st);
+    if (e != hipSuccess) return fail_hip(e, "clearing the epsilon table");
+    hipLaunchKernelGGL(eps_accumulate_kernel, dim3((unsigned)std::min<uint64_t>((npts + 255) / 256, 4096)), dim3(256), 0,
+                       st, d_y, d_idx, npts, m, L->segments, L->eps);
+    hipLaunchKernelGGL(eps_finalize_kernel, dim3((L->segments + 255) / 256), dim3(256), 0, st, L->eps, L->segments);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "epsilon table launch");
+    L->has_eps = true;
+    return PLANB_OK;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
+};
+
+}  // namespace
+
 void release_learned(planb_fib_t* f)
 {
-    delete f->learned;
+    LearnedModel* L = f->learned;
+    if (!L) return;
+    for (void* p : {(void*)L->w, (void*)L->m1, (void*)L->m2, (void*)L->wb, (void*)L->eps, (void*)L->partials})
+        if (p) (void)hipFree(p);
+    delete L;
     f->learned = nullptr;
 }
+
 }  // namespace planb
+
+using namespace planb;
+
+extern "C" {
+
+int planb_model_set_params(planb_fib_t* fib, const float* params, uint32_t segments)
+{
+    if (!fib || !params) return fail(PLANB_EINVAL, "NULL argument");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK || (rc = ensure_model(fib, segments ? segments : 4096)) != PLANB_OK) return rc;
+    return upload_params(fib->learned, params);
+}
+
+int planb_model_get_params(const planb_fib_t* fib, float* params)
+{
+    if (!fib || !params) return fail(PLANB_EINVAL, "NULL argument");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    hipError_t e = hipMemcpy(params, fib->learned->w, kParams * 4, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "reading parameters");
+}
+
+int planb_model_num_params(void) { return kParams; }
+
+int planb_model_predict(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, float* y, void* stream)
+{
+    if (!fib || (n && (!addrs || !y))) return fail(PLANB_EINVAL, "NULL argument");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    if (n == 0) return PLANB_OK;
+    if (reinterpret_cast<uintptr_t>(addrs) % 16 || reinterpret_cast<uintptr_t>(y) % 4)
+        return fail(PLANB_EINVAL, "misaligned pointer");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    hipLaunchKernelGGL(predict_kernel, dim3((unsigned)std::min<uint64_t>((n + 63) / 64, 8192)), dim3(kLearnBlock), 0,
+                       static_cast<hipStream_t>(stream), model_desc(fib->learned),
+                       reinterpret_cast<const u64x2*>(addrs), (uint64_t)n, y);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "predict launch");
+}
+
+int planb_model_grad(planb_fib_t* fib, const planb_addr_t* samples, const float* targets, size_t n, float* grad,
+                     void* stream)
+{
+    if (!fib || !samples || !targets || !grad || n == 0) return fail(PLANB_EINVAL, "bad argument");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    if (n >= (1ull << 31)) return fail(PLANB_ERANGE, "too many samples");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    TrainArgs T{reinterpret_cast<const u64x2*>(samples), targets, nullptr, 0, (uint32_t)n, nullptr};
+    uint32_t parts = 0;
+    if ((rc = launch_grad(fib->learned, T, &parts, static_cast<hipStream_t>(stream))) != PLANB_OK) return rc;
+    return launch_adam(fib->learned, parts, grad, false, 0.f, static_cast<hipStream_t>(stream));
+}
+
+int planb_model_adam(planb_fib_t* fib, const float* grad, float lr, void* stream)
+{
+    if (!fib || !grad) return fail(PLANB_EINVAL, "NULL argument");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(fib->learned->partials, grad, kParams * 4, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "copying the gradient");
+    return launch_adam(fib->learned, 1, nullptr, true, lr, st);
+}
+
+int planb_model_build_eps(planb_fib_t* fib, void* stream)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    std::vector<U128> pts;
+    std::vector<uint32_t> idx;
+    boundary_points(fib->iv, 1, &pts, &idx);
+    DevBuf dp, di, dy;
+    hipError_t e;
+    if ((e = dp.alloc(pts.size() * 16)) != hipSuccess || (e = di.alloc(idx.size() * 4)) != hipSuccess ||
+        (e = dy.alloc(idx.size() * 4)) != hipSuccess)
+        return fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((e = hipMemcpyAsync(dp.p, pts.data(), pts.size() * 16, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(di.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail_hip(e, "uploading boundary points");
+    rc = build_eps(fib, static_cast<const u64x2*>(dp.p), static_cast<const uint32_t*>(di.p), pts.size(),
+                   static_cast<float*>(dy.p), st);
+    if (rc != PLANB_OK) return rc;
+    e = hipStreamSynchronize(st);
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "epsilon table");
+}
+
+int planb_model_get_eps(const planb_fib_t* fib, uint32_t* eps, uint32_t cap)
+{
+    if (!fib || !eps) return fail(PLANB_EINVAL, "NULL argument");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    const uint32_t n = std::min(cap, fib->learned->segments);
+    hipError_t e = hipMemcpy(eps, fib->learned->eps, (size_t)n * 4, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? (int)n : fail_hip(e, "reading the epsilon table");
+}
+
+int planb_model_set_eps(planb_fib_t* fib, const uint32_t* eps, uint32_t n)
+{
+    if (!fib || !eps) return fail(PLANB_EINVAL, "NULL argument");
+    if (!fib->learned) return fail(PLANB_EINVAL, "the FIB has no model");
+    if (n != fib->learned->segments) return fail(PLANB_EINVAL, "segment count differs from the model's");
+    hipError_t e = hipMemcpy(fib->learned->eps, eps, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "writing the epsilon table");
+    fib->learned->has_eps = true;
+    return PLANB_OK;
+}
+
+int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg_in, void* stream, planb_train_report_t* report)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    planb_train_cfg_t cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    const uint64_t npts_all = kPointsPerInterval * (uint64_t)fib->iv.starts.size();
+    if (cfg.batch == 0)  // about 32 steps per epoch, 64..4096 points per step
+        cfg.batch = (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(64, npts_all / 32 / 16 * 16));
+    if (cfg.epochs == 0) {  // about 3000 Adam steps in all
+        const uint64_t per_epoch = (npts_all + cfg.batch - 1) / cfg.batch;
+        cfg.epochs = (uint32_t)std::min<uint64_t>(400, std::max<uint64_t>(8, (3000 + per_epoch - 1) / per_epoch));
+    }
+    if (cfg.lr <= 0.f) cfg.lr = 3e-3f;
+    cfg.segments = effective_segments(cfg.segments, fib->iv.starts.size());
+    if (cfg.batch % 16) return fail(PLANB_EINVAL, "batch must be a multiple of 16");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK || (rc = ensure_model(fib, cfg.segments)) != PLANB_OK) return rc;
+    LearnedModel* L = fib->learned;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<float> p0 = init_params(cfg.seed);
+    if ((rc = upload_params(L, p0.data())) != PLANB_OK) return rc;
+    std::vector<U128> pts;
+    std::vector<uint32_t> idx;
+    boundary_points(fib->iv, cfg.seed, &pts, &idx);
+    const uint64_t npts = pts.size(), m = fib->iv.starts.size();
+    std::vector<float> tgt(npts);
+    for (uint64_t k = 0; k < npts; ++k) tgt[k] = (float)(((double)idx[k] + 0.5) / (double)m);
+    DevBuf dp, di, dt, dord, dy;
+    hipError_t e;
+    if ((e = dp.alloc(npts * 16)) != hipSuccess || (e = di.alloc(npts * 4)) != hipSuccess ||
+        (e = dt.alloc(npts * 4)) != hipSuccess || (e = dord.alloc(npts * 4)) != hipSuccess ||
+        (e = dy.alloc(npts * 4)) != hipSuccess)
+        return fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((e = hipMemcpyAsync(dp.p, pts.data(), npts * 16, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(di.p, idx.data(), npts * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(dt.p, tgt.data(), npts * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail_hip(e, "uploading training points");
+    std::vector<uint32_t> order(npts);
+    for (uint64_t k = 0; k < npts; ++k) order[k] = (uint32_t)k;
+    std::mt19937_64 rng(cfg.seed ^ 0x9E3779B97F4A7C15ull);
+    uint32_t steps = 0;
+    for (uint32_t ep = 0; ep < cfg.epochs; ++ep) {
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(e, "training");
+        std::shuffle(order.begin(), order.end(), rng);
+        if ((e = hipMemcpyAsync(dord.p, order.data(), npts * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail_hip(e, "uploading the sample order");
+        // cosine decay of the step size over the whole run
+        for (uint64_t first = 0; first < npts; first += cfg.batch) {
+            const uint32_t cnt = (uint32_t)std::min<uint64_t>(cfg.batch, npts - first);
+            const double prog = (double)steps / std::max(1.0, (double)cfg.epochs * ((npts + cfg.batch - 1) / cfg.batch));
+            const float lr = (float)(cfg.lr * (0.02 + 0.98 * 0.5 * (1.0 + std::cos(3.141592653589793 * prog))));
+            TrainArgs T{static_cast<const u64x2*>(dp.p), static_cast<const float*>(dt.p),
+                        static_cast<const uint32_t*>(dord.p), first, cnt, nullptr};
+            uint32_t parts = 0;
+            if ((rc = launch_grad(L, T, &parts, st)) != PLANB_OK) return rc;
+            if ((rc = launch_adam(L, parts, nullptr, true, lr, st)) != PLANB_OK) return rc;
+            ++steps;
+        }
+    }
+    if ((rc = build_eps(fib, static_cast<const u64x2*>(dp.p), static_cast<const uint32_t*>(di.p), npts,
+                        static_cast<float*>(dy.p), st)) != PLANB_OK)
+        return rc;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(e, "training");
+    if (report) {
+        std::memset(report, 0, sizeof(*report));
+        std::vector<float> y(npts);
+        std::vector<uint32_t> eps(L->segments);
+        if ((e = hipMemcpy(y.data(), dy.p, npts * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+            (e = hipMemcpy(eps.data(), L->eps, (size_t)L->segments * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+            return fail_hip(e, "reading the training report");
+        double se = 0.0;
+        for (uint64_t k = 0; k < npts; ++k) se += (double)(y[k] - tgt[k]) * (double)(y[k] - tgt[k]);
+        report->final_loss = (float)(se / (double)npts);
+        report->steps = steps;
+        double sum = 0.0;
+        uint32_t used = 0;
+        for (uint32_t s = 0; s < L->segments; ++s) {
+            if (eps[s] == kEmpty) {
+                ++report->empty_segments;
+                continue;
+            }
+            report->max_eps = std::max(report->max_eps, eps[s]);
+            sum += eps[s];
+            ++used;
+        }
+        report->mean_eps = used ? (float)(sum / used) : 0.f;
+        report->seconds =
+            (float)std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return PLANB_OK;
+}
+
+int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
+                         uint32_t* fallback_count, void* stream)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (!fib->learned || !fib->learned->has_eps) return fail(PLANB_EINVAL, "the FIB has no trained model");
+    if (n == 0) return PLANB_OK;
+    if (n >= (1ull << 40)) return fail(PLANB_ERANGE, "batch too large (n must be < 2^40)");
+    if (!addrs || !out) return fail(PLANB_EINVAL, "NULL device pointer");
+    if (reinterpret_cast<uintptr_t>(addrs) % 16 || reinterpret_cast<uintptr_t>(out) % 2 ||
+        reinterpret_cast<uintptr_t>(fallback_count) % 4)
+        return fail(PLANB_EINVAL, "misaligned pointer");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    void* fn = pick_learned((int)fib->desc.fanout, fib->desc.key_bytes == 16);
+    if (!fn) return fail(PLANB_EINVAL, "no learned kernel for this fanout");
+    DevProps p;
+    hipError_t e = dev_props(&p);
+    if (e != hipSuccess) return fail_hip(e, "device properties");
+    int nb = 1;
+    if ((e = occupancy(fn, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
+    const uint64_t want = (n + (kLearnBlock / 64) * 64 - 1) / ((kLearnBlock / 64) * 64);
+    const uint64_t cap = (uint64_t)p.cus * nb;
+    const unsigned grid = (unsigned)std::min(want, cap);
+    TreeDesc t = fib->desc;
+    void* args_t = &t;
+    ModelDesc M = model_desc(fib->learned);
+    const u64x2* a = reinterpret_cast<const u64x2*>(addrs);
+    uint64_t nn = n;
+    void* args[] = {args_t, &M, &a, &nn, &out, &fallback_count};
+    e = hipLaunchKernel(fn, dim3(grid), dim3(kLearnBlock), args, 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "learned lookup launch");
+}
+
+}  // extern "C"

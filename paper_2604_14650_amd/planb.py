@@ -65,6 +65,16 @@ class planb_autotune_result_t(ctypes.Structure):
                 ("candidates", ctypes.c_uint32)]
 
 
+class planb_train_cfg_t(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("segments", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class planb_train_report_t(ctypes.Structure):
+    _fields_ = [("final_loss", ctypes.c_float), ("steps", ctypes.c_uint32), ("seconds", ctypes.c_float),
+                ("max_eps", ctypes.c_uint32), ("mean_eps", ctypes.c_float), ("empty_segments", ctypes.c_uint32)]
+
+
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
 
@@ -95,6 +105,17 @@ _sig("planb_graph_create", _vp, _vp, ctypes.c_uint32)
 _sig("planb_graph_launch", ctypes.c_int, _vp, _vp, ctypes.c_uint32, _vp)
 _sig("planb_graph_free", None, _vp)
 _sig("planb_autotune", ctypes.c_int, _vp, _vp, _sz, ctypes.c_uint32, _vp, ctypes.POINTER(planb_autotune_result_t))
+_sig("planb_train", ctypes.c_int, _vp, ctypes.POINTER(planb_train_cfg_t), _vp, ctypes.POINTER(planb_train_report_t))
+_sig("planb_lookup_learned", ctypes.c_int, _vp, _vp, _sz, _vp, _vp, _vp)
+_sig("planb_model_num_params", ctypes.c_int)
+_sig("planb_model_set_params", ctypes.c_int, _vp, _vp, ctypes.c_uint32)
+_sig("planb_model_get_params", ctypes.c_int, _vp, _vp)
+_sig("planb_model_predict", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
+_sig("planb_model_grad", ctypes.c_int, _vp, _vp, _vp, _sz, _vp, _vp)
+_sig("planb_model_adam", ctypes.c_int, _vp, _vp, ctypes.c_float, _vp)
+_sig("planb_model_build_eps", ctypes.c_int, _vp, _vp)
+_sig("planb_model_get_eps", ctypes.c_int, _vp, _vp, ctypes.c_uint32)
+_sig("planb_model_set_eps", ctypes.c_int, _vp, _vp, ctypes.c_uint32)
 _sig("planb_layout", ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
      ctypes.POINTER(planb_info_t))
 
@@ -341,6 +362,74 @@ def planb_autotune(fib: Fib, sample, n: int | None = None, reps: int = 3, stream
     return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels, "lookups_per_group": t.lookups_per_group,
             "block_threads": t.block_threads, "ms_per_call": r.ms_per_call, "glps": r.glps,
             "candidates": r.candidates}
+
+
+def planb_train(fib: Fib, epochs: int = 0, batch: int = 0, lr: float = 0.0, segments: int = 0, seed: int = 0,
+                stream=None) -> dict:
+    cfg = planb_train_cfg_t(epochs, batch, lr, segments, seed)
+    r = planb_train_report_t()
+    _check(_lib.planb_train(fib, ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in planb_train_report_t._fields_}
+
+
+def planb_lookup_learned(fib: Fib, addrs, n: int | None = None, out=None, fallback_count=None, stream=None):
+    if n is None:
+        n = addrs.shape[0]
+    fb = _dev_ptr(fallback_count, "fallback_count") if fallback_count is not None else None
+    _check(_lib.planb_lookup_learned(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), fb,
+                                     _stream_handle(stream)))
+    return out
+
+
+def planb_model_num_params() -> int:
+    return int(_lib.planb_model_num_params())
+
+
+def planb_model_set_params(fib: Fib, params, segments: int = 4096):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.shape != (planb_model_num_params(),):
+        raise ValueError("wrong parameter count")
+    _check(_lib.planb_model_set_params(fib, p.ctypes.data, segments))
+
+
+def planb_model_get_params(fib: Fib) -> np.ndarray:
+    p = np.empty(planb_model_num_params(), dtype=np.float32)
+    _check(_lib.planb_model_get_params(fib, p.ctypes.data))
+    return p
+
+
+def planb_model_predict(fib: Fib, addrs, n=None, y=None, stream=None):
+    if n is None:
+        n = addrs.shape[0]
+    _check(_lib.planb_model_predict(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(y, "y"), _stream_handle(stream)))
+    return y
+
+
+def planb_model_grad(fib: Fib, samples, targets, n=None, grad=None, stream=None):
+    if n is None:
+        n = samples.shape[0]
+    _check(_lib.planb_model_grad(fib, _dev_ptr(samples, "samples"), _dev_ptr(targets, "targets"), n,
+                                 _dev_ptr(grad, "grad"), _stream_handle(stream)))
+    return grad
+
+
+def planb_model_adam(fib: Fib, grad, lr: float, stream=None):
+    _check(_lib.planb_model_adam(fib, _dev_ptr(grad, "grad"), lr, _stream_handle(stream)))
+
+
+def planb_model_build_eps(fib: Fib, stream=None):
+    _check(_lib.planb_model_build_eps(fib, _stream_handle(stream)))
+
+
+def planb_model_get_eps(fib: Fib, segments: int) -> np.ndarray:
+    e = np.empty(segments, dtype=np.uint32)
+    got = _check(_lib.planb_model_get_eps(fib, e.ctypes.data, segments))
+    return e[:got]
+
+
+def planb_model_set_eps(fib: Fib, eps):
+    e = np.ascontiguousarray(eps, dtype=np.uint32)
+    _check(_lib.planb_model_set_eps(fib, e.ctypes.data, e.shape[0]))
 
 
 def exported_symbols() -> list[str]:

@@ -1,0 +1,253 @@
+"""Learned position model on the GPU, through the C ABI:
+
+* inference, gradient and Adam kernels against the float64 oracle
+  (oracle/mlp.py) on the same seeded parameters and samples;
+* training is deterministic and its error table bounds every boundary point;
+* learned lookups are bit-exact against the LPM oracle, also with the window
+  search forced to fail (zero or empty error bounds) and with random weights.
+"""
+import numpy as np
+import pytest
+
+import planb_synth as S
+from helpers import fib_of, host_u16, oracle_trie, say, to_dev
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2604_14650_amd import planb
+    return planb
+
+
+def seeded_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = mlp.unpack(np.zeros(mlp.N_PARAMS))
+    p["W1"] = rng.uniform(-0.25, 0.25, (64, 16)) * scale
+    p["b1"] = rng.normal(0, 0.05, 64)
+    p["W2"] = rng.uniform(-0.125, 0.125, (64, 64)) * scale
+    p["b2"] = rng.normal(0, 0.05, 64)
+    p["w3"] = rng.uniform(-0.125, 0.125, 64)
+    p["b3"] = np.array([0.5])
+    return mlp.pack(p).astype(np.float32).astype(np.float64)
+
+
+def f32_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _magnitude(vec, X):
+    """S(x) = sum_u |w3_u| sum_v |W2_uv| |h1_v| : scale of y's sensitivity to h1."""
+    p = mlp.model_weights(vec)
+    _, c = mlp.forward(vec, X)
+    return (np.abs(c["h1q"]) @ np.abs(p["W2"]).T) @ np.abs(p["w3"]) + np.abs(p["b3"][0])
+
+
+def test_predict_matches_oracle(P):
+    import torch
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    vec = seeded_params(1)
+    P.planb_model_set_params(h, vec)
+    addrs = S.tiny_traffic(fib, 1 << 14, seed=9)
+    y = torch.empty(len(addrs), dtype=torch.float32, device="cuda")
+    P.planb_model_predict(h, to_dev(addrs), len(addrs), y)
+    got = y.cpu().numpy().astype(np.float64)
+    X = mlp.features(addrs)
+    want, _ = mlp.forward(vec, X)
+    Sx = _magnitude(vec, X)
+    err = np.abs(got - want)
+    # float32 accumulation plus at most one flipped bf16 rounding per h1 element
+    assert np.all(err <= 2.0 ** -8 * Sx + 1e-6), err.max()
+    assert np.median(err / Sx) < 1e-5
+
+
+def test_gradient_matches_oracle(P):
+    import torch
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    vec = seeded_params(2)
+    P.planb_model_set_params(h, vec)
+    rng = np.random.default_rng(3)
+    n = 4096 + 9  # a ragged last tile
+    samples = S.tiny_traffic(fib, n, seed=10)
+    t = rng.random(n).astype(np.float32)
+    g = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    P.planb_model_grad(h, to_dev(samples), f32_dev(t), n, g)
+    got = g.cpu().numpy().astype(np.float64)
+    _, want = mlp.loss_and_grad(vec, mlp.features(samples), t.astype(np.float64))
+    o = 0
+    for name, shape in mlp.SHAPES:
+        k = int(np.prod(shape))
+        a, b = got[o:o + k], want[o:o + k]
+        o += k
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel < 2e-2, (name, rel)
+        if k > 1:
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            assert cos > 0.9995, (name, cos)
+
+
+def test_adam_matches_oracle(P):
+    import torch
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    vec = seeded_params(4)
+    P.planb_model_set_params(h, vec)
+    rng = np.random.default_rng(5)
+    w = vec.copy()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for step in range(1, 5):
+        grad = rng.normal(0, 1e-2, mlp.N_PARAMS).astype(np.float32)
+        P.planb_model_adam(h, f32_dev(grad), 1e-3)
+        w, m, v = mlp.adam_step(w, m, v, grad.astype(np.float64), step, 1e-3)
+    torch.cuda.synchronize()
+    got = P.planb_model_get_params(h).astype(np.float64)
+    assert np.max(np.abs(got - w)) < 2e-6
+
+
+@pytest.fixture(scope="module")
+def trained_tiny(P):
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    rep = P.planb_train(h, seed=7)
+    say(f"tiny training report {rep}")
+    return fib, h, rep
+
+
+def test_training_is_deterministic(P, trained_tiny):
+    fib, h, rep = trained_tiny
+    h2 = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    rep2 = P.planb_train(h2, seed=7)
+    assert np.array_equal(P.planb_model_get_params(h), P.planb_model_get_params(h2))
+    assert np.array_equal(P.planb_model_get_eps(h, 4096), P.planb_model_get_eps(h2, 4096))
+    assert rep["final_loss"] == rep2["final_loss"]
+
+
+def test_training_reduces_loss(P, trained_tiny):
+    import torch
+    fib, h, rep = trained_tiny
+    starts, _ = P.planb_export_intervals(h)
+    m = len(starts)
+    t = (np.arange(m) + 0.5) / m
+    y = torch.empty(m, dtype=torch.float32, device="cuda")
+    P.planb_model_predict(h, to_dev(starts), m, y)
+    loss = np.mean((y.cpu().numpy() - t) ** 2)
+    # far below the best constant predictor's loss (the variance of t)
+    assert loss < 0.01 * np.var(t)
+    assert rep["steps"] >= 1000 and rep["max_eps"] < m // 4
+
+
+def test_error_table_bounds_every_boundary_point(P, trained_tiny):
+    import torch
+    fib, h, rep = trained_tiny
+    starts, _ = P.planb_export_intervals(h)
+    m = len(starts)
+    ints = [S.to_int(r) for r in starts]
+    lasts = [(ints[i + 1] - 1) if i + 1 < m else (1 << 128) - 1 for i in range(m)]
+    pts = np.concatenate([starts, S.from_ints(lasts)])
+    idx = np.concatenate([np.arange(m)] * 2)
+    y = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+    P.planb_model_predict(h, to_dev(pts), len(pts), y)
+    p = mlp.predict_positions(y.cpu().numpy(), m)
+    eps = P.planb_model_get_eps(h, 4096).astype(np.int64)
+    assert len(eps) == max(1, min(4096, m // 64))  # at least 64 positions per segment
+    seg = p * len(eps) // m
+    assert np.all(eps[seg] != 0xFFFFFFFF)
+    assert np.all(np.abs(p - idx) <= eps[seg])
+
+
+def test_prediction_error_on_traffic_is_near_the_table(P, trained_tiny):
+    """Lookup traffic (random low bytes) is predicted about as well as the
+    table's points: most addresses land inside their widened window."""
+    import torch
+    fib, h, rep = trained_tiny
+    addrs = S.tiny_traffic(fib, 1 << 15, seed=21)
+    d = to_dev(addrs)
+    y = torch.empty(len(addrs), dtype=torch.float32, device="cuda")
+    P.planb_model_predict(h, d, len(addrs), y)
+    idx = torch.empty(len(addrs), dtype=torch.int32, device="cuda")
+    P.planb_lookup_index(h, d, len(addrs), idx)
+    m = P.planb_num_intervals(h)
+    p = mlp.predict_positions(y.cpu().numpy(), m)
+    eps = P.planb_model_get_eps(h, 4096).astype(np.int64)
+    e = eps[p * len(eps) // m]
+    inside = np.abs(p - idx.cpu().numpy()) <= e + e // 2 + 16
+    assert inside.mean() > 0.9
+
+
+def _learned(P, h, addrs):
+    import torch
+    d = to_dev(addrs)
+    out = torch.full((len(addrs),), -1, dtype=torch.int16, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.planb_lookup_learned(h, d, len(addrs), out, fb)
+    return host_u16(out, len(addrs)), int(fb.item())
+
+
+def test_learned_lookup_exact_tiny(P, trained_tiny):
+    fib, h, rep = trained_tiny
+    addrs = S.tiny_traffic(fib, 1 << 20, seed=1011)
+    want = oracle_trie("tiny", 11).lookup(addrs)
+    got, fb = _learned(P, h, addrs)
+    say(f"tiny learned fallbacks {fb} of {len(addrs)}")
+    assert np.array_equal(got, want)
+    assert fb < 0.05 * len(addrs)
+
+
+def test_forced_fallbacks_stay_exact(P, trained_tiny):
+    fib, h, _ = trained_tiny
+    addrs = S.tiny_traffic(fib, 1 << 16, seed=12)
+    want = oracle_trie("tiny", 11).lookup(addrs)
+    saved = P.planb_model_get_eps(h, 4096)
+    G = len(saved)
+    try:
+        P.planb_model_set_eps(h, np.zeros(G, np.uint32))  # windows of +-16 positions only
+        got, fb = _learned(P, h, addrs)
+        assert np.array_equal(got, want) and fb > 0
+        P.planb_model_set_eps(h, np.full(G, 0xFFFFFFFF, np.uint32))
+        got, fb = _learned(P, h, addrs)
+        assert np.array_equal(got, want) and fb == len(addrs)
+        P.planb_model_set_eps(h, np.full(G, 1 << 30, np.uint32))  # whole-range windows
+        got, fb = _learned(P, h, addrs)
+        assert np.array_equal(got, want) and fb == 0
+    finally:
+        P.planb_model_set_eps(h, saved)
+
+
+def test_random_weights_stay_exact(P):
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
+    P.planb_model_set_params(h, seeded_params(21, scale=3.0), 256)
+    P.planb_model_build_eps(h)
+    addrs = S.tiny_traffic(fib, 1 << 16, seed=13)
+    got, _ = _learned(P, h, addrs)
+    assert np.array_equal(got, oracle_trie("tiny", 11).lookup(addrs))
+
+
+@pytest.mark.parametrize("kind,seed,fanout", [("backbone", 22, 8), ("backbone", 22, 16), ("large", 33, 16)])
+def test_learned_lookup_exact_large_fibs(P, kind, seed, fanout):
+    fib = fib_of(kind, seed)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    rep = P.planb_train(h, seed=3)
+    say(f"{kind} fanout={fanout} training report {rep}")
+    addrs = S.backbone_traffic(fib, 1 << 21, seed=2222) if kind == "backbone" else S.zipf_traffic(fib, 1 << 21, 7)
+    want = oracle_trie(kind, seed).lookup(addrs)
+    got, fb = _learned(P, h, addrs)
+    say(f"{kind} learned fallbacks {fb} of {len(addrs)}")
+    assert np.array_equal(got, want)
+
+
+def test_learned_requires_a_model(P):
+    import torch
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops)
+    d = to_dev(S.tiny_traffic(fib, 64, seed=1))
+    out = torch.empty(64, dtype=torch.int16, device="cuda")
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_lookup_learned(h, d, 64, out)
+    assert e.value.code == P.PLANB_EINVAL
