@@ -308,6 +308,91 @@ int planb_model_get_eps(const planb_fib_t* fib, uint32_t* eps, uint32_t cap);
 int planb_model_set_eps(planb_fib_t* fib, const uint32_t* eps, uint32_t n);
 
 /*
+ * Several FIBs in one launch.  A table set is a device array of tree
+ * descriptors (slot -> FIB); every FIB in a set must share fanout and key
+ * width.  planb_lookup_multi walks a device list of bursts, each naming its
+ * slot, in one persistent launch (tiles as in planb_lookup_batches; all tree
+ * levels are read through the caches).  Bursts naming an empty or
+ * out-of-range slot are skipped (their outputs are not written).
+ */
+typedef struct planb_burst {
+    uint32_t table;            /* slot in the table set */
+    uint32_t n;                /* addresses in the burst */
+    const planb_addr_t* addrs; /* device, 16-byte aligned */
+    uint16_t* out;             /* device, 2-byte aligned */
+} planb_burst_t;
+
+typedef struct planb_tableset planb_tableset_t;
+planb_tableset_t* planb_tableset_create(uint32_t max_tables);
+/* Points slot at fib (NULL empties it); synchronous.  The caller keeps fib
+ * alive while any launch may use the slot. */
+int planb_tableset_set(planb_tableset_t* ts, uint32_t slot, const planb_fib_t* fib);
+/* Launch shape of the multi-FIB kernel (keys per lane, lookups per group, block size). */
+int planb_tableset_set_tuning(planb_tableset_t* ts, uint32_t keys_per_lane, uint32_t lookups_per_group,
+                              uint32_t block_threads);
+/* 4 * (max_bursts + block_threads + 1) bytes of LDS must fit a workgroup. */
+int planb_lookup_multi(const planb_tableset_t* ts, const planb_burst_t* bursts, const uint32_t* n_bursts,
+                       uint32_t max_bursts, void* stream);
+void planb_tableset_free(planb_tableset_t* ts);
+
+/*
+ * Serving runtime (Section 3 "Batching" and "Dynamic FIB Update", Section 4's
+ * RX-LPM-TX pipeline, for a GPU).  Tables are registered by id with their
+ * rules and built on the device when a burst first needs them; while the
+ * device memory budget would be exceeded, the least recently used tables with
+ * no launch in flight are evicted (rebuilt on a later use).  Bursts are
+ * queued by planb_server_submit; planb_server_poll finishes launches whose
+ * completion event has fired (copying results to the callers' host buffers)
+ * and packs queued bursts of any tables into every free launch slot, one
+ * stream per slot, so arrivals join the next launch while others run
+ * (continuous batching).  planb_server_set_table on a live id swaps in the
+ * rebuilt FIB; the old one is freed after the last launch using it.
+ * Single-threaded: call a server's functions from one thread.
+ */
+typedef struct planb_server planb_server_t;
+
+typedef struct planb_server_cfg {
+    uint32_t max_tables;    /* table ids 0 .. max_tables-1 (0 -> 16) */
+    uint32_t streams;       /* launch slots / streams in flight at once, 1..8 (0 -> 2) */
+    uint32_t max_bursts;    /* bursts per launch (0 -> 1024) */
+    uint32_t max_lookups;   /* addresses per launch (0 -> 2^20) */
+    uint32_t fanout;        /* fanout of every table (0 -> 16) */
+    uint32_t key_bits;      /* 64 or 128 for every table (0 -> 128) */
+    uint64_t memory_budget; /* device bytes for resident trees (0 = unlimited) */
+} planb_server_cfg_t;
+
+typedef struct planb_completion {
+    int64_t tag;      /* the submitter's tag */
+    uint32_t table;
+    uint32_t n;
+    double submit_us; /* planb_server_now_us() at submit */
+    double done_us;   /* ... when poll saw the launch complete */
+    int32_t status;   /* PLANB_OK */
+    int32_t pad;
+} planb_completion_t;
+
+typedef struct planb_server_stats {
+    uint64_t launches, bursts, lookups, admissions, evictions, resident_bytes;
+    uint32_t resident_tables, queued;
+} planb_server_stats_t;
+
+planb_server_t* planb_server_create(const planb_server_cfg_t* cfg);
+void planb_server_free(planb_server_t* server); /* waits for launches in flight */
+/* Registers or replaces table id (the rules are validated and copied). */
+int planb_server_set_table(planb_server_t* server, uint32_t id, const planb_addr_t* prefixes,
+                           const uint8_t* lengths, const uint16_t* next_hops, size_t n);
+/* Queues a burst: addrs (host) are copied now; out (host, n uint16) is
+ * written before the burst's completion is returned by poll. */
+int planb_server_submit(planb_server_t* server, uint32_t table, const planb_addr_t* addrs, uint32_t n,
+                        uint16_t* out, int64_t tag);
+/* Progresses the server and returns up to cap completions (count >= 0 or a
+ * status).  block != 0 waits until at least one completion is available or
+ * nothing is queued or in flight. */
+int planb_server_poll(planb_server_t* server, planb_completion_t* out, uint32_t cap, int block);
+int planb_server_stats(const planb_server_t* server, planb_server_stats_t* stats);
+double planb_server_now_us(void);
+
+/*
  * Host-only halves of planb_build, usable without a GPU (tools, tests).
  *
  * planb_build_intervals -- range conversion and interval partitioning

@@ -1,0 +1,432 @@
+// Serving runtime: several FIBs resident on one GPU, admitted against a device
+// memory budget, with continuous batching of arriving bursts.
+//
+// The paper's router forms lookup batches from NIC bursts in a dedicated LPM
+// stage and rebuilds a FIB in the background, swapping it in atomically and
+// freeing the old one once in-flight lookups finish (Section 3 "Batching",
+// "Dynamic FIB Update"; Section 4 "Thread Pipeline").  Here:
+//  * submit() queues a burst (table id, host addresses, host output);
+//  * poll() completes finished launches (results copied to the caller's
+//    buffers, completion times recorded) and packs queued bursts -- from any
+//    tables -- into the next free launch slot, so bursts that arrive while
+//    others run join the next launch and launches on different streams
+//    overlap;
+//  * a table is built on the device when a burst first needs it, evicting the
+//    least recently used idle tables while the budget would be exceeded;
+//  * set_table() on a live id builds the new FIB and swaps it in; the old one
+//    is freed when the last launch that used it has completed.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <unordered_map>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "multi.hpp"
+
+using namespace planb;
+
+namespace {
+
+double now_us()
+{
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void free_fib_nosync(planb_fib_t* f)
+{
+    release_learned(f);
+    if (f->d_keys) (void)hipFree(f->d_keys);
+    if (f->d_vals) (void)hipFree(f->d_vals);
+    delete f;
+}
+
+struct Pending {
+    int64_t tag;
+    uint32_t table;
+    uint32_t n;
+    std::vector<planb_addr_t> addrs;
+    uint16_t* out;
+    double submit_us;
+    uint32_t offset = 0;  // position in the launch
+};
+
+struct Table {
+    bool registered = false;
+    std::vector<planb_addr_t> pfx;
+    std::vector<uint8_t> len;
+    std::vector<uint16_t> nh;
+    uint64_t m = 0;              // elementary intervals of the rule set
+    planb_fib_t* fib = nullptr;  // resident structure, or NULL
+    size_t bytes = 0;
+    double last_use = 0;
+    int inflight = 0;            // launches in flight that use `fib`
+};
+
+struct Slot {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    planb_addr_t* h_in = nullptr;
+    uint16_t* h_out = nullptr;
+    unsigned char* h_desc = nullptr;  // [count u32, pad][BurstRec x max_bursts]
+    planb_addr_t* d_in = nullptr;
+    uint16_t* d_out = nullptr;
+    unsigned char* d_desc = nullptr;
+    bool busy = false;
+    std::vector<Pending> bursts;
+    std::vector<planb_fib_t*> fibs;  // FIB used by each table of the launch (for deferred frees)
+    std::vector<uint32_t> tables;
+};
+
+}  // namespace
+
+struct planb_server {
+    planb_server_cfg_t cfg{};
+    planb_tableset_t* ts = nullptr;
+    MultiLaunch launch;
+    std::vector<Table> tables;
+    std::deque<Pending> queue;
+    std::vector<Slot> slots;
+    std::deque<planb_completion_t> done;
+    std::unordered_map<planb_fib_t*, int> retired;  // replaced FIBs -> launches still using them
+    uint64_t used_bytes = 0;
+    planb_server_stats_t stats{};
+};
+
+namespace {
+
+void server_release(planb_server_t* s)
+{
+    for (auto& sl : s->slots) {
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
+        if (sl.h_in) (void)hipHostFree(sl.h_in);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+        if (sl.d_in) (void)hipFree(sl.d_in);
+        if (sl.d_out) (void)hipFree(sl.d_out);
+        if (sl.d_desc) (void)hipFree(sl.d_desc);
+    }
+    for (auto& t : s->tables)
+        if (t.fib) free_fib_nosync(t.fib);
+    for (auto& r : s->retired) free_fib_nosync(r.first);
+    if (s->ts) planb_tableset_free(s->ts);
+    delete s;
+}
+
+// Device bytes planb_build will allocate for the table (same layout arithmetic).
+size_t table_bytes(const Table& t, uint32_t fanout, uint32_t key_bits)
+{
+    planb_info_t info;
+    if (planb_layout(t.m, fanout, fanout, 1, &info) != PLANB_OK) return SIZE_MAX;
+    return info.key_bytes / 128 * key_bits + (t.m + 63) / 64 * 64 * 2;
+}
+
+// Make table `id` resident; false if the budget cannot be met right now
+// (memory held by tables with launches in flight).
+int admit(planb_server_t* s, uint32_t id, bool* ok)
+{
+    Table& t = s->tables[id];
+    *ok = true;
+    if (t.fib) return PLANB_OK;
+    const uint64_t budget = s->cfg.memory_budget;
+    const size_t need = table_bytes(t, s->cfg.fanout, s->cfg.key_bits);
+    if (budget) {
+        if (need > budget) return fail(PLANB_ERANGE, "table " + std::to_string(id) + " alone exceeds the budget");
+        while (s->used_bytes + need > budget) {
+            int victim = -1;
+            for (uint32_t k = 0; k < s->tables.size(); ++k) {
+                const Table& c = s->tables[k];
+                if (c.fib && c.inflight == 0 && (victim < 0 || c.last_use < s->tables[victim].last_use))
+                    victim = (int)k;
+            }
+            if (victim < 0) {
+                *ok = false;
+                return PLANB_OK;
+            }
+            Table& v = s->tables[victim];
+            int rc = planb_tableset_set(s->ts, (uint32_t)victim, nullptr);
+            if (rc != PLANB_OK) return rc;
+            free_fib_nosync(v.fib);
+            s->used_bytes -= v.bytes;
+            v.fib = nullptr;
+            v.bytes = 0;
+            ++s->stats.evictions;
+        }
+    }
+    planb_params_t p{};
+    p.fanout = s->cfg.fanout;
+    p.key_bits = s->cfg.key_bits;
+    planb_fib_t* f = planb_build_ex(t.pfx.data(), t.len.data(), t.nh.data(), t.len.size(), &p);
+    if (!f) return planb_last_status() ? planb_last_status() : PLANB_EDEVICE;
+    int rc = planb_tableset_set(s->ts, id, f);
+    if (rc != PLANB_OK) {
+        free_fib_nosync(f);
+        return rc;
+    }
+    t.fib = f;
+    t.bytes = f->key_bytes + f->value_bytes;
+    s->used_bytes += t.bytes;
+    ++s->stats.admissions;
+    return PLANB_OK;
+}
+
+void finish_slot(planb_server_t* s, Slot& sl)
+{
+    const double t = now_us();
+    for (Pending& p : sl.bursts) {
+        std::memcpy(p.out, sl.h_out + p.offset, (size_t)p.n * sizeof(uint16_t));
+        planb_completion_t c{};
+        c.tag = p.tag;
+        c.table = p.table;
+        c.n = p.n;
+        c.submit_us = p.submit_us;
+        c.done_us = t;
+        c.status = PLANB_OK;
+        s->done.push_back(c);
+    }
+    for (size_t k = 0; k < sl.tables.size(); ++k) {
+        Table& tb = s->tables[sl.tables[k]];
+        planb_fib_t* f = sl.fibs[k];
+        if (tb.fib == f) {
+            --tb.inflight;
+        } else {  // replaced while in flight
+            auto it = s->retired.find(f);
+            if (it != s->retired.end() && --it->second == 0) {
+                free_fib_nosync(f);
+                s->retired.erase(it);
+            }
+        }
+    }
+    sl.bursts.clear();
+    sl.tables.clear();
+    sl.fibs.clear();
+    sl.busy = false;
+}
+
+int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
+{
+    *launched = false;
+    const uint32_t maxb = s->cfg.max_bursts, maxl = s->cfg.max_lookups;
+    uint32_t nb = 0, na = 0;
+    BurstRec* desc = reinterpret_cast<BurstRec*>(sl.h_desc + 16);
+    std::vector<char> blocked(s->tables.size(), 0);
+    for (auto it = s->queue.begin(); it != s->queue.end() && nb < maxb;) {
+        Pending& p = *it;
+        if (na + p.n > maxl) {
+            if (na == 0) return fail(PLANB_ERANGE, "burst larger than max_lookups");
+            break;
+        }
+        if (blocked[p.table]) {
+            ++it;
+            continue;
+        }
+        bool ok = true;
+        int rc = admit(s, p.table, &ok);
+        if (rc != PLANB_OK) return rc;
+        if (!ok) {  // keep it queued until memory frees up
+            blocked[p.table] = 1;
+            ++it;
+            continue;
+        }
+        Table& t = s->tables[p.table];
+        std::memcpy(sl.h_in + na, p.addrs.data(), (size_t)p.n * sizeof(planb_addr_t));
+        desc[nb] = BurstRec{p.table, p.n, reinterpret_cast<const u64x2*>(sl.d_in + na), sl.d_out + na};
+        p.offset = na;
+        na += p.n;
+        ++nb;
+        if (std::find(sl.tables.begin(), sl.tables.end(), p.table) == sl.tables.end()) {
+            sl.tables.push_back(p.table);
+            sl.fibs.push_back(t.fib);
+            ++t.inflight;
+        }
+        t.last_use = now_us();
+        sl.bursts.push_back(std::move(p));
+        it = s->queue.erase(it);
+    }
+    if (nb == 0) return PLANB_OK;
+    if (s->launch.fn == nullptr) {  // first launch: the table set now knows fanout and key width
+        int rc = tableset_plan(s->ts, maxb, &s->launch);
+        if (rc != PLANB_OK) return rc;
+    }
+    std::memcpy(sl.h_desc, &nb, sizeof(uint32_t));
+    hipError_t e;
+    if ((e = hipMemcpyAsync(sl.d_in, sl.h_in, (size_t)na * 16, hipMemcpyHostToDevice, sl.st)) != hipSuccess ||
+        (e = hipMemcpyAsync(sl.d_desc, sl.h_desc, 16 + (size_t)nb * sizeof(BurstRec), hipMemcpyHostToDevice, sl.st)) !=
+            hipSuccess ||
+        (e = launch_multi(s->launch, tableset_device(s->ts), tableset_capacity(s->ts),
+                          reinterpret_cast<const BurstRec*>(sl.d_desc + 16), reinterpret_cast<const uint32_t*>(sl.d_desc),
+                          maxb, sl.st)) != hipSuccess ||
+        (e = hipMemcpyAsync(sl.h_out, sl.d_out, (size_t)na * 2, hipMemcpyDeviceToHost, sl.st)) != hipSuccess ||
+        (e = hipEventRecord(sl.done, sl.st)) != hipSuccess)
+        return fail_hip(e, "server launch");
+    sl.busy = true;
+    ++s->stats.launches;
+    s->stats.bursts += nb;
+    s->stats.lookups += na;
+    *launched = true;
+    return PLANB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+double planb_server_now_us(void) { return now_us(); }
+
+planb_server_t* planb_server_create(const planb_server_cfg_t* cfg_in)
+{
+    clear_error();
+    planb_server_cfg_t cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.max_tables == 0) cfg.max_tables = 16;
+    if (cfg.streams == 0) cfg.streams = 2;
+    if (cfg.max_bursts == 0) cfg.max_bursts = 1024;
+    if (cfg.max_lookups == 0) cfg.max_lookups = 1u << 20;
+    if (cfg.fanout == 0) cfg.fanout = 16;
+    if (cfg.key_bits == 0) cfg.key_bits = 128;
+    if ((cfg.key_bits != 64 && cfg.key_bits != 128) || (cfg.fanout != 8 && cfg.fanout != 16 && cfg.fanout != 32)) {
+        fail(PLANB_EINVAL, "server fanout must be 8/16/32 and key_bits 64 or 128");
+        return nullptr;
+    }
+    if (cfg.streams > 8 || cfg.max_tables > 65536 || cfg.max_bursts > 16384) {
+        fail(PLANB_EINVAL, "server configuration out of range");
+        return nullptr;
+    }
+    auto* s = new (std::nothrow) planb_server_t();
+    if (!s) {
+        fail(PLANB_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    s->cfg = cfg;
+    s->tables.resize(cfg.max_tables);
+    s->ts = planb_tableset_create(cfg.max_tables);
+    if (!s->ts) {
+        server_release(s);
+        return nullptr;
+    }
+    // fix the table set's shape before planning the launch
+    planb_tableset_set_tuning(s->ts, cfg.fanout >= 16 ? 4 : 2, 2, 512);
+    s->slots.resize(cfg.streams);
+    const size_t dbytes = 16 + (size_t)cfg.max_bursts * sizeof(BurstRec);
+    hipError_t e = hipSuccess;
+    for (auto& sl : s->slots) {
+        if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_in), (size_t)cfg.max_lookups * 16, 0)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_out), (size_t)cfg.max_lookups * 2, 0)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_desc), dbytes, 0)) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&sl.d_in), (size_t)cfg.max_lookups * 16)) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&sl.d_out), (size_t)cfg.max_lookups * 2)) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&sl.d_desc), dbytes)) != hipSuccess)
+            break;
+    }
+    if (e != hipSuccess) {
+        fail_hip(e, "creating the server");
+        server_release(s);
+        return nullptr;
+    }
+    return s;
+}
+
+void planb_server_free(planb_server_t* s)
+{
+    if (s) server_release(s);
+}
+
+int planb_server_set_table(planb_server_t* s, uint32_t id, const planb_addr_t* prefixes, const uint8_t* lengths,
+                           const uint16_t* next_hops, size_t n)
+{
+    if (!s) return fail(PLANB_EINVAL, "NULL server");
+    if (id >= s->cfg.max_tables) return fail(PLANB_ERANGE, "table id out of range");
+    if (n && (!prefixes || !lengths || !next_hops)) return fail(PLANB_EINVAL, "NULL rule array");
+    // validate now so that a bad rule set never replaces a good one
+    long long m = planb_build_intervals(prefixes, lengths, next_hops, n, 0, nullptr, nullptr, 0);
+    if (m < 0) return (int)m;
+    Table& t = s->tables[id];
+    if (t.fib) {  // rebuild-and-swap: retire the live structure
+        int rc = planb_tableset_set(s->ts, id, nullptr);
+        if (rc != PLANB_OK) return rc;
+        s->used_bytes -= t.bytes;
+        if (t.inflight > 0)
+            s->retired[t.fib] = t.inflight;
+        else
+            free_fib_nosync(t.fib);
+        t.fib = nullptr;
+        t.bytes = 0;
+        t.inflight = 0;
+    }
+    t.registered = true;
+    t.m = (uint64_t)m;
+    t.pfx.assign(prefixes, prefixes + n);
+    t.len.assign(lengths, lengths + n);
+    t.nh.assign(next_hops, next_hops + n);
+    return PLANB_OK;
+}
+
+int planb_server_submit(planb_server_t* s, uint32_t table, const planb_addr_t* addrs, uint32_t n, uint16_t* out,
+                        int64_t tag)
+{
+    if (!s) return fail(PLANB_EINVAL, "NULL server");
+    if (table >= s->cfg.max_tables || !s->tables[table].registered) return fail(PLANB_EINVAL, "unknown table id");
+    if (n > s->cfg.max_lookups) return fail(PLANB_ERANGE, "burst larger than max_lookups");
+    if (n && (!addrs || !out)) return fail(PLANB_EINVAL, "NULL host buffer");
+    Pending p;
+    p.tag = tag;
+    p.table = table;
+    p.n = n;
+    p.addrs.assign(addrs, addrs + n);
+    p.out = out;
+    p.submit_us = now_us();
+    s->queue.push_back(std::move(p));
+    return PLANB_OK;
+}
+
+int planb_server_poll(planb_server_t* s, planb_completion_t* out, uint32_t cap, int block)
+{
+    if (!s) return fail(PLANB_EINVAL, "NULL server");
+    for (;;) {
+        for (auto& sl : s->slots) {
+            if (!sl.busy) continue;
+            hipError_t q = hipEventQuery(sl.done);
+            if (q == hipSuccess) {
+                finish_slot(s, sl);
+            } else if (q != hipErrorNotReady) {
+                return fail_hip(q, "server completion");
+            }
+        }
+        for (auto& sl : s->slots) {
+            if (sl.busy || s->queue.empty()) continue;
+            bool launched = false;
+            int rc = fill_slot(s, sl, &launched);
+            if (rc != PLANB_OK) return rc;
+            if (!launched) break;
+        }
+        bool any_busy = false;
+        for (auto& sl : s->slots) any_busy |= sl.busy;
+        if (!block || !s->done.empty() || (!any_busy && s->queue.empty())) break;
+        if (!any_busy && !s->queue.empty())  // queued bursts cannot be admitted and nothing will free memory
+            return fail(PLANB_ERANGE, "queued bursts need more memory than the budget allows");
+    }
+    uint32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    return (int)k;
+}
+
+int planb_server_stats(const planb_server_t* s, planb_server_stats_t* st)
+{
+    if (!s || !st) return fail(PLANB_EINVAL, "NULL argument");
+    *st = s->stats;
+    st->resident_bytes = s->used_bytes;
+    st->resident_tables = 0;
+    for (const auto& t : s->tables) st->resident_tables += t.fib != nullptr;
+    st->queued = (uint32_t)s->queue.size();
+    return PLANB_OK;
+}
+
+}  // extern "C"

@@ -75,6 +75,29 @@ class planb_train_report_t(ctypes.Structure):
                 ("max_eps", ctypes.c_uint32), ("mean_eps", ctypes.c_float), ("empty_segments", ctypes.c_uint32)]
 
 
+class planb_burst_t(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_uint32), ("n", ctypes.c_uint32), ("addrs", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+class planb_server_cfg_t(ctypes.Structure):
+    _fields_ = [("max_tables", ctypes.c_uint32), ("streams", ctypes.c_uint32), ("max_bursts", ctypes.c_uint32),
+                ("max_lookups", ctypes.c_uint32), ("fanout", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
+                ("memory_budget", ctypes.c_uint64)]
+
+
+class planb_completion_t(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("table", ctypes.c_uint32), ("n", ctypes.c_uint32),
+                ("submit_us", ctypes.c_double), ("done_us", ctypes.c_double), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class planb_server_stats_t(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("bursts", ctypes.c_uint64), ("lookups", ctypes.c_uint64),
+                ("admissions", ctypes.c_uint64), ("evictions", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
+                ("resident_tables", ctypes.c_uint32), ("queued", ctypes.c_uint32)]
+
+
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
 
@@ -116,6 +139,18 @@ _sig("planb_model_adam", ctypes.c_int, _vp, _vp, ctypes.c_float, _vp)
 _sig("planb_model_build_eps", ctypes.c_int, _vp, _vp)
 _sig("planb_model_get_eps", ctypes.c_int, _vp, _vp, ctypes.c_uint32)
 _sig("planb_model_set_eps", ctypes.c_int, _vp, _vp, ctypes.c_uint32)
+_sig("planb_tableset_create", _vp, ctypes.c_uint32)
+_sig("planb_tableset_set", ctypes.c_int, _vp, ctypes.c_uint32, _vp)
+_sig("planb_tableset_set_tuning", ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32)
+_sig("planb_lookup_multi", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
+_sig("planb_tableset_free", None, _vp)
+_sig("planb_server_create", _vp, ctypes.POINTER(planb_server_cfg_t))
+_sig("planb_server_free", None, _vp)
+_sig("planb_server_set_table", ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp, _vp, _sz)
+_sig("planb_server_submit", ctypes.c_int, _vp, ctypes.c_uint32, _vp, ctypes.c_uint32, _vp, ctypes.c_int64)
+_sig("planb_server_poll", ctypes.c_int, _vp, ctypes.POINTER(planb_completion_t), ctypes.c_uint32, ctypes.c_int)
+_sig("planb_server_stats", ctypes.c_int, _vp, ctypes.POINTER(planb_server_stats_t))
+_sig("planb_server_now_us", ctypes.c_double)
 _sig("planb_layout", ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
      ctypes.POINTER(planb_info_t))
 
@@ -430,6 +465,108 @@ def planb_model_get_eps(fib: Fib, segments: int) -> np.ndarray:
 def planb_model_set_eps(fib: Fib, eps):
     e = np.ascontiguousarray(eps, dtype=np.uint32)
     _check(_lib.planb_model_set_eps(fib, e.ctypes.data, e.shape[0]))
+
+
+class TableSet:
+    """Owner of a planb_tableset_t* (slot -> FIB descriptors on the device)."""
+
+    def __init__(self, max_tables: int):
+        self.ptr = _lib.planb_tableset_create(max_tables)
+        if not self.ptr:
+            raise PlanbError(planb_last_status(), planb_last_error())
+        self.fibs = {}
+
+    def set(self, slot: int, fib: Fib | None):
+        _check(_lib.planb_tableset_set(self.ptr, slot, fib if fib is not None else None))
+        self.fibs[slot] = fib  # keeps the FIB alive while the slot points at it
+
+    def set_tuning(self, keys_per_lane: int, lookups_per_group: int = 2, block_threads: int = 512):
+        _check(_lib.planb_tableset_set_tuning(self.ptr, keys_per_lane, lookups_per_group, block_threads))
+
+    def close(self):
+        if self.ptr:
+            _lib.planb_tableset_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def burst_array(bursts):
+    """[(slot, addrs_tensor_or_ptr, out_tensor_or_ptr, n), ...] -> ctypes array of planb_burst_t."""
+    arr = (planb_burst_t * max(1, len(bursts)))()
+    for i, (slot, a, o, n) in enumerate(bursts):
+        arr[i].table = slot
+        arr[i].n = n
+        arr[i].addrs = _dev_ptr(a, "addrs") if n else 0
+        arr[i].out = _dev_ptr(o, "out") if n else 0
+    return arr
+
+
+def planb_lookup_multi(ts: TableSet, bursts_dev, n_bursts_dev, max_bursts: int, stream=None):
+    _check(_lib.planb_lookup_multi(ts.ptr, _dev_ptr(bursts_dev, "bursts"), _dev_ptr(n_bursts_dev, "n_bursts"),
+                                   max_bursts, _stream_handle(stream)))
+
+
+class Server:
+    """Owner of a planb_server_t* (see planb.h for the semantics)."""
+
+    def __init__(self, max_tables=16, streams=2, max_bursts=1024, max_lookups=1 << 20, fanout=16, key_bits=128,
+                 memory_budget=0):
+        self.cfg = planb_server_cfg_t(max_tables, streams, max_bursts, max_lookups, fanout, key_bits, memory_budget)
+        self.ptr = _lib.planb_server_create(ctypes.byref(self.cfg))
+        if not self.ptr:
+            raise PlanbError(planb_last_status(), planb_last_error())
+        self._comp = (planb_completion_t * 4096)()
+        self._keep = {}
+
+    def set_table(self, table_id, prefixes, lengths, next_hops):
+        n = len(lengths)
+        p = _host(prefixes, np.uint64, (2,)) if n else np.zeros((0, 2), np.uint64)
+        L = _host(lengths, np.uint8)
+        nh = _host(next_hops, np.uint16)
+        _check(_lib.planb_server_set_table(self.ptr, table_id, p.ctypes.data if n else None,
+                                           L.ctypes.data if n else None, nh.ctypes.data if n else None, n))
+
+    def submit(self, table_id, addrs: np.ndarray, out: np.ndarray, tag: int):
+        """addrs (n, 2) uint64 host; out (n,) uint16 host array written before completion."""
+        a = _host(addrs, np.uint64, (2,))
+        if out.dtype != np.uint16 or not out.flags.c_contiguous or out.shape[0] < a.shape[0]:
+            raise ValueError("out must be a contiguous uint16 array of at least n elements")
+        self._keep[tag] = out
+        _check(_lib.planb_server_submit(self.ptr, table_id, a.ctypes.data, a.shape[0], out.ctypes.data, tag))
+
+    def poll(self, block: bool = False):
+        k = _check(_lib.planb_server_poll(self.ptr, self._comp, len(self._comp), 1 if block else 0))
+        res = []
+        for i in range(k):
+            c = self._comp[i]
+            self._keep.pop(c.tag, None)
+            res.append((c.tag, c.table, c.n, c.submit_us, c.done_us))
+        return res
+
+    def stats(self) -> dict:
+        st = planb_server_stats_t()
+        _check(_lib.planb_server_stats(self.ptr, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in planb_server_stats_t._fields_}
+
+    def close(self):
+        if self.ptr:
+            _lib.planb_server_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def planb_server_now_us() -> float:
+    return float(_lib.planb_server_now_us())
 
 
 def exported_symbols() -> list[str]:

@@ -1,0 +1,43 @@
+"""Serving driver: replays burst arrivals against the native server
+(planb_server_*) and reports latency percentiles and throughput.
+
+The server does admission, continuous batching, streams and completion
+tracking; this module only feeds it arrivals at their scheduled times (an open
+loop: a burst's latency runs from its scheduled arrival to the moment the
+server reports it complete, so time spent queued behind a slow driver or a
+busy GPU counts) and summarises the completions.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import planb as P
+
+
+def replay(server: "P.Server", arrivals_s, tables, addrs, outs, timeout_s: float = 120.0):
+    """arrivals_s: sorted arrival offsets (seconds); tables / addrs / outs per
+    burst.  Returns per-burst latencies (microseconds) and the wall time."""
+    n = len(arrivals_s)
+    lat = np.zeros(n)
+    t0 = P.planb_server_now_us() + 1000.0  # start 1 ms from now
+    sched = t0 + np.asarray(arrivals_s) * 1e6
+    nxt = 0
+    done = 0
+    while done < n:
+        now = P.planb_server_now_us()
+        while nxt < n and sched[nxt] <= now:
+            server.submit(int(tables[nxt]), addrs[nxt], outs[nxt], nxt)
+            nxt += 1
+        for tag, _, _, _, done_us in server.poll(block=(nxt == n)):
+            lat[tag] = done_us - sched[tag]
+            done += 1
+        if now - t0 > timeout_s * 1e6:
+            raise TimeoutError(f"serving replay did not finish: {done} of {n} bursts done")
+    wall = (P.planb_server_now_us() - t0) / 1e6
+    return lat, wall
+
+
+def summary(lat_us, sizes, wall_s) -> dict:
+    return {"bursts": int(len(lat_us)), "lookups": int(np.sum(sizes)),
+            "p50_us": float(np.percentile(lat_us, 50)), "p99_us": float(np.percentile(lat_us, 99)),
+            "mean_us": float(np.mean(lat_us)), "glps": float(np.sum(sizes) / wall_s / 1e9), "seconds": wall_s}
