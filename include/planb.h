@@ -391,6 +391,17 @@ int planb_server_submit(planb_server_t* server, uint32_t table, const planb_addr
 int planb_server_poll(planb_server_t* server, planb_completion_t* out, uint32_t cap, int block);
 int planb_server_stats(const planb_server_t* server, planb_server_stats_t* stats);
 double planb_server_now_us(void);
+/* Makes table id resident now (evicting idle tables if the budget needs it). */
+int planb_server_admit(planb_server_t* server, uint32_t id);
+/* Open-loop load generator beside the server: burst k arrives at
+ * start + arrival_us[k] (start = now + 1 ms), is submitted then, and its
+ * latency_us[k] runs from that arrival to the poll that sees it complete.
+ * addrs / out (host) hold all bursts back to back, burst k at
+ * [offsets[k], offsets[k+1]) (n_bursts + 1 offsets); arrivals and offsets are
+ * non-decreasing.  *wall_s (may be NULL) receives the elapsed seconds. */
+int planb_server_replay(planb_server_t* server, uint32_t n_bursts, const double* arrival_us, const uint32_t* table,
+                        const uint64_t* offsets, const planb_addr_t* addrs, uint16_t* out, double* latency_us,
+                        double* wall_s);
 
 /*
  * Host-only halves of planb_build, usable without a GPU (tools, tests).

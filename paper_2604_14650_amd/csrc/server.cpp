@@ -418,6 +418,51 @@ int planb_server_poll(planb_server_t* s, planb_completion_t* out, uint32_t cap, 
     return (int)k;
 }
 
+int planb_server_admit(planb_server_t* s, uint32_t id)
+{
+    if (!s) return fail(PLANB_EINVAL, "NULL server");
+    if (id >= s->cfg.max_tables || !s->tables[id].registered) return fail(PLANB_EINVAL, "unknown table id");
+    bool ok = true;
+    int rc = admit(s, id, &ok);
+    if (rc != PLANB_OK) return rc;
+    return ok ? PLANB_OK : fail(PLANB_ERANGE, "no idle table to evict for this one");
+}
+
+int planb_server_replay(planb_server_t* s, uint32_t n_bursts, const double* arrival_us, const uint32_t* table,
+                        const uint64_t* offsets, const planb_addr_t* addrs, uint16_t* out, double* latency_us,
+                        double* wall_s)
+{
+    if (!s || (n_bursts && (!arrival_us || !table || !offsets || !addrs || !out || !latency_us)))
+        return fail(PLANB_EINVAL, "NULL argument");
+    for (uint32_t k = 1; k < n_bursts; ++k)
+        if (arrival_us[k] < arrival_us[k - 1] || offsets[k] < offsets[k - 1])
+            return fail(PLANB_EINVAL, "arrivals and offsets must be non-decreasing");
+    std::vector<double> sched(n_bursts);
+    const double t0 = now_us() + 1000.0;
+    for (uint32_t k = 0; k < n_bursts; ++k) sched[k] = t0 + arrival_us[k];
+    std::vector<planb_completion_t> comp(1024);
+    uint32_t next = 0, done = 0;
+    while (done < n_bursts) {
+        const double now = now_us();
+        while (next < n_bursts && sched[next] <= now) {
+            const uint64_t o = offsets[next];
+            int rc = planb_server_submit(s, table[next], addrs + o, (uint32_t)(offsets[next + 1] - o), out + o,
+                                         (int64_t)next);
+            if (rc != PLANB_OK) return rc;
+            ++next;
+        }
+        const int got = planb_server_poll(s, comp.data(), (uint32_t)comp.size(), 0);
+        if (got < 0) return got;
+        for (int k = 0; k < got; ++k) {
+            const int64_t tag = comp[k].tag;
+            latency_us[tag] = comp[k].done_us - sched[tag];
+            ++done;
+        }
+    }
+    if (wall_s) *wall_s = (now_us() - t0) / 1e6;
+    return PLANB_OK;
+}
+
 int planb_server_stats(const planb_server_t* s, planb_server_stats_t* st)
 {
     if (!s || !st) return fail(PLANB_EINVAL, "NULL argument");

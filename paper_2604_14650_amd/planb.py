@@ -151,6 +151,9 @@ _sig("planb_server_submit", ctypes.c_int, _vp, ctypes.c_uint32, _vp, ctypes.c_ui
 _sig("planb_server_poll", ctypes.c_int, _vp, ctypes.POINTER(planb_completion_t), ctypes.c_uint32, ctypes.c_int)
 _sig("planb_server_stats", ctypes.c_int, _vp, ctypes.POINTER(planb_server_stats_t))
 _sig("planb_server_now_us", ctypes.c_double)
+_sig("planb_server_admit", ctypes.c_int, _vp, ctypes.c_uint32)
+_sig("planb_server_replay", ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
+     ctypes.POINTER(ctypes.c_double))
 _sig("planb_layout", ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
      ctypes.POINTER(planb_info_t))
 
@@ -547,6 +550,23 @@ class Server:
             self._keep.pop(c.tag, None)
             res.append((c.tag, c.table, c.n, c.submit_us, c.done_us))
         return res
+
+    def admit(self, table_id: int):
+        _check(_lib.planb_server_admit(self.ptr, table_id))
+
+    def replay(self, arrival_us, tables, offsets, addrs, out):
+        """Native open-loop replay (planb_server_replay); returns (latency_us, wall_s)."""
+        arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        tb = np.ascontiguousarray(tables, dtype=np.uint32)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        a = _host(addrs, np.uint64, (2,))
+        if out.dtype != np.uint16 or not out.flags.c_contiguous or out.shape[0] < a.shape[0]:
+            raise ValueError("out must be a contiguous uint16 array covering every address")
+        lat = np.zeros(arr.shape[0], dtype=np.float64)
+        wall = ctypes.c_double(0.0)
+        _check(_lib.planb_server_replay(self.ptr, arr.shape[0], arr.ctypes.data, tb.ctypes.data, off.ctypes.data,
+                                        a.ctypes.data, out.ctypes.data, lat.ctypes.data, ctypes.byref(wall)))
+        return lat, wall.value
 
     def stats(self) -> dict:
         st = planb_server_stats_t()

@@ -37,6 +37,17 @@ def replay(server: "P.Server", arrivals_s, tables, addrs, outs, timeout_s: float
     return lat, wall
 
 
+def replay_native(server: "P.Server", arrivals_s, tables, addrs_list):
+    """The same open-loop replay run by the native planb_server_replay (no
+    Python in the submit/poll loop).  Returns (latency_us, wall_s, outputs)."""
+    sizes = np.array([len(a) for a in addrs_list], dtype=np.uint64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    flat = np.concatenate(addrs_list) if len(addrs_list) else np.zeros((0, 2), np.uint64)
+    out = np.zeros(max(1, flat.shape[0]), dtype=np.uint16)
+    lat, wall = server.replay(np.asarray(arrivals_s) * 1e6, tables, offsets, flat, out)
+    return lat, wall, [out[offsets[k]:offsets[k + 1]] for k in range(len(addrs_list))]
+
+
 def summary(lat_us, sizes, wall_s) -> dict:
     return {"bursts": int(len(lat_us)), "lookups": int(np.sum(sizes)),
             "p50_us": float(np.percentile(lat_us, 50)), "p99_us": float(np.percentile(lat_us, 99)),

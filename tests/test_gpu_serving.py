@@ -172,4 +172,13 @@ def test_serving_replay_reports_latency(P, vrfs):
     assert s["p99_us"] >= s["p50_us"] > 0
     for i in range(len(addrs)):
         assert np.array_equal(outs[i], tries[tids[i]].lookup(addrs[i]))
+    # the native replay, tables admitted beforehand
+    for k in range(len(tabs)):
+        srv.admit(k)
+    lat, wall, outs = serve.replay_native(srv, arrivals, tids, addrs)
+    s = serve.summary(lat, sizes, wall)
+    say(f"native replay summary {s}")
+    assert s["p99_us"] >= s["p50_us"] > 0
+    for i in range(len(addrs)):
+        assert np.array_equal(outs[i], tries[tids[i]].lookup(addrs[i]))
     srv.close()
