@@ -96,9 +96,9 @@ def kernel_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def measured_traffic(per_launch_lookups: int):
+def measured_traffic(per_launch_lookups: int, config: str):
     """HBM bytes per launch from the committed PMC summary, if it was taken
-    with the current kernel sources (else None)."""
+    with the current kernel sources and the same kernel configuration (else None)."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -108,7 +108,8 @@ def measured_traffic(per_launch_lookups: int):
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_sources_sha1") != kernel_hash() or int(kv.get("lookups_per_launch", -1)) != per_launch_lookups:
+    if (kv.get("kernel_sources_sha1") != kernel_hash() or int(kv.get("lookups_per_launch", -1)) != per_launch_lookups
+            or kv.get("kernel_config") != config):
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -281,7 +282,11 @@ def main():
     P.planb_lookup(h, d, n, out)
     torch.cuda.synchronize()
     got = out.cpu().numpy().view(np.uint16).copy()
-    traffic = measured_traffic(n)
+    tu = P.planb_get_tuning(h)
+    kconf = (f"fanout={info['fanout']} key_bits={info['key_bits']} keys_per_lane={tu['keys_per_lane']} "
+             f"lds_levels={tu['lds_levels']} lookups_per_group={tu['lookups_per_group']} "
+             f"block_threads={tu['block_threads']}")
+    traffic = measured_traffic(n, kconf)
 
     result = {
         "metric": METRIC, "value": round(glps, 3), "unit": "GLPS", "n_gpus": 1,
