@@ -115,7 +115,7 @@ def measured_traffic(per_launch_lookups: int, config: str):
 
 
 # Launch shapes the autotuner chose for this workload on MI355X (used with --no-autotune).
-KNOWN_TUNING = {0: {"fanout": 8, "tuning": (8, 5, 2, 1024)}, 128: {"fanout": 8, "tuning": (2, 4, 1, 512)}}
+KNOWN_TUNING = {0: {"fanout": 8, "tuning": (4, 5, 2, 512, 1)}, 128: {"fanout": 8, "tuning": (2, 4, 2, 512, 1)}}
 
 
 def plain_leg(P, fib, d, n, out, args):
@@ -285,7 +285,7 @@ def main():
     tu = P.planb_get_tuning(h)
     kconf = (f"fanout={info['fanout']} key_bits={info['key_bits']} keys_per_lane={tu['keys_per_lane']} "
              f"lds_levels={tu['lds_levels']} lookups_per_group={tu['lookups_per_group']} "
-             f"block_threads={tu['block_threads']}")
+             f"block_threads={tu['block_threads']} lds_search={tu['lds_search']}")
     traffic = measured_traffic(n, kconf)
 
     result = {

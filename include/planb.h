@@ -163,12 +163,18 @@ int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
  *                      (0..depth; -1 = the deepest that fits 64 KiB)
  *   lookups_per_group  independent lookups each lane group keeps in flight (1, 2 or 4)
  *   block_threads      workgroup size, 512 or 1024
+ *   lds_search         0: every lane compares all its keys of a node;
+ *                      1: in the LDS-staged levels every lane walks its own
+ *                      lookups by binary search inside the nodes; the lower
+ *                      levels are then shared by fanout/keys_per_lane lanes
+ *                      (1, 2 or 4), which take the lookups over by shuffles
  */
 typedef struct planb_tuning {
     uint32_t keys_per_lane;
     int32_t lds_levels;
     uint32_t lookups_per_group;
     uint32_t block_threads;
+    uint32_t lds_search;
 } planb_tuning_t;
 
 /* Returns PLANB_EINVAL for an unsupported combination, PLANB_ERANGE when the

@@ -54,7 +54,8 @@ def tune(prefixes, lengths, next_hops, sample, n: int | None = None, fanouts=(8,
     if rec:
         h = P.planb_build(prefixes, lengths, next_hops, fanout=rec["fanout"], key_bits=key_bits)
         t = rec["tuning"]
-        P.planb_set_tuning(h, t["keys_per_lane"], t["lds_levels"], t["lookups_per_group"], t["block_threads"])
+        P.planb_set_tuning(h, t["keys_per_lane"], t["lds_levels"], t["lookups_per_group"], t["block_threads"],
+                           t.get("lds_search", 0))
         return h, dict(rec, cached=True)
     best = None
     trials = {}
@@ -73,7 +74,8 @@ def tune(prefixes, lengths, next_hops, sample, n: int | None = None, fanouts=(8,
             h.close()
     h, r, b = best
     rec = {"fanout": b, "key_bits": P.planb_get_info(h)["key_bits"],
-           "tuning": {k: r[k] for k in ("keys_per_lane", "lds_levels", "lookups_per_group", "block_threads")},
+           "tuning": {k: r[k] for k in ("keys_per_lane", "lds_levels", "lookups_per_group", "block_threads",
+                                        "lds_search")},
            "glps": round(r["glps"], 3), "fanout_glps": trials, "sample": n,
            "seconds": round(time.time() - t0, 2)}
     if cache_path:

@@ -62,8 +62,10 @@ void refresh_desc(planb_fib_t* f)
 int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning* out, int32_t* lds_out)
 {
     const uint32_t b = f->lay.b, kpl = tu.keys_per_lane, R = tu.lookups_per_group, bs = tu.block_threads;
+    const bool bin = tu.lds_search != 0;
     if (kpl == 0 || (kpl & (kpl - 1)) || b % kpl || b / kpl > 32 || (bs != 512 && bs != 1024) ||
-        !lookup_variant_exists((int)b, (int)kpl, (int)R, (int)bs))
+        tu.lds_search > 1 || (bin && kpl != b && b / kpl != 2 && b / kpl != 4) ||
+        !lookup_variant_exists((int)b, (int)kpl, (int)R, (int)bs, bin))
         return fail(PLANB_EINVAL, "unsupported tuning: keys_per_lane " + std::to_string(kpl) +
                                       ", lookups_per_group " + std::to_string(R) + ", block_threads " +
                                       std::to_string(bs) + " for fanout " + std::to_string(b));
@@ -77,6 +79,7 @@ int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning
     out->kpl = (int)kpl;
     out->R = (int)R;
     out->block = (int)bs;
+    out->bin = bin;
     *lds_out = lds_levels;
     return PLANB_OK;
 }
@@ -369,6 +372,7 @@ int planb_get_tuning(const planb_fib_t* fib, planb_tuning_t* tuning)
     tuning->lds_levels = fib->lds_levels;
     tuning->lookups_per_group = (uint32_t)fib->tune.R;
     tuning->block_threads = (uint32_t)fib->tune.block;
+    tuning->lds_search = fib->tune.bin ? 1u : 0u;
     return PLANB_OK;
 }
 

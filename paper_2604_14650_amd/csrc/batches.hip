@@ -25,12 +25,12 @@ struct BatchRec {  // same layout as planb_batch_t
 };
 static_assert(sizeof(BatchRec) == sizeof(planb_batch_t), "planb_batch_t layout");
 
-template <int B, int KPL, int R, bool WIDE, int BS>
+template <int B, int KPL, int R, bool WIDE, int BS, bool BIN>
 __global__ void __launch_bounds__(BS)
 batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t* __restrict__ count,
                uint32_t max_batches, int index_out)
 {
-    using D = Descent<B, KPL, R, WIDE>;
+    using D = Descent<B, KPL, R, WIDE, BIN>;
     extern __shared__ uint4 lds_raw[];
     uint32_t* tile_off = reinterpret_cast<uint32_t*>(lds_raw + D::lds_bytes(t) / 16);  // max_batches + 1
     uint32_t* part = tile_off + max_batches + 1;                                       // BS
@@ -74,14 +74,14 @@ batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t*
 
 namespace {
 
-template <int B, int KPL, int R, bool W, int BS>
+template <int B, int KPL, int R, bool W, int BS, bool BIN>
 struct BatchesKernel {
     using Fn = void (*)(TreeDesc, const BatchRec*, const uint32_t*, uint32_t, int);
-    static Fn get() { return batches_kernel<B, KPL, R, W, BS>; }
+    static Fn get() { return batches_kernel<B, KPL, R, W, BS, BIN>; }
 };
 
 struct BatchesLaunch {
-    BatchesKernel<8, 1, 1, true, 512>::Fn fn = nullptr;
+    BatchesKernel<8, 1, 1, true, 512, false>::Fn fn = nullptr;
     unsigned grid = 0;
     size_t lds = 0;
 };
@@ -90,7 +90,7 @@ int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
 {
     const TreeDesc& t = fib->desc;
     const LookupTuning& tu = fib->tune;
-    L->fn = VariantTable<BatchesKernel>::pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block);
+    L->fn = VariantTable<BatchesKernel>::pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block, tu.bin);
     if (!L->fn) return fail(PLANB_EINVAL, "no batches kernel for this tuning");
     DevProps p;
     hipError_t e = dev_props(&p);
@@ -178,8 +178,7 @@ planb_graph_t* planb_graph_create(const planb_fib_t* fib, uint32_t max_batches)
     }
     g->fib = fib;
     g->max_batches = max_batches;
-    const int G = (int)fib->desc.fanout / fib->tune.kpl;
-    g->step = (uint64_t)(64 / G) * fib->tune.R;
+    g->step = lookups_per_wave_step((int)fib->desc.fanout, fib->tune);
     const size_t bytes = 16 + (size_t)max_batches * sizeof(BatchRec);
     hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
     for (int k = 0; e == hipSuccess && k < planb_graph::kSlots; ++k) {
@@ -259,10 +258,11 @@ int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint3
     std::vector<planb_tuning_t> cands;
     for (uint32_t kpl = 1; kpl <= b && kpl <= 16; kpl *= 2) {
         if (b / kpl > 32) continue;
-        for (uint32_t R : {1u, 2u, 4u})
-            for (uint32_t bs : {512u, 1024u})
-                for (int lds = std::max(0, deepest - 2); lds <= deepest; ++lds)
-                    cands.push_back(planb_tuning_t{kpl, lds, R, bs});
+        for (uint32_t bin = 0; bin <= ((kpl == b || b / kpl == 2 || b / kpl == 4) ? 1u : 0u); ++bin)
+            for (uint32_t R : {1u, 2u, 4u})
+                for (uint32_t bs : {512u, 1024u})
+                    for (int lds = std::max(0, deepest - 2); lds <= deepest; ++lds)
+                        cands.push_back(planb_tuning_t{kpl, lds, R, bs, bin});
     }
     uint16_t* out = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;

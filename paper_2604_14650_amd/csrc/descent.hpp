@@ -3,7 +3,7 @@
 //
 // This is the search of the PlanB paper's Section 3 (Algorithm 1 and Listing 1)
 // mapped onto a wave64: G = B / KPL lanes cooperate on one lookup.  Each lane
-// compares KPL keys of the current node with the address x (strided by G so a
+// compares KPL keys of the current node with the address x (arranged so that a
 // group's loads are contiguous), the group adds its counts with DPP, and the
 // count c of keys <= x selects child q*B + c.  At the leaf the interval index
 // is q*(B-1) + c - 1.  Node indices are clamped to each level's last allocated
@@ -15,13 +15,17 @@
 
 namespace planb {
 
-template <int B, int KPL, int R, bool WIDE>
+template <int B, int KPL, int R, bool WIDE, bool BIN = false>
 struct Descent {
     using KF = KeyFmt<WIDE>;
     using K = typename KF::T;
-    static constexpr int G = B / KPL;                     // lanes per lookup
-    static constexpr int LPW = 64 / G;                    // lookups per wavefront per step
-    static constexpr uint64_t kStep = (uint64_t)LPW * R;  // lookups per wavefront step
+    static constexpr int G = B / KPL;   // lanes per lookup in the cache-resident levels
+    static constexpr int LPW = 64 / G;  // lookups per wavefront per round there
+    // Hybrid mode (BIN with KPL < B): every lane owns R lookups and walks the
+    // LDS-staged levels alone by binary search, then groups of G lanes take
+    // the lookups over, one owner lane's at a time, for the lower levels.
+    static constexpr bool kHybrid = BIN && KPL < B;
+    static constexpr uint64_t kStep = kHybrid ? 64ull * R : (uint64_t)LPW * R;  // lookups per wavefront step
 
     // Bytes of LDS the top levels of t take.
     static __host__ __device__ size_t lds_bytes(const TreeDesc& t) { return (size_t)t.lds_nodes * B * sizeof(K); }
@@ -34,13 +38,129 @@ struct Descent {
         for (uint32_t i = tid; i < units; i += nthreads) lds_raw[i] = src[i];
     }
 
+    // Keys <= x in the node whose first slot is keys[node0], summed over the
+    // lookup's G lanes (lane j of the group is `j`).
     template <bool FROM_LDS>
-    static __device__ __forceinline__ uint32_t node_count(const K* keys, size_t nb, uint64_t xhi, uint64_t xlo)
+    static __device__ __forceinline__ uint32_t node_count(const K* keys, size_t node0, int j, uint64_t xhi,
+                                                          uint64_t xlo)
     {
-        int cnt = 0;
+        if constexpr (BIN && FROM_LDS && KPL == B) {
+            // one lane per lookup: branch-free binary search over the node's
+            // slots.  It counts the keys <= x among slots 0..B-2 (B-1 at most):
+            // the sentinel slot is never probed, which changes nothing because
+            // only an address equal to the sentinel would count it, and that
+            // address ends clamped on the last interval either way.
+            uint32_t c = 0;
 #pragma unroll
-        for (int s = 0; s < KPL; ++s) cnt += KF::le(keys[nb + s * G], xhi, xlo);
+            for (int step = B / 2; step >= 1; step >>= 1) c += KF::le(keys[node0 + c + step - 1], xhi, xlo) ? step : 0;
+            return c;
+        }
+        int cnt = 0;
+        if constexpr (!WIDE && KPL >= 2) {
+            // 8-byte keys: each lane reads its KPL keys as contiguous 16-byte
+            // pairs, so a group covers its node with G x KPL/2 full-width loads
+            const uint4* p = reinterpret_cast<const uint4*>(keys + node0 + (size_t)j * KPL);
+#pragma unroll
+            for (int s = 0; s < KPL / 2; ++s) {
+                const uint4 v = p[s];
+                cnt += ((((uint64_t)v.y << 32) | v.x) <= xhi) + ((((uint64_t)v.w << 32) | v.z) <= xhi);
+            }
+        } else {
+            // 16-byte keys (or one 8-byte key per lane): key s*G + j, so one
+            // load instruction covers G consecutive keys of each group's node
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) cnt += KF::le(keys[node0 + s * G + j], xhi, xlo);
+        }
         return (uint32_t)group_sum<G>(cnt);
+    }
+
+    template <bool FROM_LDS>
+    static __device__ __forceinline__ uint32_t lane_bincount(const K* keys, size_t node0, uint64_t xhi, uint64_t xlo)
+    {
+        uint32_t c = 0;  // keys <= x among slots 0..B-2 (see node_count)
+#pragma unroll
+        for (int step = B / 2; step >= 1; step >>= 1) c += KF::le(keys[node0 + c + step - 1], xhi, xlo) ? step : 0;
+        return c;
+    }
+
+    static __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+    {
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+        return ((uint64_t)hi << 32) | lo;
+    }
+
+    static __device__ __forceinline__ void store(const TreeDesc& t, void* out, int index_out, uint64_t i, uint64_t idx)
+    {
+        if (index_out)
+            __builtin_nontemporal_store((uint32_t)idx, static_cast<uint32_t*>(out) + i);
+        else
+            __builtin_nontemporal_store(t.vals[idx], static_cast<uint16_t*>(out) + i);
+    }
+
+    static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const K* lds_keys, const u64x2* addrs,
+                                                       uint64_t base, uint64_t n, void* out, int index_out)
+    {
+        const int lane = threadIdx.x & 63;
+        uint64_t xh[R], xl[R];
+        uint32_t q[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t i = base + (uint64_t)r * 64 + lane;
+            const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
+            xh[r] = a.x;
+            xl[r] = a.y;
+            q[r] = 0;
+        }
+        // LDS-staged levels, one lane per lookup
+        const uint32_t lds_internal = t.lds_levels < t.depth - 1 ? t.lds_levels : t.depth - 1;
+        for (uint32_t l = 0; l < lds_internal; ++l) {
+            const uint32_t off = t.off[l], lim = t.last[l + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                q[r] = min(q[r] * B + lane_bincount<true>(lds_keys, (size_t)(off + q[r]) * B, xh[r], xl[r]), lim);
+        }
+        if (t.lds_levels >= t.depth) {  // the whole tree is in LDS
+            const uint32_t loff = t.off[t.depth - 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t c = lane_bincount<true>(lds_keys, (size_t)(loff + q[r]) * B, xh[r], xl[r]);
+                uint64_t idx = (uint64_t)q[r] * (B - 1) + c - 1;
+                idx = idx < t.m_minus_1 ? idx : t.m_minus_1;
+                const uint64_t i = base + (uint64_t)r * 64 + lane;
+                if (i < n) store(t, out, index_out, i, idx);
+            }
+            return;
+        }
+        // lower levels: G lanes per lookup; round u serves owner lane
+        // (u % G) * LPW + lane / G, its lookup u / G
+        constexpr int T = R * G;
+        const int grp = lane / G, j = lane % G;
+        const K* gkeys = static_cast<const K*>(t.keys);
+        uint64_t yh[T], yl[T];
+        uint32_t p[T];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const int owner = (u % G) * LPW + grp;
+            yh[u] = shfl64(xh[u / G], owner);
+            yl[u] = WIDE ? shfl64(xl[u / G], owner) : 0;
+            p[u] = (uint32_t)__shfl((int)q[u / G], owner, 64);
+        }
+        for (uint32_t l = lds_internal; l + 1 < t.depth; ++l) {
+            const uint32_t off = t.off[l], lim = t.last[l + 1];
+#pragma unroll
+            for (int u = 0; u < T; ++u)
+                p[u] = min(p[u] * B + node_count<false>(gkeys, (size_t)(off + p[u]) * B, j, yh[u], yl[u]), lim);
+        }
+        const uint32_t loff = t.off[t.depth - 1];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const uint32_t c = node_count<false>(gkeys, (size_t)(loff + p[u]) * B, j, yh[u], yl[u]);
+            uint64_t idx = (uint64_t)p[u] * (B - 1) + c - 1;
+            idx = idx < t.m_minus_1 ? idx : t.m_minus_1;
+            const uint64_t i = base + (uint64_t)(u / G) * 64 + (u % G) * LPW + grp;
+            if (j == 0 && i < n) store(t, out, index_out, i, idx);
+        }
     }
 
     // Lookups [base, base + kStep) of a batch of n >= 1 addresses.  Every lane
@@ -48,6 +168,10 @@ struct Descent {
     static __device__ __forceinline__ void step(const TreeDesc& t, const K* lds_keys, const u64x2* addrs,
                                                 uint64_t base, uint64_t n, void* out, int index_out)
     {
+        if constexpr (kHybrid) {
+            step_hybrid(t, lds_keys, addrs, base, n, out, index_out);
+            return;
+        }
         const int lane = threadIdx.x & 63;
         const int grp = lane / G;
         const int j = lane % G;
@@ -67,20 +191,20 @@ struct Descent {
             if (l < t.lds_levels) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    q[r] = min(q[r] * B + node_count<true>(lds_keys, (size_t)(off + q[r]) * B + j, xhi[r], xlo[r]), lim);
+                    q[r] = min(q[r] * B + node_count<true>(lds_keys, (size_t)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    q[r] = min(q[r] * B + node_count<false>(gkeys, (size_t)(off + q[r]) * B + j, xhi[r], xlo[r]), lim);
+                    q[r] = min(q[r] * B + node_count<false>(gkeys, (size_t)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
             }
         }
         const uint32_t loff = t.off[t.depth - 1];
         const bool leaf_lds = t.lds_levels >= t.depth;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const size_t nb = (size_t)(loff + q[r]) * B + j;
-            const uint32_t c = leaf_lds ? node_count<true>(lds_keys, nb, xhi[r], xlo[r])
-                                        : node_count<false>(gkeys, nb, xhi[r], xlo[r]);
+            const size_t nb = (size_t)(loff + q[r]) * B;
+            const uint32_t c = leaf_lds ? node_count<true>(lds_keys, nb, j, xhi[r], xlo[r])
+                                        : node_count<false>(gkeys, nb, j, xhi[r], xlo[r]);
             uint64_t idx = (uint64_t)q[r] * (B - 1) + c - 1;  // c >= 1: interval 0 starts at 0
             idx = idx < t.m_minus_1 ? idx : t.m_minus_1;
             const uint64_t i = base + (uint64_t)r * LPW + grp;
@@ -94,49 +218,57 @@ struct Descent {
     }
 };
 
-// Picks KernelOf<B, KPL, R, W, BS>::get() for runtime values among the
+// Picks KernelOf<B, KPL, R, W, BS, BIN>::get() for runtime values among the
 // compiled-in variants: B in {8, 16, 32}, KPL in {1, 2, 4, 8, 16} with B/KPL
-// in [1, 32], R in {1, 2, 4}, W (wide keys) and BS in {512, 1024}.
-template <template <int, int, int, bool, int> class KernelOf>
+// in [1, 32], R in {1, 2, 4}, W (wide keys), BS in {512, 1024}, and BIN
+// (binary search by one lane per lookup in the LDS levels; with KPL < B the
+// lower levels are then shared by B/KPL lanes, for B/KPL in {2, 4}).
+template <template <int, int, int, bool, int, bool> class KernelOf>
 struct VariantTable {
-    using Fn = typename KernelOf<8, 1, 1, true, 512>::Fn;
+    using Fn = typename KernelOf<8, 1, 1, true, 512, false>::Fn;
 
-    template <int B, int KPL, bool W, int BS>
+    template <int B, int KPL, bool W, int BS, bool BIN>
     static Fn by_r(int R)
     {
         switch (R) {
-        case 1: return KernelOf<B, KPL, 1, W, BS>::get();
-        case 2: return KernelOf<B, KPL, 2, W, BS>::get();
-        case 4: return KernelOf<B, KPL, 4, W, BS>::get();
+        case 1: return KernelOf<B, KPL, 1, W, BS, BIN>::get();
+        case 2: return KernelOf<B, KPL, 2, W, BS, BIN>::get();
+        case 4: return KernelOf<B, KPL, 4, W, BS, BIN>::get();
         default: return nullptr;
         }
     }
     template <int B, bool W, int BS>
-    static Fn by_kpl(int kpl, int R)
+    static Fn by_kpl(int kpl, int R, bool bin)
     {
+        if (bin) {
+            if (kpl == B) return by_r<B, B, W, BS, true>(R);
+            if (kpl == B / 2) return by_r<B, B / 2, W, BS, true>(R);
+            if (kpl == B / 4) return by_r<B, B / 4, W, BS, true>(R);
+            return nullptr;
+        }
         switch (kpl) {
-        case 1: return by_r<B, 1, W, BS>(R);
-        case 2: return by_r<B, 2, W, BS>(R);
-        case 4: return by_r<B, 4, W, BS>(R);
-        case 8: return by_r<B, 8, W, BS>(R);
-        case 16: if constexpr (B >= 16) return by_r<B, 16, W, BS>(R); else return nullptr;
+        case 1: return by_r<B, 1, W, BS, false>(R);
+        case 2: return by_r<B, 2, W, BS, false>(R);
+        case 4: return by_r<B, 4, W, BS, false>(R);
+        case 8: return by_r<B, 8, W, BS, false>(R);
+        case 16: if constexpr (B >= 16) return by_r<B, 16, W, BS, false>(R); else return nullptr;
         default: return nullptr;
         }
     }
     template <bool W, int BS>
-    static Fn by_b(int B, int kpl, int R)
+    static Fn by_b(int B, int kpl, int R, bool bin)
     {
         switch (B) {
-        case 8: return by_kpl<8, W, BS>(kpl, R);
-        case 16: return by_kpl<16, W, BS>(kpl, R);
-        case 32: return by_kpl<32, W, BS>(kpl, R);
+        case 8: return by_kpl<8, W, BS>(kpl, R, bin);
+        case 16: return by_kpl<16, W, BS>(kpl, R, bin);
+        case 32: return by_kpl<32, W, BS>(kpl, R, bin);
         default: return nullptr;
         }
     }
-    static Fn pick(int B, int kpl, int R, bool wide, int bs)
+    static Fn pick(int B, int kpl, int R, bool wide, int bs, bool bin = false)
     {
-        if (bs == 512) return wide ? by_b<true, 512>(B, kpl, R) : by_b<false, 512>(B, kpl, R);
-        if (bs == 1024) return wide ? by_b<true, 1024>(B, kpl, R) : by_b<false, 1024>(B, kpl, R);
+        if (bs == 512) return wide ? by_b<true, 512>(B, kpl, R, bin) : by_b<false, 512>(B, kpl, R, bin);
+        if (bs == 1024) return wide ? by_b<true, 1024>(B, kpl, R, bin) : by_b<false, 1024>(B, kpl, R, bin);
         return nullptr;
     }
 };

@@ -27,11 +27,11 @@
 
 namespace planb {
 
-template <int B, int KPL, int R, bool WIDE, int BS>
+template <int B, int KPL, int R, bool WIDE, int BS, bool BIN>
 __global__ void __launch_bounds__(BS)
 lookup_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
 {
-    using D = Descent<B, KPL, R, WIDE>;
+    using D = Descent<B, KPL, R, WIDE, BIN>;
     extern __shared__ uint4 lds_raw[];
     D::stage(t, lds_raw, threadIdx.x, BS);
     __syncthreads();
@@ -44,15 +44,18 @@ lookup_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __r
 
 namespace {
 
-template <int B, int KPL, int R, bool W, int BS>
+template <int B, int KPL, int R, bool W, int BS, bool BIN>
 struct PlainKernel {
     using Fn = void (*)(TreeDesc, const u64x2*, uint64_t, void*, int);
-    static Fn get() { return lookup_kernel<B, KPL, R, W, BS>; }
+    static Fn get() { return lookup_kernel<B, KPL, R, W, BS, BIN>; }
 };
 
-using KernelFn = PlainKernel<8, 1, 1, true, 512>::Fn;
+using KernelFn = PlainKernel<8, 1, 1, true, 512, false>::Fn;
 
-KernelFn pick(int B, int kpl, int R, bool wide, int bs) { return VariantTable<PlainKernel>::pick(B, kpl, R, wide, bs); }
+KernelFn pick(int B, int kpl, int R, bool wide, int bs, bool bin)
+{
+    return VariantTable<PlainKernel>::pick(B, kpl, R, wide, bs, bin);
+}
 
 std::mutex g_mu;
 std::unordered_map<int, DevProps> g_props;
@@ -108,7 +111,7 @@ hipError_t occupancy(const void* fn, int bs, size_t lds, int* blocks)
     return hipSuccess;
 }
 
-bool lookup_variant_exists(int B, int kpl, int R, int bs) { return pick(B, kpl, R, true, bs) != nullptr; }
+bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin) { return pick(B, kpl, R, true, bs, bin) != nullptr; }
 
 int max_lds_bytes()
 {
@@ -121,7 +124,7 @@ hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* 
                          bool index_out, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    KernelFn fn = pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block);
+    KernelFn fn = pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block, tu.bin);
     if (!fn) return hipErrorInvalidValue;
     DevProps p;
     hipError_t e = dev_props(&p);
@@ -130,8 +133,7 @@ hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* 
     if (lds > (size_t)p.max_lds) return hipErrorInvalidValue;
     int nb = 1;
     if ((e = occupancy(reinterpret_cast<const void*>(fn), tu.block, lds, &nb)) != hipSuccess) return e;
-    const int G = (int)t.fanout / tu.kpl;
-    const uint64_t per_block = (uint64_t)(tu.block / 64) * (64 / G) * tu.R;
+    const uint64_t per_block = (uint64_t)(tu.block / 64) * lookups_per_wave_step((int)t.fanout, tu);
     const uint64_t want = (n + per_block - 1) / per_block;
     const uint64_t cap = (uint64_t)p.cus * nb;
     const unsigned grid = (unsigned)(want < cap ? want : cap);

@@ -12,10 +12,18 @@ struct LookupTuning {
     int kpl = 4;      // keys each lane compares per node (B / kpl lanes per lookup)
     int R = 2;        // lookups each lane group keeps in flight
     int block = 512;  // threads per workgroup
+    bool bin = false; // one lane per lookup, binary search, in the LDS-staged levels
 };
 
+// Lookups one wavefront handles per step of the descent for this shape.
+inline uint64_t lookups_per_wave_step(int B, const LookupTuning& tu)
+{
+    const bool hybrid = tu.bin && tu.kpl < B;
+    return hybrid ? 64ull * tu.R : (uint64_t)(64 / (B / tu.kpl)) * tu.R;
+}
+
 // Whether a (fanout, keys per lane, lookups per group, block size) kernel is compiled in.
-bool lookup_variant_exists(int B, int kpl, int R, int bs);
+bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin = false);
 
 // Largest dynamic LDS allocation a workgroup may request on the current device.
 int max_lds_bytes();

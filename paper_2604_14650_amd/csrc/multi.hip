@@ -10,12 +10,12 @@
 
 namespace planb {
 
-template <int B, int KPL, int R, bool WIDE, int BS>
+template <int B, int KPL, int R, bool WIDE, int BS, bool BIN>
 __global__ void __launch_bounds__(BS)
 multi_kernel(const TreeDesc* __restrict__ tables, uint32_t n_tables, const BurstRec* __restrict__ bursts,
              const uint32_t* __restrict__ count, uint32_t max_bursts)
 {
-    using D = Descent<B, KPL, R, WIDE>;
+    using D = Descent<B, KPL, R, WIDE, BIN>;
     extern __shared__ uint32_t lds_u32[];
     uint32_t* tile_off = lds_u32;                 // max_bursts + 1
     uint32_t* part = tile_off + max_bursts + 1;   // BS
@@ -61,17 +61,17 @@ multi_kernel(const TreeDesc* __restrict__ tables, uint32_t n_tables, const Burst
 
 namespace {
 
-template <int B, int KPL, int R, bool W, int BS>
+template <int B, int KPL, int R, bool W, int BS, bool BIN>
 struct MultiKernel {
     using Fn = void (*)(const TreeDesc*, uint32_t, const BurstRec*, const uint32_t*, uint32_t);
-    static Fn get() { return multi_kernel<B, KPL, R, W, BS>; }
+    static Fn get() { return multi_kernel<B, KPL, R, W, BS, BIN>; }
 };
 
 }  // namespace
 
 int plan_multi(int fanout, bool wide, const LookupTuning& tu, uint32_t max_bursts, MultiLaunch* L)
 {
-    L->fn = reinterpret_cast<const void*>(VariantTable<MultiKernel>::pick(fanout, tu.kpl, tu.R, wide, tu.block));
+    L->fn = reinterpret_cast<const void*>(VariantTable<MultiKernel>::pick(fanout, tu.kpl, tu.R, wide, tu.block, false));
     if (!L->fn) return fail(PLANB_EINVAL, "no multi-FIB kernel for this fanout / tuning");
     DevProps p;
     hipError_t e = dev_props(&p);

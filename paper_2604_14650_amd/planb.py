@@ -45,7 +45,8 @@ class planb_params_t(ctypes.Structure):
 
 class planb_tuning_t(ctypes.Structure):
     _fields_ = [("keys_per_lane", ctypes.c_uint32), ("lds_levels", ctypes.c_int32),
-                ("lookups_per_group", ctypes.c_uint32), ("block_threads", ctypes.c_uint32)]
+                ("lookups_per_group", ctypes.c_uint32), ("block_threads", ctypes.c_uint32),
+                ("lds_search", ctypes.c_uint32)]
 
 
 class planb_info_t(ctypes.Structure):
@@ -295,8 +296,8 @@ def planb_get_info(fib: Fib) -> dict:
 
 
 def planb_set_tuning(fib: Fib, keys_per_lane: int, lds_levels: int = -1, lookups_per_group: int = 2,
-                     block_threads: int = 512):
-    t = planb_tuning_t(keys_per_lane, lds_levels, lookups_per_group, block_threads)
+                     block_threads: int = 512, lds_search: int = 0):
+    t = planb_tuning_t(keys_per_lane, lds_levels, lookups_per_group, block_threads, lds_search)
     _check(_lib.planb_set_tuning(fib, ctypes.byref(t)))
 
 
@@ -304,7 +305,7 @@ def planb_get_tuning(fib: Fib) -> dict:
     t = planb_tuning_t()
     _check(_lib.planb_get_tuning(fib, ctypes.byref(t)))
     return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels,
-            "lookups_per_group": t.lookups_per_group, "block_threads": t.block_threads}
+            "lookups_per_group": t.lookups_per_group, "block_threads": t.block_threads, "lds_search": t.lds_search}
 
 
 def planb_layout(m: int, fanout: int, slots: int, trimmed: bool = True) -> dict:
@@ -398,8 +399,8 @@ def planb_autotune(fib: Fib, sample, n: int | None = None, reps: int = 3, stream
     _check(_lib.planb_autotune(fib, _dev_ptr(sample, "sample"), n, reps, _stream_handle(stream), ctypes.byref(r)))
     t = r.tuning
     return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels, "lookups_per_group": t.lookups_per_group,
-            "block_threads": t.block_threads, "ms_per_call": r.ms_per_call, "glps": r.glps,
-            "candidates": r.candidates}
+            "block_threads": t.block_threads, "lds_search": t.lds_search, "ms_per_call": r.ms_per_call,
+            "glps": r.glps, "candidates": r.candidates}
 
 
 def planb_train(fib: Fib, epochs: int = 0, batch: int = 0, lr: float = 0.0, segments: int = 0, seed: int = 0,

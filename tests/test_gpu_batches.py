@@ -40,6 +40,8 @@ def test_persistent_batches_device_descriptors(P, kind, seed):
     out = torch.full((len(addrs),), -1, dtype=torch.int16, device="cuda")
     for fanout in (8, 16, 32):
         h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+        if fanout == 16:  # hybrid descent: binary search in LDS, 2 lanes per lookup below
+            P.planb_set_tuning(h, 8, 2, 2, 512, 1)
         arr = P.batch_array(_batches(P, d, out, sizes, offs))
         raw = np.frombuffer(bytes(arr), dtype=np.uint8)
         desc = torch.from_numpy(raw.copy()).cuda()

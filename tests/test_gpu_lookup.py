@@ -14,6 +14,9 @@ M128 = (1 << 128) - 1
 
 VARIANTS = [(8, 1, 1), (8, 2, 2), (8, 4, 4), (8, 8, 1), (16, 1, 2), (16, 2, 1), (16, 4, 2), (16, 4, 4),
             (16, 8, 2), (16, 16, 1), (32, 1, 1), (32, 2, 2), (32, 4, 2), (32, 8, 4), (32, 16, 1)]
+# (fanout, keys_per_lane, R) with binary search in the LDS levels; keys_per_lane < fanout = hybrid
+BIN_VARIANTS = [(8, 8, 1), (8, 8, 2), (8, 4, 4), (8, 2, 2), (16, 16, 1), (16, 8, 2), (16, 4, 4),
+                (32, 32 // 2, 2), (32, 8, 1)]
 
 
 def gpu_lookup(P, fib, addrs, fanout=16, kpl=None, lds=-1, R=2, key_bits=0, block=512):
@@ -61,6 +64,21 @@ def test_tiny_all_addresses(P, tiny, fanout, kpl, R, key_bits):
         assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
 
 
+@pytest.mark.parametrize("key_bits", [0, 128])
+@pytest.mark.parametrize("fanout,kpl,R", BIN_VARIANTS)
+def test_tiny_binary_search_in_lds(P, tiny, fanout, kpl, R, key_bits):
+    fib, addrs, want = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
+    depth = P.planb_get_info(h)["depth"]
+    d = to_dev(addrs)
+    for lds in sorted({0, 1, depth - 1, depth}):
+        say(f"tiny binary key_bits={key_bits} fanout={fanout} kpl={kpl} R={R} lds={lds}")
+        P.planb_set_tuning(h, kpl, lds, R, 1024, 1)
+        out = out_u16(addrs.shape[0])
+        P.planb_lookup(h, d, addrs.shape[0], out)
+        assert np.array_equal(host_u16(out, addrs.shape[0]), want)
+
+
 def _edge_fibs():
     base = 0x20010DB8 << 96
     return {
@@ -104,6 +122,15 @@ def test_edge_cases(P, fanout, name):
             assert np.array_equal(got, want)
             got, _ = gpu_lookup(P, fib, q, fanout, kpl, 0, 1, key_bits, 1024)
             assert np.array_equal(got, want)
+    for key_bits in (0, 128):  # binary search in the LDS levels (whole tree, or with hybrid lower levels)
+        h = P.planb_build(p, L, nh, fanout=fanout, key_bits=key_bits)
+        depth = P.planb_get_info(h)["depth"]
+        d = to_dev(q)
+        for kpl, lds in ((fanout, depth), (fanout // 2, depth - 1), (fanout // 4, 0)):
+            P.planb_set_tuning(h, kpl, lds, 2, 512, 1)
+            out = out_u16(q.shape[0])
+            P.planb_lookup(h, d, q.shape[0], out)
+            assert np.array_equal(host_u16(out, q.shape[0]), want), (kpl, lds)
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097, 123457])
