@@ -139,17 +139,31 @@ long long planb_export_intervals(const planb_fib_t* fib, planb_addr_t* starts,
 
 #define PLANB_MAX_LEVELS 16
 
-/* Shape of a built tree (all node counts and offsets in nodes of `slots` keys). */
+/*
+ * Shape of a built tree.  Internal nodes have `slots` key slots (b - 1 keys
+ * and a sentinel) and are counted and offset in nodes.  Leaves follow them in
+ * the same slot array from slot leaf_base on, each leaf_slots slots long and
+ * holding leaf_keys interval starts (interval i in leaf i / leaf_keys).  In a
+ * built FIB a leaf also carries the next hops of its intervals: leaf_keys
+ * uint16 values right after its keys (byte leaf_keys * key_bits / 8 of the
+ * leaf), so that a lookup reads its answer from the line it already loaded.
+ * A FIB's leaf is max(b slots, 128 bytes) long and leaf_keys is the number
+ * of (key, next hop) pairs that fit; in the paper's layout (planb_layout)
+ * leaves are ordinary nodes: leaf_keys = b - 1, leaf_slots = slots.
+ */
 typedef struct planb_info {
     uint64_t intervals;                 /* m */
     uint32_t fanout;                    /* b */
-    uint32_t slots;                     /* key slots per node (b: k keys + 1 sentinel) */
+    uint32_t slots;                     /* key slots per internal node (b: k keys + 1 sentinel) */
     uint32_t depth;                     /* D: levels including the leaf level */
     uint32_t key_bits;                  /* 128 or 64, see planb_params_t */
-    uint64_t level_nodes[PLANB_MAX_LEVELS];      /* allocated nodes per level */
-    uint64_t level_offset[PLANB_MAX_LEVELS + 1]; /* first node of each level */
-    uint64_t key_bytes;                 /* device bytes of the key array */
-    uint64_t value_bytes;               /* device bytes of the next-hop array */
+    uint64_t level_nodes[PLANB_MAX_LEVELS];      /* allocated nodes per level (leaves last) */
+    uint64_t level_offset[PLANB_MAX_LEVELS + 1]; /* first node of each level (internal levels) */
+    uint64_t key_bytes;                 /* device bytes of the slot array (keys + in-leaf next hops) */
+    uint64_t value_bytes;               /* device bytes of the plain next-hop array */
+    uint32_t leaf_keys;                 /* interval starts per leaf */
+    uint32_t leaf_slots;                /* slots per leaf */
+    uint64_t leaf_base;                 /* slot index of leaf 0 */
 } planb_info_t;
 
 int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
@@ -426,11 +440,13 @@ long long planb_build_intervals(const planb_addr_t* prefixes, const uint8_t* len
  * planb_build_keys -- the linearized B+-tree key array (Section 3, "Linearized
  * B+-Tree", "Maintaining Structural Integrity", Algorithm 2's leaf fill and
  * separator pass) for m strictly increasing interval starts (starts[0] == 0),
- * laid out as planb_build lays it out on the device: node-major, `fanout`
- * 16-byte slots per node (fanout-1 keys + one sentinel 2^128-1 slot), levels
- * top-down, trailing all-sentinel nodes dropped.  keys: host, cap_keys records;
- * info (may be NULL) receives the shape.  Returns the number of key slots
- * (may exceed cap_keys, then nothing is written) or a negative status.
+ * laid out as planb_build lays out a FIB with 128-bit keys: internal nodes of
+ * `fanout` 16-byte slots (fanout-1 keys + one sentinel 2^128-1 slot), levels
+ * top-down, trailing all-sentinel nodes dropped, then the leaves (see
+ * planb_info_t; here every slot a built FIB fills with next hops holds the
+ * sentinel).  keys: host, cap_keys records; info (may be NULL) receives the
+ * shape.  Returns the number of slots (may exceed cap_keys, then nothing is
+ * written) or a negative status.
  */
 long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout,
                            planb_addr_t* keys, size_t cap_keys, planb_info_t* info);

@@ -38,7 +38,7 @@ int check_current_device(const planb_fib_t* fib)
 int deepest_lds_levels(const Layout& lay, size_t key_bytes, size_t budget)
 {
     int L = 0;
-    while (L < (int)lay.depth && lay.offset[L + 1] * lay.b * key_bytes <= budget) ++L;
+    while (L < (int)lay.depth && lay.prefix_slots(L + 1) * key_bytes <= budget) ++L;
     return L;
 }
 
@@ -51,8 +51,9 @@ void refresh_desc(planb_fib_t* f)
     t.m_minus_1 = f->iv.starts.size() - 1;
     t.depth = f->lay.depth;
     t.lds_levels = (uint32_t)f->lds_levels;
-    t.lds_nodes = (uint32_t)f->lay.offset[f->lds_levels];
+    t.lds_slots = (uint32_t)f->lay.prefix_slots(f->lds_levels);
     t.fanout = f->lay.b;
+    t.leaf_base = (uint32_t)f->lay.leaf_base();
     for (int l = 0; l < kDevMaxLevels; ++l) {
         t.off[l] = l < (int)f->lay.depth ? (uint32_t)f->lay.offset[l] : 0;
         t.last[l] = l < (int)f->lay.depth ? (uint32_t)(f->lay.nodes[l] - 1) : 0;
@@ -72,7 +73,7 @@ int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning
     int32_t lds_levels = tu.lds_levels;
     if (lds_levels < 0) lds_levels = deepest_lds_levels(f->lay, f->key_bytes_per_slot, 64 * 1024);
     if (lds_levels > (int32_t)f->lay.depth) return fail(PLANB_EINVAL, "lds_levels exceeds the tree depth");
-    const size_t bytes = f->lay.offset[lds_levels] * b * (size_t)f->key_bytes_per_slot;
+    const size_t bytes = f->lay.prefix_slots(lds_levels) * (size_t)f->key_bytes_per_slot;
     if (bytes > (size_t)max_lds_bytes())
         return fail(PLANB_ERANGE, "the top " + std::to_string(lds_levels) + " levels need " + std::to_string(bytes) +
                                       " bytes of LDS, more than a workgroup may allocate");
@@ -94,7 +95,10 @@ void layout_to_info(const Layout& lay, planb_info_t* info)
     for (uint32_t l = 0; l < lay.depth; ++l) info->level_nodes[l] = lay.nodes[l];
     for (uint32_t l = 0; l <= lay.depth; ++l) info->level_offset[l] = lay.offset[l];
     info->key_bits = 128;
-    info->key_bytes = lay.total_nodes() * lay.slots * 16ull;
+    info->key_bytes = lay.total_slots() * 16ull;
+    info->leaf_keys = lay.leaf_cap;
+    info->leaf_slots = lay.leaf_slots;
+    info->leaf_base = lay.leaf_base();
 }
 
 void clear_error()
@@ -153,38 +157,51 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
         delete f;
         return nullptr;
     }
-    if ((rc = plan_layout(m, p.fanout, p.fanout, true, &f->lay, &err)) != 0) {
-        fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
-        delete f;
-        return nullptr;
-    }
-    std::vector<U128> keys;
-    try {
-        fill_keys(f->iv, f->lay, &keys);
-    } catch (const std::bad_alloc&) {
-        fail(PLANB_ENOMEM, "out of host memory");
-        delete f;
-        return nullptr;
-    }
-    bool all_lo_zero = true;
-    for (const U128& k : f->iv.starts) all_lo_zero &= (k.lo == 0);
     if (p.key_bits != 0 && p.key_bits != 64 && p.key_bits != 128) {
         fail(PLANB_EINVAL, "key_bits must be 0, 64 or 128");
         delete f;
         return nullptr;
     }
+    bool all_lo_zero = true;
+    for (const U128& k : f->iv.starts) all_lo_zero &= (k.lo == 0);
     if (p.key_bits == 64 && !all_lo_zero) {
         fail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
         delete f;
         return nullptr;
     }
     const bool narrow = p.key_bits == 64 || (p.key_bits == 0 && all_lo_zero);
-    f->key_bytes_per_slot = narrow ? 8 : 16;
-    std::vector<uint64_t> keys_hi;
-    if (narrow) {
-        keys_hi.resize(keys.size());
-        for (size_t i = 0; i < keys.size(); ++i) keys_hi[i] = keys[i].hi;
-        std::vector<U128>().swap(keys);
+    const int kb = narrow ? 8 : 16;
+    f->key_bytes_per_slot = (uint32_t)kb;
+    if ((rc = plan_layout(m, p.fanout, p.fanout, (uint32_t)leaf_cap_for((int)p.fanout, kb),
+                          (uint32_t)leaf_slots_for((int)p.fanout, kb), true, &f->lay, &err)) != 0) {
+        fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
+        delete f;
+        return nullptr;
+    }
+    std::vector<uint8_t> image;  // the device slot array, leaves carrying their next hops
+    try {
+        std::vector<U128> keys;
+        fill_keys(f->iv, f->lay, &keys);
+        image.resize(keys.size() * kb);
+        if (narrow) {
+            uint64_t* d = reinterpret_cast<uint64_t*>(image.data());
+            for (size_t i = 0; i < keys.size(); ++i) d[i] = keys[i].hi;
+        } else {
+            std::memcpy(image.data(), keys.data(), image.size());
+        }
+        const uint64_t LC = f->lay.leaf_cap, LS = f->lay.leaf_slots, base = f->lay.leaf_base();
+        for (uint64_t q = 0; q < f->lay.leaves; ++q) {
+            uint8_t* hops = image.data() + (base + q * LS + LC) * kb;
+            for (uint64_t s = 0; s < LC; ++s) {
+                const uint64_t i = q * LC + s;
+                const uint16_t v = i < m ? f->iv.nh[i] : kNoRoute;
+                std::memcpy(hops + 2 * s, &v, 2);
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        fail(PLANB_ENOMEM, "out of host memory");
+        delete f;
+        return nullptr;
     }
     hipError_t e = hipGetDevice(&f->device);
     if (e != hipSuccess) {
@@ -192,8 +209,7 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
         delete f;
         return nullptr;
     }
-    const void* host_keys = narrow ? (const void*)keys_hi.data() : (const void*)keys.data();
-    const size_t kbytes = narrow ? keys_hi.size() * sizeof(uint64_t) : keys.size() * sizeof(U128);
+    const size_t kbytes = image.size();
     const size_t vbytes = ((m + 63) / 64) * 64 * sizeof(uint16_t);
     if ((e = hipMalloc(&f->d_keys, kbytes)) != hipSuccess || (e = hipMalloc(&f->d_vals, vbytes)) != hipSuccess) {
         fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -202,7 +218,7 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
     }
     f->key_bytes = kbytes;
     f->value_bytes = vbytes;
-    if ((e = hipMemcpy(f->d_keys, host_keys, kbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+    if ((e = hipMemcpy(f->d_keys, image.data(), kbytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(f->d_vals, 0xFF, vbytes)) != hipSuccess ||
         (e = hipMemcpy(f->d_vals, f->iv.nh.data(), m * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) {
         fail_hip(e, "uploading the tree");
@@ -313,10 +329,11 @@ long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout
         if (!(s[i - 1] < s[i])) return fail(PLANB_EINVAL, "starts must be strictly increasing");
     Layout lay;
     std::string err;
-    int rc = plan_layout(m, fanout, fanout, true, &lay, &err);
+    int rc = plan_layout(m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, 16),
+                         (uint32_t)leaf_slots_for((int)fanout, 16), true, &lay, &err);
     if (rc != 0) return fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
     if (info) layout_to_info(lay, info);
-    const size_t slots = lay.total_nodes() * fanout;
+    const size_t slots = lay.total_slots();
     if (!keys || slots > cap_keys) return (long long)slots;
     Intervals iv;
     iv.starts.assign(s, s + m);
@@ -346,7 +363,7 @@ int planb_layout(uint64_t m, uint32_t fanout, uint32_t slots, int trimmed, planb
     if (!info) return fail(PLANB_EINVAL, "NULL info");
     Layout lay;
     std::string err;
-    int rc = plan_layout(m, fanout, slots, trimmed != 0, &lay, &err);
+    int rc = plan_layout(m, fanout, slots, fanout - 1, slots, trimmed != 0, &lay, &err);
     if (rc != 0) return fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
     layout_to_info(lay, info);
     return PLANB_OK;

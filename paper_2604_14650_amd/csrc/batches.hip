@@ -95,7 +95,7 @@ int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
     DevProps p;
     hipError_t e = dev_props(&p);
     if (e != hipSuccess) return fail_hip(e, "device properties");
-    L->lds = (size_t)t.lds_nodes * t.fanout * t.key_bytes + ((size_t)max_batches + 1 + tu.block) * 4;
+    L->lds = (size_t)t.lds_slots * t.key_bytes + ((size_t)max_batches + 1 + tu.block) * 4;
     if (L->lds > (size_t)p.max_lds)
         return fail(PLANB_ERANGE, "LDS levels plus " + std::to_string(max_batches) +
                                       " batch offsets exceed the workgroup LDS limit; lower lds_levels or max_batches");

@@ -128,21 +128,23 @@ int make_intervals(const U128* prefixes, const uint8_t* lengths, const uint16_t*
     return 0;
 }
 
-int plan_layout(uint64_t m, uint32_t b, uint32_t slots, bool trimmed, Layout* lay, std::string* err)
+int plan_layout(uint64_t m, uint32_t b, uint32_t slots, uint32_t leaf_cap, uint32_t leaf_slots, bool trimmed,
+                Layout* lay, std::string* err)
 {
-    if (b < 2 || slots < b - 1 || m == 0) {
-        *err = "layout needs m >= 1, fanout >= 2 and slots >= fanout - 1";
+    if (b < 2 || slots < b - 1 || m == 0 || leaf_cap == 0 || leaf_slots < leaf_cap) {
+        *err = "layout needs m >= 1, fanout >= 2, slots >= fanout - 1 and leaf slots >= leaf keys >= 1";
         return -1;
     }
-    const uint64_t k = b - 1;
     Layout L;
     L.b = b;
     L.slots = slots;
+    L.leaf_cap = leaf_cap;
+    L.leaf_slots = leaf_slots;
     L.m = m;
-    L.leaves = (m + k - 1) / k;
-    // smallest D with k * b^(D-1) >= m
+    L.leaves = (m + leaf_cap - 1) / leaf_cap;
+    // smallest D with leaf_cap * b^(D-1) >= m
     uint32_t D = 1;
-    uint64_t cap = k;
+    uint64_t cap = leaf_cap;
     while (cap < m) {
         if (D >= (uint32_t)kMaxLevels) {
             *err = "tree deeper than the supported maximum";
@@ -173,10 +175,11 @@ int plan_layout(uint64_t m, uint32_t b, uint32_t slots, bool trimmed, Layout* la
 void fill_keys(const Intervals& iv, const Layout& lay, std::vector<U128>* keys)
 {
     const uint64_t b = lay.b, S = lay.slots, k = b - 1, D = lay.depth, m = iv.starts.size();
-    keys->assign(lay.total_nodes() * S, kSentinel);
+    const uint64_t LC = lay.leaf_cap, LS = lay.leaf_slots;
+    keys->assign(lay.total_slots(), kSentinel);
     U128* K = keys->data();
-    const uint64_t leaf0 = lay.offset[D - 1];
-    for (uint64_t i = 0; i < m; ++i) K[(leaf0 + i / k) * S + i % k] = iv.starts[i];
+    const uint64_t leaf0 = lay.leaf_base();
+    for (uint64_t i = 0; i < m; ++i) K[leaf0 + (i / LC) * LS + i % LC] = iv.starts[i];
     // internal levels: separator j-1 of node q = first key of the leftmost
     // leaf under child q*b + j
     uint64_t span = 1;  // leaves under one node of level l + 1
@@ -184,7 +187,7 @@ void fill_keys(const Intervals& iv, const Layout& lay, std::vector<U128>* keys)
         for (uint64_t q = 0; q < lay.nodes[l]; ++q) {
             for (uint64_t j = 1; j <= k; ++j) {
                 uint64_t leaf = (q * b + j) * span;
-                if (leaf < lay.leaves) K[(lay.offset[l] + q) * S + (j - 1)] = iv.starts[leaf * k];
+                if (leaf < lay.leaves) K[(lay.offset[l] + q) * S + (j - 1)] = iv.starts[leaf * LC];
             }
         }
         span *= b;

@@ -33,21 +33,30 @@ struct Intervals {
 int make_intervals(const U128* prefixes, const uint8_t* lengths, const uint16_t* next_hops,
                    size_t n, bool merge_equal, Intervals* out, std::string* err);
 
-// Shape of a tree over m keys: fanout b, `slots` key slots per node.
+// Shape of a tree over m keys: internal nodes of fanout b with `slots` key
+// slots each; leaves of `leaf_slots` slots holding `leaf_cap` keys each.
 struct Layout {
     uint32_t b = 0, slots = 0, depth = 0;
+    uint32_t leaf_cap = 0, leaf_slots = 0;
     uint64_t m = 0, leaves = 0;
-    uint64_t nodes[kMaxLevels] = {};
-    uint64_t offset[kMaxLevels + 1] = {};
-    uint64_t total_nodes() const { return offset[depth]; }
+    uint64_t nodes[kMaxLevels] = {};       // nodes per level, the leaf level last
+    uint64_t offset[kMaxLevels + 1] = {};  // first node of each level (internal levels, then leaves)
+    uint64_t internal_nodes() const { return offset[depth - 1]; }
+    // slot of leaf 0's first key: the internal slots rounded up to a whole leaf,
+    // so that leaves of 128 bytes never straddle a cache line
+    uint64_t leaf_base() const { return (internal_nodes() * slots + leaf_slots - 1) / leaf_slots * leaf_slots; }
+    uint64_t total_slots() const { return leaf_base() + leaves * leaf_slots; }
+    // slots occupied by the top `levels` levels (the whole array when levels = depth)
+    uint64_t prefix_slots(uint32_t levels) const { return levels >= depth ? total_slots() : offset[levels] * slots; }
 };
 
 // trimmed: drop trailing internal nodes holding only sentinels.
-int plan_layout(uint64_t m, uint32_t b, uint32_t slots, bool trimmed, Layout* lay, std::string* err);
+int plan_layout(uint64_t m, uint32_t b, uint32_t slots, uint32_t leaf_cap, uint32_t leaf_slots, bool trimmed,
+                Layout* lay, std::string* err);
 
-// Fills the node-major key array (slots = b: k = b-1 keys + one sentinel slot
-// per node).  Leaves hold the interval starts in order, k per node; separator
-// j-1 of an internal node is the smallest key under its child j.
+// Fills the slot array (every unused slot is the sentinel 2^128 - 1).  Leaf q
+// holds the interval starts q*leaf_cap .. in its first leaf_cap slots;
+// separator j-1 of an internal node is the smallest key under its child j.
 void fill_keys(const Intervals& iv, const Layout& lay, std::vector<U128>* keys);
 
 }  // namespace planb

@@ -5,8 +5,8 @@
 // mapped onto a wave64: G = B / KPL lanes cooperate on one lookup.  Each lane
 // compares KPL keys of the current node with the address x (arranged so that a
 // group's loads are contiguous), the group adds its counts with DPP, and the
-// count c of keys <= x selects child q*B + c.  At the leaf the interval index
-// is q*(B-1) + c - 1.  Node indices are clamped to each level's last allocated
+// count c of keys <= x selects child q*B + c.  At leaf q (kLC keys and their
+// next hops) the interval index is q*kLC + c - 1.  Node indices are clamped to each level's last allocated
 // node, which only alters the path of an address equal to the sentinel padding
 // (all ones in the compared width); that address's answer is the last interval.
 #pragma once
@@ -25,15 +25,18 @@ struct Descent {
     // LDS-staged levels alone by binary search, then groups of G lanes take
     // the lookups over, one owner lane's at a time, for the lower levels.
     static constexpr bool kHybrid = BIN && KPL < B;
+    static constexpr int kLS = leaf_slots_for(B, (int)sizeof(K));  // slots per leaf
+    static constexpr int kLC = leaf_cap_for(B, (int)sizeof(K));    // keys per leaf
+    static constexpr int kLPER = kLS / G;                          // leaf slots per lane
     static constexpr uint64_t kStep = kHybrid ? 64ull * R : (uint64_t)LPW * R;  // lookups per wavefront step
 
     // Bytes of LDS the top levels of t take.
-    static __host__ __device__ size_t lds_bytes(const TreeDesc& t) { return (size_t)t.lds_nodes * B * sizeof(K); }
+    static __host__ __device__ size_t lds_bytes(const TreeDesc& t) { return (size_t)t.lds_slots * sizeof(K); }
 
-    // Copy the first t.lds_nodes nodes (the top t.lds_levels levels) to LDS.
+    // Copy the first t.lds_slots slots (the top t.lds_levels levels) to LDS.
     static __device__ void stage(const TreeDesc& t, uint4* lds_raw, int tid, int nthreads)
     {
-        const uint32_t units = t.lds_nodes * (uint32_t)(B * sizeof(K) / 16);
+        const uint32_t units = (uint32_t)(t.lds_slots * sizeof(K) / 16);
         const uint4* src = static_cast<const uint4*>(t.keys);
         for (uint32_t i = tid; i < units; i += nthreads) lds_raw[i] = src[i];
     }
@@ -74,6 +77,97 @@ struct Descent {
         return (uint32_t)group_sum<G>(cnt);
     }
 
+    // Search of the leaf at slot node0 by the G lanes of a group (lane j of
+    // the group is `j`, its first lane `lane0`): counts the keys <= x among the
+    // first kLC slots, turns the count into the interval index (*idx) and
+    // returns that interval's next hop.  The next hops sit in the same leaf
+    // after the keys, so the words the lanes already loaded hold it: the lane
+    // holding it picks the word out of its registers and the group reads it
+    // with one cross-lane shuffle instead of a second memory access.
+    static __device__ __forceinline__ uint16_t leaf_search(const TreeDesc& t, const K* keys, size_t node0, uint32_t q,
+                                                           int j, int lane0, uint64_t xhi, uint64_t xlo,
+                                                           uint64_t* idx)
+    {
+        constexpr int kb = (int)sizeof(K);
+        constexpr bool kContig = !WIDE && kLPER >= 2;  // lane j holds slots [j*kLPER, (j+1)*kLPER)
+        constexpr int kW = kLPER * kb / 4;              // 32-bit words per lane
+        uint32_t w[kW];
+        int cnt = 0;
+        if constexpr (kContig) {
+            const uint4* p = reinterpret_cast<const uint4*>(keys + node0 + (size_t)j * kLPER);
+#pragma unroll
+            for (int s = 0; s < kLPER / 2; ++s) {
+                const int slot = j * kLPER + 2 * s;
+                const uint4 v = p[s];
+                w[4 * s] = v.x;
+                w[4 * s + 1] = v.y;
+                w[4 * s + 2] = v.z;
+                w[4 * s + 3] = v.w;
+                cnt += (slot < kLC && (((uint64_t)v.y << 32) | v.x) <= xhi) +
+                       (slot + 1 < kLC && (((uint64_t)v.w << 32) | v.z) <= xhi);
+            }
+        } else {  // lane j holds slots j, G + j, 2G + j, ...
+#pragma unroll
+            for (int s = 0; s < kLPER; ++s) {
+                const int slot = s * G + j;
+                const K k = keys[node0 + slot];
+                if constexpr (WIDE) {  // uint4: the key's four words in memory order
+                    w[4 * s] = k.x;
+                    w[4 * s + 1] = k.y;
+                    w[4 * s + 2] = k.z;
+                    w[4 * s + 3] = k.w;
+                } else {
+                    w[2 * s] = (uint32_t)k;
+                    w[2 * s + 1] = (uint32_t)(k >> 32);
+                }
+                cnt += slot < kLC ? KF::le(k, xhi, xlo) : 0;
+            }
+        }
+        const uint32_t c = (uint32_t)group_sum<G>(cnt);
+        *idx = leaf_index(t, q, c);
+        const uint32_t pos = (uint32_t)(*idx - (uint64_t)q * kLC);  // in [0, kLC)
+        const uint32_t byte = kLC * kb + 2 * pos;                    // of the next hop, in the leaf
+        uint32_t owner, word;
+        if constexpr (kContig) {
+            owner = byte / (kLPER * kb);
+            word = (byte % (kLPER * kb)) / 4;
+        } else {
+            const uint32_t slot = byte / kb;
+            owner = slot % G;
+            word = (slot / G) * (kb / 4) + (byte % kb) / 4;
+        }
+        uint32_t sel = 0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) sel = (uint32_t)k == word ? w[k] : sel;
+        if constexpr (G > 1) sel = (uint32_t)__shfl((int)sel, lane0 + (int)owner, 64);
+        return (uint16_t)(sel >> (16 * (pos & 1)));
+    }
+
+    // One lane: the same count by branch-free binary search (slots >= kLC act
+    // as larger than every address).
+    static __device__ __forceinline__ uint32_t lane_leaf_bincount(const K* keys, size_t node0, uint64_t xhi,
+                                                                  uint64_t xlo)
+    {
+        uint32_t c = 0;
+#pragma unroll
+        for (int step = kLS / 2; step >= 1; step >>= 1) {
+            const uint32_t probe = c + step - 1;
+            c += (probe < (uint32_t)kLC && KF::le(keys[node0 + probe], xhi, xlo)) ? step : 0;
+        }
+        return c;
+    }
+
+    // Interval index and next hop of the leaf result (c keys <= x in leaf q).
+    static __device__ __forceinline__ uint64_t leaf_index(const TreeDesc& t, uint32_t q, uint32_t c)
+    {
+        const uint64_t idx = (uint64_t)q * kLC + c - 1;  // c >= 1: interval 0 starts at 0
+        return idx < t.m_minus_1 ? idx : t.m_minus_1;
+    }
+    static __device__ __forceinline__ uint16_t leaf_hop(const K* keys, size_t node0, uint32_t q, uint64_t idx)
+    {
+        return reinterpret_cast<const uint16_t*>(keys + node0 + kLC)[idx - (uint64_t)q * kLC];
+    }
+
     template <bool FROM_LDS>
     static __device__ __forceinline__ uint32_t lane_bincount(const K* keys, size_t node0, uint64_t xhi, uint64_t xlo)
     {
@@ -90,12 +184,12 @@ struct Descent {
         return ((uint64_t)hi << 32) | lo;
     }
 
-    static __device__ __forceinline__ void store(const TreeDesc& t, void* out, int index_out, uint64_t i, uint64_t idx)
+    static __device__ __forceinline__ void store(void* out, int index_out, uint64_t i, uint64_t idx, uint16_t hop)
     {
         if (index_out)
             __builtin_nontemporal_store((uint32_t)idx, static_cast<uint32_t*>(out) + i);
         else
-            __builtin_nontemporal_store(t.vals[idx], static_cast<uint16_t*>(out) + i);
+            __builtin_nontemporal_store(hop, static_cast<uint16_t*>(out) + i);
     }
 
     static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const K* lds_keys, const u64x2* addrs,
@@ -121,14 +215,13 @@ struct Descent {
                 q[r] = min(q[r] * B + lane_bincount<true>(lds_keys, (size_t)(off + q[r]) * B, xh[r], xl[r]), lim);
         }
         if (t.lds_levels >= t.depth) {  // the whole tree is in LDS
-            const uint32_t loff = t.off[t.depth - 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const uint32_t c = lane_bincount<true>(lds_keys, (size_t)(loff + q[r]) * B, xh[r], xl[r]);
-                uint64_t idx = (uint64_t)q[r] * (B - 1) + c - 1;
-                idx = idx < t.m_minus_1 ? idx : t.m_minus_1;
+                const size_t node0 = t.leaf_base + (size_t)q[r] * kLS;
+                const uint32_t c = lane_leaf_bincount(lds_keys, node0, xh[r], xl[r]);
+                const uint64_t idx = leaf_index(t, q[r], c);
                 const uint64_t i = base + (uint64_t)r * 64 + lane;
-                if (i < n) store(t, out, index_out, i, idx);
+                if (i < n) store(out, index_out, i, idx, leaf_hop(lds_keys, node0, q[r], idx));
             }
             return;
         }
@@ -152,14 +245,13 @@ struct Descent {
             for (int u = 0; u < T; ++u)
                 p[u] = min(p[u] * B + node_count<false>(gkeys, (size_t)(off + p[u]) * B, j, yh[u], yl[u]), lim);
         }
-        const uint32_t loff = t.off[t.depth - 1];
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            const uint32_t c = node_count<false>(gkeys, (size_t)(loff + p[u]) * B, j, yh[u], yl[u]);
-            uint64_t idx = (uint64_t)p[u] * (B - 1) + c - 1;
-            idx = idx < t.m_minus_1 ? idx : t.m_minus_1;
+            uint64_t idx;
+            const uint16_t hop =
+                leaf_search(t, gkeys, t.leaf_base + (size_t)p[u] * kLS, p[u], j, lane - j, yh[u], yl[u], &idx);
             const uint64_t i = base + (uint64_t)(u / G) * 64 + (u % G) * LPW + grp;
-            if (j == 0 && i < n) store(t, out, index_out, i, idx);
+            if (j == 0 && i < n) store(out, index_out, i, idx, hop);
         }
     }
 
@@ -198,22 +290,20 @@ struct Descent {
                     q[r] = min(q[r] * B + node_count<false>(gkeys, (size_t)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
             }
         }
-        const uint32_t loff = t.off[t.depth - 1];
         const bool leaf_lds = t.lds_levels >= t.depth;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const size_t nb = (size_t)(loff + q[r]) * B;
-            const uint32_t c = leaf_lds ? node_count<true>(lds_keys, nb, j, xhi[r], xlo[r])
-                                        : node_count<false>(gkeys, nb, j, xhi[r], xlo[r]);
-            uint64_t idx = (uint64_t)q[r] * (B - 1) + c - 1;  // c >= 1: interval 0 starts at 0
-            idx = idx < t.m_minus_1 ? idx : t.m_minus_1;
-            const uint64_t i = base + (uint64_t)r * LPW + grp;
-            if (j == 0 && i < n) {
-                if (index_out)
-                    __builtin_nontemporal_store((uint32_t)idx, static_cast<uint32_t*>(out) + i);
-                else
-                    __builtin_nontemporal_store(t.vals[idx], static_cast<uint16_t*>(out) + i);
+            const size_t node0 = t.leaf_base + (size_t)q[r] * kLS;
+            uint64_t idx;
+            uint16_t hop;
+            if (BIN && KPL == B && leaf_lds) {
+                idx = leaf_index(t, q[r], lane_leaf_bincount(lds_keys, node0, xhi[r], xlo[r]));
+                hop = leaf_hop(lds_keys, node0, q[r], idx);
+            } else {
+                hop = leaf_search(t, leaf_lds ? lds_keys : gkeys, node0, q[r], j, lane - j, xhi[r], xlo[r], &idx);
             }
+            const uint64_t i = base + (uint64_t)r * LPW + grp;
+            if (j == 0 && i < n) store(out, index_out, i, idx, hop);
         }
     }
 };

@@ -12,18 +12,31 @@ constexpr int kDevMaxLevels = 16;
 // A 16-byte address record {hi, lo} as a native vector (for streaming loads).
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
+// Leaf nodes hold keys and, after the keys, one uint16 next hop per key, so a
+// lookup reads its next hop from the line that held its leaf.  A leaf spans
+// max(B slots, 128 bytes) and holds as many (key, next hop) pairs as fit.
+__host__ __device__ constexpr int leaf_slots_for(int B, int key_bytes)
+{
+    return B * key_bytes >= 128 ? B : 128 / key_bytes;
+}
+__host__ __device__ constexpr int leaf_cap_for(int B, int key_bytes)
+{
+    return leaf_slots_for(B, key_bytes) * key_bytes / (key_bytes + 2);
+}
+
 // What a kernel needs to descend one built tree.  Passed by value (kernarg).
 struct TreeDesc {
-    const void* keys;        // node-major key array; node = B slots of key_bytes
+    const void* keys;        // slot array: internal nodes of B slots, then leaves
     uint32_t key_bytes;      // 16: full 128-bit keys {hi, lo}; 8: the hi word only (every key's lo is 0)
-    const uint16_t* vals;    // next hop of interval i at vals[i]
+    const uint16_t* vals;    // next hop of interval i at vals[i] (also stored in the leaves)
     uint64_t m_minus_1;      // last interval index
     uint32_t depth;          // D, levels including the leaf level
     uint32_t lds_levels;     // top levels staged in LDS (<= depth)
-    uint32_t lds_nodes;      // nodes in those levels (= off[lds_levels])
+    uint32_t lds_slots;      // slots in those levels (a prefix of the slot array)
     uint32_t fanout;         // B (checked against the kernel's template)
-    uint32_t off[kDevMaxLevels];   // first node of each level
-    uint32_t last[kDevMaxLevels];  // last allocated node of each level
+    uint32_t leaf_base;      // slot of the first leaf
+    uint32_t off[kDevMaxLevels];   // first node of each internal level
+    uint32_t last[kDevMaxLevels];  // last allocated node of each level (the leaf level last)
 };
 
 // Key formats.  Wide: the 16-byte record {hi, lo}, compared as a 128-bit

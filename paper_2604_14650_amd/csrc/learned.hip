@@ -153,8 +153,10 @@ __device__ inline uint64_t predict_position(float y, uint64_t m)
 template <int B, bool WIDE>
 __device__ inline typename KeyFmt<WIDE>::T leaf_key(const TreeDesc& t, uint64_t i)
 {
+    constexpr int kb = (int)sizeof(typename KeyFmt<WIDE>::T);
+    constexpr uint64_t LC = leaf_cap_for(B, kb), LS = leaf_slots_for(B, kb);
     const auto* keys = static_cast<const typename KeyFmt<WIDE>::T*>(t.keys);
-    return keys[(size_t)(t.off[t.depth - 1] + i / (B - 1)) * B + i % (B - 1)];
+    return keys[t.leaf_base + (i / LC) * LS + i % LC];
 }
 
 // Plain one-lane descent (every key of each node), used for fallbacks.
@@ -171,11 +173,12 @@ __device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_
         for (int s = 0; s < B; ++s) c += KF::le(keys[nb + s], xhi, xlo);
         q = min(q * B + c, t.last[l + 1]);
     }
-    const size_t nb = (size_t)(t.off[t.depth - 1] + q) * B;
+    constexpr int LC = leaf_cap_for(B, (int)sizeof(typename KF::T)), LS = leaf_slots_for(B, (int)sizeof(typename KF::T));
+    const size_t nb = t.leaf_base + (size_t)q * LS;
     uint32_t c = 0;
 #pragma unroll
-    for (int s = 0; s < B; ++s) c += KF::le(keys[nb + s], xhi, xlo);
-    const uint64_t idx = (uint64_t)q * (B - 1) + c - 1;
+    for (int s = 0; s < LC; ++s) c += KF::le(keys[nb + s], xhi, xlo);
+    const uint64_t idx = (uint64_t)q * LC + c - 1;
     return idx < t.m_minus_1 ? idx : t.m_minus_1;
 }
 

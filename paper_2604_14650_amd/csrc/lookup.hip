@@ -129,7 +129,7 @@ hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* 
     DevProps p;
     hipError_t e = dev_props(&p);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)t.lds_nodes * t.fanout * t.key_bytes;
+    const size_t lds = (size_t)t.lds_slots * t.key_bytes;
     if (lds > (size_t)p.max_lds) return hipErrorInvalidValue;
     int nb = 1;
     if ((e = occupancy(reinterpret_cast<const void*>(fn), tu.block, lds, &nb)) != hipSuccess) return e;

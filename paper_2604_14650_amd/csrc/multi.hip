@@ -165,7 +165,7 @@ int planb_tableset_set(planb_tableset_t* ts, uint32_t slot, const planb_fib_t* f
         }
         d = fib->desc;
         d.lds_levels = 0;
-        d.lds_nodes = 0;
+        d.lds_slots = 0;
     }
     hipError_t e = hipMemcpy(ts->dev + slot, &d, sizeof(TreeDesc), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail_hip(e, "writing a table descriptor");

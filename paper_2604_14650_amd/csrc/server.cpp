@@ -119,9 +119,13 @@ void server_release(planb_server_t* s)
 // Device bytes planb_build will allocate for the table (same layout arithmetic).
 size_t table_bytes(const Table& t, uint32_t fanout, uint32_t key_bits)
 {
-    planb_info_t info;
-    if (planb_layout(t.m, fanout, fanout, 1, &info) != PLANB_OK) return SIZE_MAX;
-    return info.key_bytes / 128 * key_bits + (t.m + 63) / 64 * 64 * 2;
+    const int kb = (int)key_bits / 8;
+    Layout lay;
+    std::string err;
+    if (plan_layout(t.m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, kb),
+                    (uint32_t)leaf_slots_for((int)fanout, kb), true, &lay, &err) != 0)
+        return SIZE_MAX;
+    return lay.total_slots() * kb + (t.m + 63) / 64 * 64 * 2;
 }
 
 // Make table `id` resident; false if the budget cannot be met right now

@@ -54,7 +54,8 @@ class planb_info_t(ctypes.Structure):
                 ("depth", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
                 ("level_nodes", ctypes.c_uint64 * PLANB_MAX_LEVELS),
                 ("level_offset", ctypes.c_uint64 * (PLANB_MAX_LEVELS + 1)),
-                ("key_bytes", ctypes.c_uint64), ("value_bytes", ctypes.c_uint64)]
+                ("key_bytes", ctypes.c_uint64), ("value_bytes", ctypes.c_uint64),
+                ("leaf_keys", ctypes.c_uint32), ("leaf_slots", ctypes.c_uint32), ("leaf_base", ctypes.c_uint64)]
 
 
 class planb_batch_t(ctypes.Structure):
@@ -286,7 +287,8 @@ def _info_dict(info: planb_info_t) -> dict:
             "key_bits": info.key_bits,
             "level_nodes": [int(info.level_nodes[i]) for i in range(D)],
             "level_offset": [int(info.level_offset[i]) for i in range(D + 1)],
-            "key_bytes": int(info.key_bytes), "value_bytes": int(info.value_bytes)}
+            "key_bytes": int(info.key_bytes), "value_bytes": int(info.value_bytes),
+            "leaf_keys": int(info.leaf_keys), "leaf_slots": int(info.leaf_slots), "leaf_base": int(info.leaf_base)}
 
 
 def planb_get_info(fib: Fib) -> dict:

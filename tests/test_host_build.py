@@ -196,20 +196,26 @@ def test_trimmed_layout_depth(m, b):
 
 
 # ------------------------------------------------------------- key array
+# Leaves of a FIB with 128-bit keys: max(b slots, 128 bytes) long, holding as
+# many 16-byte keys plus 2-byte next hops as fit (written out per fanout).
+LEAF_SHAPE_128 = {8: (7, 8), 16: (14, 16), 32: (28, 32)}  # b -> (keys, slots)
+
+
 def _descend(keys, info, x):
     """Count-based descent over the host key array (the semantics the kernel
-    implements): c = #{slots <= x}, child q*b + c clamped, leaf idx q*k + c - 1."""
-    b = info["fanout"]
-    D = info["depth"]
+    implements): c = #{keys <= x}, child q*b + c clamped to the level's last
+    node; at leaf q with L keys the interval is q*L + c - 1 (clamped to m-1)."""
+    b, D = info["fanout"], info["depth"]
     off, nodes = info["level_offset"], info["level_nodes"]
+    L, LS, base = info["leaf_keys"], info["leaf_slots"], info["leaf_base"]
     q = 0
-    for l in range(D):
-        base = (off[l] + q) * b
-        c = sum(1 for s in range(b) if keys[base + s] <= x)
-        if l + 1 < D:
-            q = min(q * b + c, nodes[l + 1] - 1)
-        else:
-            return min(q * (b - 1) + c - 1, info["intervals"] - 1)
+    for l in range(D - 1):
+        node = (off[l] + q) * b
+        c = sum(1 for s in range(b) if keys[node + s] <= x)
+        q = min(q * b + c, nodes[l + 1] - 1)
+    leaf = base + q * LS
+    c = sum(1 for s in range(L) if keys[leaf + s] <= x)
+    return min(q * L + c - 1, info["intervals"] - 1)
 
 
 @pytest.mark.parametrize("b", [8, 16, 32])
@@ -226,17 +232,27 @@ def test_key_array_structure_and_descent(b, m):
     keys_arr, info = P.planb_build_keys(starts, b)
     keys = ints(keys_arr)
     D, off, nodes = info["depth"], info["level_offset"], info["level_nodes"]
+    L, LS, base = info["leaf_keys"], info["leaf_slots"], info["leaf_base"]
+    assert (L, LS) == LEAF_SHAPE_128[b]
+    leaves = -(-m // L)
+    assert nodes[D - 1] == leaves
+    # leaves start at the first whole leaf after the internal nodes
+    assert base % LS == 0 and off[D - 1] * b <= base < off[D - 1] * b + LS
+    assert len(keys) == base + leaves * LS
     k = b - 1
-    assert len(keys) == off[D] * b
-    for q in range(off[D]):
-        assert keys[q * b + k] == M128  # sentinel slot
-    leaf_keys = [keys[(off[D - 1] + i // k) * b + i % k] for i in range(m)]
+    for q in range(off[D - 1]):
+        assert keys[q * b + k] == M128  # sentinel slot of every internal node
+    assert all(keys[s] == M128 for s in range(off[D - 1] * b, base))  # alignment gap
+    leaf_keys = [keys[base + (i // L) * LS + i % L] for i in range(m)]
     assert leaf_keys == vals
+    for q in range(leaves):  # unused key slots and the next-hop area hold sentinels here
+        used = min(L, m - q * L)
+        assert all(keys[base + q * LS + s] == M128 for s in range(used, LS))
 
     def subtree_min(l, q):
         while l < D - 1:
             l, q = l + 1, q * b
-        return keys[(off[D - 1] + q) * b] if q < nodes[D - 1] else M128
+        return keys[base + q * LS] if q < leaves else M128
 
     for l in range(D - 1):
         for q in range(nodes[l]):
