@@ -451,6 +451,22 @@ long long planb_build_intervals(const planb_addr_t* prefixes, const uint8_t* len
 long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout,
                            planb_addr_t* keys, size_t cap_keys, planb_info_t* info);
 
+/*
+ * planb_build_image -- the exact device slot array planb_build uploads for m
+ * strictly increasing interval starts (starts[0] == 0) and their next hops:
+ * the key array above in key_bits-wide slots (64: the high word of each key;
+ * 0 picks 64 when every start's low word is zero, as planb_build does) with
+ * every leaf carrying its next hops (see planb_info_t).  With 64-bit slots a
+ * leaf is a run of 32-byte blocks of three keys and their three uint16 next
+ * hops; with 128-bit slots the keys come first, then the next hops.  Slots
+ * past the last interval hold the all-ones sentinel and next hop 0xFFFF.
+ * image: host, cap_bytes bytes; info (may be NULL) receives the shape.
+ * Returns the image size in bytes (may exceed cap_bytes, then nothing is
+ * written) or a negative status.
+ */
+long long planb_build_image(const planb_addr_t* starts, const uint16_t* next_hops, size_t m, uint32_t fanout,
+                            uint32_t key_bits, void* image, size_t cap_bytes, planb_info_t* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,6 +109,50 @@ void clear_error()
 
 uint32_t default_kpl(uint32_t b) { return b == 8 ? 2 : b == 16 ? 4 : 8; }
 
+int plan_fib_layout(uint64_t m, uint32_t fanout, int key_bytes, Layout* lay, std::string* err)
+{
+    return plan_layout(m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, key_bytes),
+                       (uint32_t)leaf_slots_for((int)fanout, key_bytes), true, lay, err);
+}
+
+// The device slot array of a FIB: the keys of fill_keys in key_bytes-wide
+// slots (8: the hi word of every key), and each leaf's next hops written
+// where the leaf format puts them (kNoRoute past the last interval).
+void build_image(const Intervals& iv, const Layout& lay, int key_bytes, std::vector<uint8_t>* image)
+{
+    std::vector<U128> keys;
+    fill_keys(iv, lay, key_bytes, &keys);
+    image->assign(keys.size() * key_bytes, 0);
+    if (key_bytes == 8) {
+        uint64_t* d = reinterpret_cast<uint64_t*>(image->data());
+        for (size_t i = 0; i < keys.size(); ++i) d[i] = keys[i].hi;
+    } else {
+        std::memcpy(image->data(), keys.data(), image->size());
+    }
+    const uint64_t m = iv.starts.size(), LC = lay.leaf_cap, LS = lay.leaf_slots, base = lay.leaf_base();
+    for (uint64_t q = 0; q < lay.leaves; ++q) {
+        uint8_t* leaf = image->data() + (base + q * LS) * key_bytes;
+        for (uint64_t s = 0; s < LC; ++s) {
+            const uint64_t i = q * LC + s;
+            const uint16_t v = i < m ? iv.nh[i] : kNoRoute;
+            std::memcpy(leaf + leaf_hop_byte((uint32_t)s, key_bytes, (int)LC), &v, 2);
+        }
+    }
+}
+
+// Key width for a set of interval starts: 8 bytes when asked (and exact) or
+// when every start has a zero low word and nothing was asked; else 16.
+int choose_key_bytes(const Intervals& iv, uint32_t key_bits, int* key_bytes)
+{
+    if (key_bits != 0 && key_bits != 64 && key_bits != 128) return fail(PLANB_EINVAL, "key_bits must be 0, 64 or 128");
+    bool all_lo_zero = true;
+    for (const U128& k : iv.starts) all_lo_zero &= (k.lo == 0);
+    if (key_bits == 64 && !all_lo_zero)
+        return fail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
+    *key_bytes = key_bits == 64 || (key_bits == 0 && all_lo_zero) ? 8 : 16;
+    return PLANB_OK;
+}
+
 }  // namespace planb
 
 extern "C" {
@@ -152,52 +196,25 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
         return nullptr;
     }
     const uint64_t m = f->iv.starts.size();
-    if (m >= (1ull << 32)) {
-        fail(PLANB_ERANGE, "too many intervals for 32-bit interval indices");
+    if (m >= (1ull << 31)) {
+        fail(PLANB_ERANGE, "too many intervals (at most 2^31 - 1)");
         delete f;
         return nullptr;
     }
-    if (p.key_bits != 0 && p.key_bits != 64 && p.key_bits != 128) {
-        fail(PLANB_EINVAL, "key_bits must be 0, 64 or 128");
+    int kb = 16;
+    if ((rc = choose_key_bytes(f->iv, p.key_bits, &kb)) != PLANB_OK) {
         delete f;
         return nullptr;
     }
-    bool all_lo_zero = true;
-    for (const U128& k : f->iv.starts) all_lo_zero &= (k.lo == 0);
-    if (p.key_bits == 64 && !all_lo_zero) {
-        fail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
-        delete f;
-        return nullptr;
-    }
-    const bool narrow = p.key_bits == 64 || (p.key_bits == 0 && all_lo_zero);
-    const int kb = narrow ? 8 : 16;
     f->key_bytes_per_slot = (uint32_t)kb;
-    if ((rc = plan_layout(m, p.fanout, p.fanout, (uint32_t)leaf_cap_for((int)p.fanout, kb),
-                          (uint32_t)leaf_slots_for((int)p.fanout, kb), true, &f->lay, &err)) != 0) {
+    if ((rc = plan_fib_layout(m, p.fanout, kb, &f->lay, &err)) != 0) {
         fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
         delete f;
         return nullptr;
     }
     std::vector<uint8_t> image;  // the device slot array, leaves carrying their next hops
     try {
-        std::vector<U128> keys;
-        fill_keys(f->iv, f->lay, &keys);
-        image.resize(keys.size() * kb);
-        if (narrow) {
-            uint64_t* d = reinterpret_cast<uint64_t*>(image.data());
-            for (size_t i = 0; i < keys.size(); ++i) d[i] = keys[i].hi;
-        } else {
-            std::memcpy(image.data(), keys.data(), image.size());
-        }
-        const uint64_t LC = f->lay.leaf_cap, LS = f->lay.leaf_slots, base = f->lay.leaf_base();
-        for (uint64_t q = 0; q < f->lay.leaves; ++q) {
-            uint8_t* hops = image.data() + (base + q * LS + LC) * kb;
-            for (uint64_t s = 0; s < LC; ++s) {
-                const uint64_t i = q * LC + s;
-                const uint16_t v = i < m ? f->iv.nh[i] : kNoRoute;
-                std::memcpy(hops + 2 * s, &v, 2);
-            }
-        }
+        build_image(f->iv, f->lay, kb, &image);
     } catch (const std::bad_alloc&) {
         fail(PLANB_ENOMEM, "out of host memory");
         delete f;
@@ -329,8 +346,7 @@ long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout
         if (!(s[i - 1] < s[i])) return fail(PLANB_EINVAL, "starts must be strictly increasing");
     Layout lay;
     std::string err;
-    int rc = plan_layout(m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, 16),
-                         (uint32_t)leaf_slots_for((int)fanout, 16), true, &lay, &err);
+    int rc = plan_fib_layout(m, fanout, 16, &lay, &err);
     if (rc != 0) return fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
     if (info) layout_to_info(lay, info);
     const size_t slots = lay.total_slots();
@@ -340,12 +356,48 @@ long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout
     iv.nh.assign(m, 0);
     std::vector<U128> k;
     try {
-        fill_keys(iv, lay, &k);
+        fill_keys(iv, lay, 16, &k);
     } catch (const std::bad_alloc&) {
         return fail(PLANB_ENOMEM, "out of host memory");
     }
     std::memcpy(keys, k.data(), slots * sizeof(planb_addr_t));
     return (long long)slots;
+}
+
+long long planb_build_image(const planb_addr_t* starts, const uint16_t* next_hops, size_t m, uint32_t fanout,
+                            uint32_t key_bits, void* image, size_t cap_bytes, planb_info_t* info)
+{
+    clear_error();
+    if (m == 0 || !starts || !next_hops) return fail(PLANB_EINVAL, "need m >= 1 interval starts and next hops");
+    if (m >= (1ull << 31)) return fail(PLANB_ERANGE, "too many intervals (at most 2^31 - 1)");
+    if (fanout != 8 && fanout != 16 && fanout != 32) return fail(PLANB_EINVAL, "fanout must be 8, 16 or 32");
+    const U128* s = reinterpret_cast<const U128*>(starts);
+    if (s[0] != U128{0, 0}) return fail(PLANB_EINVAL, "starts[0] must be 0");
+    for (size_t i = 1; i < m; ++i)
+        if (!(s[i - 1] < s[i])) return fail(PLANB_EINVAL, "starts must be strictly increasing");
+    Intervals iv;
+    int kb = 16, rc;
+    std::vector<uint8_t> img;
+    try {
+        iv.starts.assign(s, s + m);
+        iv.nh.assign(next_hops, next_hops + m);
+        if ((rc = choose_key_bytes(iv, key_bits, &kb)) != PLANB_OK) return rc;
+        Layout lay;
+        std::string err;
+        if ((rc = plan_fib_layout(m, fanout, kb, &lay, &err)) != 0) return fail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
+        if (info) {
+            layout_to_info(lay, info);
+            info->key_bits = (uint32_t)kb * 8;
+            info->key_bytes = lay.total_slots() * kb;
+        }
+        const size_t bytes = lay.total_slots() * kb;
+        if (!image || bytes > cap_bytes) return (long long)bytes;
+        build_image(iv, lay, kb, &img);
+    } catch (const std::bad_alloc&) {
+        return fail(PLANB_ENOMEM, "out of host memory");
+    }
+    std::memcpy(image, img.data(), img.size());
+    return (long long)img.size();
 }
 
 int planb_get_info(const planb_fib_t* fib, planb_info_t* info)

@@ -172,14 +172,14 @@ int plan_layout(uint64_t m, uint32_t b, uint32_t slots, uint32_t leaf_cap, uint3
     return 0;
 }
 
-void fill_keys(const Intervals& iv, const Layout& lay, std::vector<U128>* keys)
+void fill_keys(const Intervals& iv, const Layout& lay, int key_bytes, std::vector<U128>* keys)
 {
     const uint64_t b = lay.b, S = lay.slots, k = b - 1, D = lay.depth, m = iv.starts.size();
     const uint64_t LC = lay.leaf_cap, LS = lay.leaf_slots;
     keys->assign(lay.total_slots(), kSentinel);
     U128* K = keys->data();
     const uint64_t leaf0 = lay.leaf_base();
-    for (uint64_t i = 0; i < m; ++i) K[leaf0 + (i / LC) * LS + i % LC] = iv.starts[i];
+    for (uint64_t i = 0; i < m; ++i) K[leaf0 + (i / LC) * LS + leaf_key_slot((uint32_t)(i % LC), key_bytes)] = iv.starts[i];
     // internal levels: separator j-1 of node q = first key of the leftmost
     // leaf under child q*b + j
     uint64_t span = 1;  // leaves under one node of level l + 1

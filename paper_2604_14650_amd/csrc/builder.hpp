@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include "leaf_format.hpp"
+
 namespace planb {
 
 struct U128 {
@@ -55,8 +57,9 @@ int plan_layout(uint64_t m, uint32_t b, uint32_t slots, uint32_t leaf_cap, uint3
                 Layout* lay, std::string* err);
 
 // Fills the slot array (every unused slot is the sentinel 2^128 - 1).  Leaf q
-// holds the interval starts q*leaf_cap .. in its first leaf_cap slots;
-// separator j-1 of an internal node is the smallest key under its child j.
-void fill_keys(const Intervals& iv, const Layout& lay, std::vector<U128>* keys);
+// holds the interval starts q*leaf_cap ..; its key s sits in slot s, or, with
+// key_bytes = 8, where the blocked 64-bit leaf format puts it.  Separator j-1
+// of an internal node is the smallest key under its child j.
+void fill_keys(const Intervals& iv, const Layout& lay, int key_bytes, std::vector<U128>* keys);
 
 }  // namespace planb

@@ -26,7 +26,7 @@ struct Descent {
     // the lookups over, one owner lane's at a time, for the lower levels.
     static constexpr bool kHybrid = BIN && KPL < B;
     static constexpr int kLS = leaf_slots_for(B, (int)sizeof(K));  // slots per leaf
-    static constexpr int kLC = leaf_cap_for(B, (int)sizeof(K));    // keys per leaf
+    static constexpr int kLC = leaf_cap_for(B, (int)sizeof(K));    // keys (intervals) per leaf
     static constexpr int kLPER = kLS / G;                          // leaf slots per lane
     static constexpr uint64_t kStep = kHybrid ? 64ull * R : (uint64_t)LPW * R;  // lookups per wavefront step
 
@@ -77,95 +77,141 @@ struct Descent {
         return (uint32_t)group_sum<G>(cnt);
     }
 
-    // Search of the leaf at slot node0 by the G lanes of a group (lane j of
-    // the group is `j`, its first lane `lane0`): counts the keys <= x among the
-    // first kLC slots, turns the count into the interval index (*idx) and
-    // returns that interval's next hop.  The next hops sit in the same leaf
-    // after the keys, so the words the lanes already loaded hold it: the lane
-    // holding it picks the word out of its registers and the group reads it
-    // with one cross-lane shuffle instead of a second memory access.
-    static __device__ __forceinline__ uint16_t leaf_search(const TreeDesc& t, const K* keys, size_t node0, uint32_t q,
-                                                           int j, int lane0, uint64_t xhi, uint64_t xlo,
-                                                           uint64_t* idx)
+    // ---- leaf level.  A lookup's G lanes load the leaf's words (lane j of
+    // the group is `j`: with kContig it holds slots [j*kLPER, (j+1)*kLPER),
+    // else slots j, G + j, 2G + j, ...), count the keys <= x among them, and
+    // turn the count into the interval index.  The interval's next hop sits
+    // in the same leaf, so the lane that loaded it picks the word out of its
+    // registers and the group reads it with one cross-lane shuffle.
+    static constexpr int kb = (int)sizeof(K);
+    static constexpr bool kContig = !WIDE && kLPER >= 2;
+    static constexpr int kW = kLPER * kb / 4;  // 32-bit words of a leaf per lane
+
+    // lane of the group, and word of that lane, that hold byte `byte` of a leaf
+    static __host__ __device__ constexpr uint32_t byte_lane(uint32_t byte)
     {
-        constexpr int kb = (int)sizeof(K);
-        constexpr bool kContig = !WIDE && kLPER >= 2;  // lane j holds slots [j*kLPER, (j+1)*kLPER)
-        constexpr int kW = kLPER * kb / 4;              // 32-bit words per lane
+        return kContig ? byte / (kLPER * kb) : (byte / kb) % G;
+    }
+    static __host__ __device__ constexpr uint32_t byte_word(uint32_t byte)
+    {
+        return kContig ? (byte % (kLPER * kb)) / 4 : (byte / kb) / G * (kb / 4) + (byte % kb) / 4;
+    }
+    // which words of a lane can hold a next hop (the pick selects among them only)
+    struct WordSet {
+        bool v[kW];
+    };
+    static constexpr WordSet hop_words()
+    {
+        WordSet m{};
+        for (int s = 0; s < kLC; ++s) m.v[byte_word(leaf_hop_byte(s, kb, kLC))] = true;
+        return m;
+    }
+    static constexpr WordSet kHopWords = hop_words();
+
+    struct LeafWords {
         uint32_t w[kW];
-        int cnt = 0;
+    };
+
+    static __device__ __forceinline__ void leaf_load(const K* keys, size_t node0, int j, LeafWords& L)
+    {
         if constexpr (kContig) {
             const uint4* p = reinterpret_cast<const uint4*>(keys + node0 + (size_t)j * kLPER);
 #pragma unroll
             for (int s = 0; s < kLPER / 2; ++s) {
-                const int slot = j * kLPER + 2 * s;
                 const uint4 v = p[s];
-                w[4 * s] = v.x;
-                w[4 * s + 1] = v.y;
-                w[4 * s + 2] = v.z;
-                w[4 * s + 3] = v.w;
-                cnt += (slot < kLC && (((uint64_t)v.y << 32) | v.x) <= xhi) +
-                       (slot + 1 < kLC && (((uint64_t)v.w << 32) | v.z) <= xhi);
+                L.w[4 * s] = v.x;
+                L.w[4 * s + 1] = v.y;
+                L.w[4 * s + 2] = v.z;
+                L.w[4 * s + 3] = v.w;
             }
-        } else {  // lane j holds slots j, G + j, 2G + j, ...
+        } else {
 #pragma unroll
             for (int s = 0; s < kLPER; ++s) {
-                const int slot = s * G + j;
-                const K k = keys[node0 + slot];
+                const K k = keys[node0 + s * G + j];
                 if constexpr (WIDE) {  // uint4: the key's four words in memory order
-                    w[4 * s] = k.x;
-                    w[4 * s + 1] = k.y;
-                    w[4 * s + 2] = k.z;
-                    w[4 * s + 3] = k.w;
+                    L.w[4 * s] = k.x;
+                    L.w[4 * s + 1] = k.y;
+                    L.w[4 * s + 2] = k.z;
+                    L.w[4 * s + 3] = k.w;
                 } else {
-                    w[2 * s] = (uint32_t)k;
-                    w[2 * s + 1] = (uint32_t)(k >> 32);
+                    L.w[2 * s] = (uint32_t)k;
+                    L.w[2 * s + 1] = (uint32_t)(k >> 32);
                 }
-                cnt += slot < kLC ? KF::le(k, xhi, xlo) : 0;
             }
         }
-        const uint32_t c = (uint32_t)group_sum<G>(cnt);
-        *idx = leaf_index(t, q, c);
-        const uint32_t pos = (uint32_t)(*idx - (uint64_t)q * kLC);  // in [0, kLC)
-        const uint32_t byte = kLC * kb + 2 * pos;                    // of the next hop, in the leaf
-        uint32_t owner, word;
-        if constexpr (kContig) {
-            owner = byte / (kLPER * kb);
-            word = (byte % (kLPER * kb)) / 4;
-        } else {
-            const uint32_t slot = byte / kb;
-            owner = slot % G;
-            word = (slot / G) * (kb / 4) + (byte % kb) / 4;
-        }
-        uint32_t sel = 0;
-#pragma unroll
-        for (int k = 0; k < kW; ++k) sel = (uint32_t)k == word ? w[k] : sel;
-        if constexpr (G > 1) sel = (uint32_t)__shfl((int)sel, lane0 + (int)owner, 64);
-        return (uint16_t)(sel >> (16 * (pos & 1)));
     }
 
-    // One lane: the same count by branch-free binary search (slots >= kLC act
-    // as larger than every address).
-    static __device__ __forceinline__ uint32_t lane_leaf_bincount(const K* keys, size_t node0, uint64_t xhi,
-                                                                  uint64_t xlo)
+    // keys <= x among the lane's key slots
+    static __device__ __forceinline__ int leaf_lane_count(const LeafWords& L, int j, uint64_t xhi, uint64_t xlo)
     {
+        int cnt = 0;
+#pragma unroll
+        for (int s = 0; s < kLPER; ++s) {
+            const uint32_t slot = kContig ? (uint32_t)(j * kLPER + s) : (uint32_t)(s * G + j);
+            int le;
+            if constexpr (WIDE)
+                le = KF::le(make_uint4(L.w[4 * s], L.w[4 * s + 1], L.w[4 * s + 2], L.w[4 * s + 3]), xhi, xlo);
+            else
+                le = (((uint64_t)L.w[2 * s + 1] << 32) | L.w[2 * s]) <= xhi;
+            cnt += leaf_slot_is_key(slot, kb, kLC) ? le : 0;
+        }
+        return cnt;
+    }
+
+    // interval index of a count c of keys <= x in leaf q (c >= 1: interval 0
+    // starts at 0); indexes fit 32 bits (a FIB has fewer than 2^31 intervals)
+    static __device__ __forceinline__ uint32_t leaf_index(const TreeDesc& t, uint32_t q, uint32_t c)
+    {
+        const uint32_t idx = q * (uint32_t)kLC + c - 1, last = (uint32_t)t.m_minus_1;
+        return idx < last ? idx : last;
+    }
+
+    // next hop of the leaf's interval `pos`, read by every lane of the group
+    // (lane0 is the group's first lane)
+    static __device__ __forceinline__ uint16_t leaf_pick_hop(const LeafWords& L, uint32_t pos, int lane0)
+    {
+        const uint32_t byte = leaf_hop_byte(pos, kb, kLC);
+        const uint32_t word = byte_word(byte);
+        uint32_t sel = 0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k)
+            if (kHopWords.v[k]) sel = word == (uint32_t)k ? L.w[k] : sel;
+        if constexpr (G > 1) sel = (uint32_t)__shfl((int)sel, lane0 + (int)byte_lane(byte), 64);
+        return (uint16_t)(sel >> (8 * (byte & 2)));
+    }
+
+    // NR lookups' leaves by lane groups: all loads first, then the searches
+    template <int NR>
+    static __device__ __forceinline__ void leaf_groups(const TreeDesc& t, const K* keys, const uint32_t* q,
+                                                       const uint64_t* xh, const uint64_t* xl, int j, int lane0,
+                                                       uint32_t* idx, uint16_t* hop)
+    {
+        LeafWords L[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) leaf_load(keys, t.leaf_base + (size_t)q[u] * kLS, j, L[u]);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const uint32_t c = (uint32_t)group_sum<G>(leaf_lane_count(L[u], j, xh[u], xl[u]));
+            idx[u] = leaf_index(t, q[u], c);
+            hop[u] = leaf_pick_hop(L[u], idx[u] - q[u] * (uint32_t)kLC, lane0);
+        }
+    }
+
+    // One lane, leaf in LDS: the count by branch-free binary search over the
+    // leaf's keys, and the next hop read directly.
+    static __device__ __forceinline__ void leaf_lane(const TreeDesc& t, const K* keys, uint32_t q, uint64_t xhi,
+                                                     uint64_t xlo, uint32_t* idx, uint16_t* hop)
+    {
+        const size_t node0 = t.leaf_base + (size_t)q * kLS;
         uint32_t c = 0;
 #pragma unroll
         for (int step = kLS / 2; step >= 1; step >>= 1) {
             const uint32_t probe = c + step - 1;
-            c += (probe < (uint32_t)kLC && KF::le(keys[node0 + probe], xhi, xlo)) ? step : 0;
+            c += (probe < (uint32_t)kLC && KF::le(keys[node0 + leaf_key_slot(probe, kb)], xhi, xlo)) ? step : 0;
         }
-        return c;
-    }
-
-    // Interval index and next hop of the leaf result (c keys <= x in leaf q).
-    static __device__ __forceinline__ uint64_t leaf_index(const TreeDesc& t, uint32_t q, uint32_t c)
-    {
-        const uint64_t idx = (uint64_t)q * kLC + c - 1;  // c >= 1: interval 0 starts at 0
-        return idx < t.m_minus_1 ? idx : t.m_minus_1;
-    }
-    static __device__ __forceinline__ uint16_t leaf_hop(const K* keys, size_t node0, uint32_t q, uint64_t idx)
-    {
-        return reinterpret_cast<const uint16_t*>(keys + node0 + kLC)[idx - (uint64_t)q * kLC];
+        *idx = leaf_index(t, q, c);
+        const uint8_t* leaf = reinterpret_cast<const uint8_t*>(keys + node0);
+        *hop = *reinterpret_cast<const uint16_t*>(leaf + leaf_hop_byte(*idx - q * (uint32_t)kLC, kb, kLC));
     }
 
     template <bool FROM_LDS>
@@ -184,10 +230,10 @@ struct Descent {
         return ((uint64_t)hi << 32) | lo;
     }
 
-    static __device__ __forceinline__ void store(void* out, int index_out, uint64_t i, uint64_t idx, uint16_t hop)
+    static __device__ __forceinline__ void store(void* out, int index_out, uint64_t i, uint32_t idx, uint16_t hop)
     {
         if (index_out)
-            __builtin_nontemporal_store((uint32_t)idx, static_cast<uint32_t*>(out) + i);
+            __builtin_nontemporal_store(idx, static_cast<uint32_t*>(out) + i);
         else
             __builtin_nontemporal_store(hop, static_cast<uint16_t*>(out) + i);
     }
@@ -217,11 +263,11 @@ struct Descent {
         if (t.lds_levels >= t.depth) {  // the whole tree is in LDS
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const size_t node0 = t.leaf_base + (size_t)q[r] * kLS;
-                const uint32_t c = lane_leaf_bincount(lds_keys, node0, xh[r], xl[r]);
-                const uint64_t idx = leaf_index(t, q[r], c);
+                uint32_t idx;
+                uint16_t hop;
+                leaf_lane(t, lds_keys, q[r], xh[r], xl[r], &idx, &hop);
                 const uint64_t i = base + (uint64_t)r * 64 + lane;
-                if (i < n) store(out, index_out, i, idx, leaf_hop(lds_keys, node0, q[r], idx));
+                if (i < n) store(out, index_out, i, idx, hop);
             }
             return;
         }
@@ -245,13 +291,13 @@ struct Descent {
             for (int u = 0; u < T; ++u)
                 p[u] = min(p[u] * B + node_count<false>(gkeys, (size_t)(off + p[u]) * B, j, yh[u], yl[u]), lim);
         }
+        uint32_t idx[T];
+        uint16_t hop[T];
+        leaf_groups<T>(t, gkeys, p, yh, yl, j, lane - j, idx, hop);
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            uint64_t idx;
-            const uint16_t hop =
-                leaf_search(t, gkeys, t.leaf_base + (size_t)p[u] * kLS, p[u], j, lane - j, yh[u], yl[u], &idx);
             const uint64_t i = base + (uint64_t)(u / G) * 64 + (u % G) * LPW + grp;
-            if (j == 0 && i < n) store(out, index_out, i, idx, hop);
+            if (j == 0 && i < n) store(out, index_out, i, idx[u], hop[u]);
         }
     }
 
@@ -290,20 +336,20 @@ struct Descent {
                     q[r] = min(q[r] * B + node_count<false>(gkeys, (size_t)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
             }
         }
-        const bool leaf_lds = t.lds_levels >= t.depth;
+        uint32_t idx[R];
+        uint16_t hop[R];
+        if (t.lds_levels < t.depth) {
+            leaf_groups<R>(t, gkeys, q, xhi, xlo, j, lane - j, idx, hop);
+        } else if constexpr (BIN && KPL == B) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) leaf_lane(t, lds_keys, q[r], xhi[r], xlo[r], &idx[r], &hop[r]);
+        } else {
+            leaf_groups<R>(t, lds_keys, q, xhi, xlo, j, lane - j, idx, hop);
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const size_t node0 = t.leaf_base + (size_t)q[r] * kLS;
-            uint64_t idx;
-            uint16_t hop;
-            if (BIN && KPL == B && leaf_lds) {
-                idx = leaf_index(t, q[r], lane_leaf_bincount(lds_keys, node0, xhi[r], xlo[r]));
-                hop = leaf_hop(lds_keys, node0, q[r], idx);
-            } else {
-                hop = leaf_search(t, leaf_lds ? lds_keys : gkeys, node0, q[r], j, lane - j, xhi[r], xlo[r], &idx);
-            }
             const uint64_t i = base + (uint64_t)r * LPW + grp;
-            if (j == 0 && i < n) store(out, index_out, i, idx, hop);
+            if (j == 0 && i < n) store(out, index_out, i, idx[r], hop[r]);
         }
     }
 };

@@ -5,24 +5,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "leaf_format.hpp"
+
 namespace planb {
 
 constexpr int kDevMaxLevels = 16;
 
 // A 16-byte address record {hi, lo} as a native vector (for streaming loads).
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-
-// Leaf nodes hold keys and, after the keys, one uint16 next hop per key, so a
-// lookup reads its next hop from the line that held its leaf.  A leaf spans
-// max(B slots, 128 bytes) and holds as many (key, next hop) pairs as fit.
-__host__ __device__ constexpr int leaf_slots_for(int B, int key_bytes)
-{
-    return B * key_bytes >= 128 ? B : 128 / key_bytes;
-}
-__host__ __device__ constexpr int leaf_cap_for(int B, int key_bytes)
-{
-    return leaf_slots_for(B, key_bytes) * key_bytes / (key_bytes + 2);
-}
 
 // What a kernel needs to descend one built tree.  Passed by value (kernarg).
 struct TreeDesc {

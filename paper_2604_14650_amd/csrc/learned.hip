@@ -156,7 +156,7 @@ __device__ inline typename KeyFmt<WIDE>::T leaf_key(const TreeDesc& t, uint64_t 
     constexpr int kb = (int)sizeof(typename KeyFmt<WIDE>::T);
     constexpr uint64_t LC = leaf_cap_for(B, kb), LS = leaf_slots_for(B, kb);
     const auto* keys = static_cast<const typename KeyFmt<WIDE>::T*>(t.keys);
-    return keys[t.leaf_base + (i / LC) * LS + i % LC];
+    return keys[t.leaf_base + (i / LC) * LS + leaf_key_slot((uint32_t)(i % LC), kb)];
 }
 
 // Plain one-lane descent (every key of each node), used for fallbacks.
@@ -177,7 +177,7 @@ __device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_
     const size_t nb = t.leaf_base + (size_t)q * LS;
     uint32_t c = 0;
 #pragma unroll
-    for (int s = 0; s < LC; ++s) c += KF::le(keys[nb + s], xhi, xlo);
+    for (int s = 0; s < LC; ++s) c += KF::le(keys[nb + leaf_key_slot(s, (int)sizeof(typename KF::T))], xhi, xlo);
     const uint64_t idx = (uint64_t)q * LC + c - 1;
     return idx < t.m_minus_1 ? idx : t.m_minus_1;
 }

@@ -125,6 +125,8 @@ _sig("planb_set_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_build_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz, ctypes.c_uint32, _vp, _vp, _sz)
 _sig("planb_build_keys", ctypes.c_longlong, _vp, _sz, ctypes.c_uint32, _vp, _sz, ctypes.POINTER(planb_info_t))
+_sig("planb_build_image", ctypes.c_longlong, _vp, _vp, _sz, ctypes.c_uint32, ctypes.c_uint32, _vp, _sz,
+     ctypes.POINTER(planb_info_t))
 _sig("planb_lookup_batches", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
 _sig("planb_graph_create", _vp, _vp, ctypes.c_uint32)
 _sig("planb_graph_launch", ctypes.c_int, _vp, _vp, ctypes.c_uint32, _vp)
@@ -338,6 +340,20 @@ def planb_build_keys(starts, fanout: int = 16):
     keys = np.empty((need, 2), dtype=np.uint64)
     _check(_lib.planb_build_keys(s.ctypes.data, s.shape[0], fanout, keys.ctypes.data, need, None))
     return keys, _info_dict(info)
+
+
+def planb_build_image(starts, next_hops, fanout: int = 16, key_bits: int = 0):
+    """Host-only device image of the tree over ``starts`` / ``next_hops``: returns (bytes (uint8), info)."""
+    s = _host(starts, np.uint64, (2,))
+    nh = _host(next_hops, np.uint16)
+    if nh.shape[0] != s.shape[0]:
+        raise ValueError("starts and next_hops differ in length")
+    info = planb_info_t()
+    args = (s.ctypes.data, nh.ctypes.data, s.shape[0], fanout, key_bits)
+    need = _check(_lib.planb_build_image(*args, None, 0, ctypes.byref(info)))
+    img = np.empty(need, dtype=np.uint8)
+    _check(_lib.planb_build_image(*args, img.ctypes.data, need, None))
+    return img, _info_dict(info)
 
 
 def batch_array(batches):

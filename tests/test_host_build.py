@@ -272,3 +272,106 @@ def test_descent_with_top_key_equal_to_sentinel():
     keys = ints(keys_arr)
     for x, want in [(0, 0), (4, 0), (5, 1), (M128 - 1, 1), (M128, 2)]:
         assert _descend(keys, info, x) == want
+
+
+# ------------------------------------------------------------- device image
+# (keys, slots) per leaf of a FIB's device image, written out per key width and
+# fanout: 64-bit slots: 32-byte blocks of 3 keys + their 3 next hops; 128-bit
+# slots: the keys, then their next hops.
+LEAF_SHAPE = {(64, 8): (12, 16), (64, 16): (12, 16), (64, 32): (24, 32),
+              (128, 8): (7, 8), (128, 16): (14, 16), (128, 32): (28, 32)}
+
+
+def _leaf_key_off(s, kbits, L):
+    return (s // 3) * 32 + (s % 3) * 8 if kbits == 64 else 16 * s
+
+
+def _leaf_hop_off(s, kbits, L):
+    return (s // 3) * 32 + 24 + (s % 3) * 2 if kbits == 64 else 16 * L + 2 * s
+
+
+def _slot_key(img, slot, kbits):
+    """Key in a slot of the image as a 128-bit integer (64-bit slots hold the high word)."""
+    if kbits == 64:
+        return int.from_bytes(img[8 * slot:8 * slot + 8].tobytes(), "little") << 64
+    hi = int.from_bytes(img[16 * slot:16 * slot + 8].tobytes(), "little")
+    lo = int.from_bytes(img[16 * slot + 8:16 * slot + 16].tobytes(), "little")
+    return hi << 64 | lo
+
+
+def _image_lookup(img, info, x):
+    """Descent over the byte image, as the kernel does it: (interval index, next hop)."""
+    b, D, kbits = info["fanout"], info["depth"], info["key_bits"]
+    off, nodes = info["level_offset"], info["level_nodes"]
+    L, LS, base = info["leaf_keys"], info["leaf_slots"], info["leaf_base"]
+    kb = kbits // 8
+    xk = x if kbits == 128 else (x >> 64) << 64  # 64-bit keys compare the high word
+    q = 0
+    for l in range(D - 1):
+        c = sum(1 for s in range(b) if _slot_key(img, (off[l] + q) * b + s, kbits) <= xk)
+        q = min(q * b + c, nodes[l + 1] - 1)
+    leaf = (base + q * LS) * kb
+    keys = [_key_at(img, leaf + _leaf_key_off(s, kbits, L), kbits) for s in range(L)]
+    c = sum(1 for k in keys if k <= xk)
+    idx = min(q * L + c - 1, info["intervals"] - 1)
+    pos = idx - q * L
+    hop = int.from_bytes(img[leaf + _leaf_hop_off(pos, kbits, L):][:2].tobytes(), "little")
+    return idx, hop
+
+
+def _key_at(img, byte, kbits):
+    if kbits == 64:
+        return int.from_bytes(img[byte:byte + 8].tobytes(), "little") << 64
+    return (int.from_bytes(img[byte:byte + 8].tobytes(), "little") << 64 |
+            int.from_bytes(img[byte + 8:byte + 16].tobytes(), "little"))
+
+
+@pytest.mark.parametrize("b", [8, 16, 32])
+@pytest.mark.parametrize("kbits", [64, 128])
+@pytest.mark.parametrize("m", [1, 2, 11, 12, 13, 25, 700, 5000])
+def test_device_image_structure_and_descent(b, kbits, m):
+    rng = np.random.default_rng(7 * m + b + kbits)
+    his = sorted(set(int(v) for v in rng.integers(1, 2**63, size=m - 1)) | {0})
+    while len(his) < m:
+        his.append(his[-1] + 1)
+    his = his[:m]
+    lo_mask = 0 if kbits == 64 else 0xFFFF
+    vals = [h << 64 | (h * 13 & lo_mask) for h in his]
+    vals[0] = 0
+    nh = rng.integers(0, 0xFFFF, size=m).astype(np.uint16)
+    img, info = P.planb_build_image(S.from_ints(vals), nh, b, kbits)
+    assert info["key_bits"] == kbits and info["intervals"] == m
+    L, LS, base = info["leaf_keys"], info["leaf_slots"], info["leaf_base"]
+    assert (L, LS) == LEAF_SHAPE[(kbits, b)]
+    kb = kbits // 8
+    leaves = -(-m // L)
+    assert info["level_nodes"][-1] == leaves
+    assert LS * kb >= 128 and base % LS == 0 and len(img) == (base + leaves * LS) * kb == info["key_bytes"]
+    for q in range(leaves):
+        leaf = (base + q * LS) * kb
+        for s in range(L):
+            i = q * L + s
+            key = _key_at(img, leaf + _leaf_key_off(s, kbits, L), kbits)
+            hop = int.from_bytes(img[leaf + _leaf_hop_off(s, kbits, L):][:2].tobytes(), "little")
+            if i < m:
+                assert key == vals[i] and hop == nh[i], (q, s)
+            else:
+                assert key == M128 >> (128 - kbits) << (128 - kbits) and hop == 0xFFFF
+    probes = [0, 1, M128, M128 - 1] + vals + [v - 1 for v in vals[1:]] + [v + 1 for v in vals]
+    probes += [int(x) << 64 | int(y) for x, y in zip(rng.integers(0, 2**63, size=100), rng.integers(0, 2**63, size=100))]
+    for x in probes[:1500]:
+        want = bisect.bisect_right(vals, x) - 1
+        assert _image_lookup(img, info, x) == (want, int(nh[want])), hex(x)
+
+
+def test_device_image_key_width_choice():
+    vals = [0, 5 << 64, 9 << 64 | 1]
+    nh = np.array([1, 2, 3], np.uint16)
+    _, info = P.planb_build_image(S.from_ints(vals), nh, 8, 0)
+    assert info["key_bits"] == 128  # a start with a nonzero low word
+    _, info = P.planb_build_image(S.from_ints(vals[:2]), nh[:2], 8, 0)
+    assert info["key_bits"] == 64
+    with pytest.raises(P.PlanbError):
+        P.planb_build_image(S.from_ints(vals), nh, 8, 64)
+    with pytest.raises(P.PlanbError):
+        P.planb_build_image(S.from_ints([1, 2]), nh[:2], 8, 0)  # starts[0] must be 0
