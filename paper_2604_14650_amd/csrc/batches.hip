@@ -253,7 +253,7 @@ int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint3
     const uint32_t b = fib->lay.b;
     int deepest = 0;
     while (deepest < (int)fib->lay.depth &&
-           fib->lay.offset[deepest + 1] * b * (size_t)fib->key_bytes_per_slot <= (size_t)max_lds)
+           fib->lay.prefix_slots(deepest + 1) * (size_t)fib->key_bytes_per_slot <= (size_t)max_lds)
         ++deepest;
     std::vector<planb_tuning_t> cands;
     for (uint32_t kpl = 1; kpl <= b && kpl <= 16; kpl *= 2) {
