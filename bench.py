@@ -115,7 +115,7 @@ def measured_traffic(per_launch_lookups: int, config: str):
 
 
 # Launch shapes the autotuner chose for this workload on MI355X (used with --no-autotune).
-KNOWN_TUNING = {0: {"fanout": 8, "tuning": (2, 5, 1, 512, 1)}, 128: {"fanout": 8, "tuning": (2, 4, 1, 512, 1)}}
+KNOWN_TUNING = {0: {"fanout": 8, "tuning": (2, 5, 2, 1024, 1)}, 128: {"fanout": 8, "tuning": (4, 5, 1, 1024, 1)}}
 
 
 def plain_leg(P, fib, d, n, out, args):

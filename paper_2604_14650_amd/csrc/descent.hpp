@@ -294,10 +294,20 @@ struct Descent {
         uint32_t idx[T];
         uint16_t hop[T];
         leaf_groups<T>(t, gkeys, p, yh, yl, j, lane - j, idx, hop);
+        // hand every result back to the lane that owns its lookup, so each of
+        // the R stores writes 64 consecutive results: owner lane L's lookup r
+        // was round r*G + L/LPW, computed by group L%LPW
+        const int g = lane / LPW, src = (lane % LPW) * G;
 #pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const uint64_t i = base + (uint64_t)(u / G) * 64 + (u % G) * LPW + grp;
-            if (j == 0 && i < n) store(out, index_out, i, idx[u], hop[u]);
+        for (int r = 0; r < R; ++r) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const uint32_t got = (uint32_t)__shfl((int)(index_out ? idx[r * G + k] : hop[r * G + k]), src, 64);
+                v = k == g ? got : v;
+            }
+            const uint64_t i = base + (uint64_t)r * 64 + lane;
+            if (i < n) store(out, index_out, i, v, (uint16_t)v);
         }
     }
 
