@@ -401,8 +401,10 @@ void planb_server_free(planb_server_t* server); /* waits for launches in flight 
 /* Registers or replaces table id (the rules are validated and copied). */
 int planb_server_set_table(planb_server_t* server, uint32_t id, const planb_addr_t* prefixes,
                            const uint8_t* lengths, const uint16_t* next_hops, size_t n);
-/* Queues a burst: addrs (host) are copied now; out (host, n uint16) is
- * written before the burst's completion is returned by poll. */
+/* Queues a burst: addrs (host, n records) must stay valid and unchanged, and
+ * out (host, n uint16) is written, until poll returns the burst's completion
+ * (the addresses are copied to pinned staging when the burst joins a launch,
+ * so submitting costs no copy). */
 int planb_server_submit(planb_server_t* server, uint32_t table, const planb_addr_t* addrs, uint32_t n,
                         uint16_t* out, int64_t tag);
 /* Progresses the server and returns up to cap completions (count >= 0 or a

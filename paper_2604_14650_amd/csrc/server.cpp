@@ -5,7 +5,8 @@
 // stage and rebuilds a FIB in the background, swapping it in atomically and
 // freeing the old one once in-flight lookups finish (Section 3 "Batching",
 // "Dynamic FIB Update"; Section 4 "Thread Pipeline").  Here:
-//  * submit() queues a burst (table id, host addresses, host output);
+//  * submit() queues a burst (table id, host addresses, host output; the
+//    addresses are read, and the output written, before its completion);
 //  * poll() completes finished launches (results copied to the caller's
 //    buffers, completion times recorded) and packs queued bursts -- from any
 //    tables -- into the next free launch slot, so bursts that arrive while
@@ -19,6 +20,7 @@
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -46,7 +48,7 @@ struct Pending {
     int64_t tag;
     uint32_t table;
     uint32_t n;
-    std::vector<planb_addr_t> addrs;
+    const planb_addr_t* addrs;  // the caller's, valid until the completion is returned
     uint16_t* out;
     double submit_us;
     uint32_t offset = 0;  // position in the launch
@@ -210,6 +212,41 @@ void finish_slot(planb_server_t* s, Slot& sl)
     sl.busy = false;
 }
 
+struct CopyJob {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+
+// Host copies into pinned staging: split over a few threads once a launch
+// carries more than a couple of MB, where one core's memcpy would otherwise
+// bound the launch rate well below what the PCIe link carries.
+void run_copies(const std::vector<CopyJob>& jobs, size_t total)
+{
+    constexpr size_t kPerThread = 2u << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned T = (unsigned)std::min<size_t>({(size_t)8, (size_t)hw, std::max<size_t>(1, total / kPerThread)});
+    auto copy_range = [&](size_t lo, size_t hi) {  // bytes [lo, hi) of the concatenated jobs
+        size_t pos = 0;
+        for (const CopyJob& j : jobs) {
+            const size_t a = std::max(lo, pos), b = std::min(hi, pos + j.bytes);
+            if (a < b)
+                std::memcpy(static_cast<char*>(j.dst) + (a - pos), static_cast<const char*>(j.src) + (a - pos), b - a);
+            pos += j.bytes;
+            if (pos >= hi) break;
+        }
+    };
+    if (T <= 1) {
+        copy_range(0, total);
+        return;
+    }
+    std::vector<std::thread> th;
+    const size_t chunk = (total + T - 1) / T;
+    for (unsigned k = 1; k < T; ++k) th.emplace_back(copy_range, k * chunk, std::min(total, (k + 1) * chunk));
+    copy_range(0, std::min(total, chunk));
+    for (auto& t : th) t.join();
+}
+
 int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
 {
     *launched = false;
@@ -217,6 +254,7 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
     uint32_t nb = 0, na = 0;
     BurstRec* desc = reinterpret_cast<BurstRec*>(sl.h_desc + 16);
     std::vector<char> blocked(s->tables.size(), 0);
+    std::vector<CopyJob> copies;
     for (auto it = s->queue.begin(); it != s->queue.end() && nb < maxb;) {
         Pending& p = *it;
         if (na + p.n > maxl) {
@@ -236,7 +274,7 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
             continue;
         }
         Table& t = s->tables[p.table];
-        std::memcpy(sl.h_in + na, p.addrs.data(), (size_t)p.n * sizeof(planb_addr_t));
+        copies.push_back(CopyJob{sl.h_in + na, p.addrs, (size_t)p.n * sizeof(planb_addr_t)});
         desc[nb] = BurstRec{p.table, p.n, reinterpret_cast<const u64x2*>(sl.d_in + na), sl.d_out + na};
         p.offset = na;
         na += p.n;
@@ -251,6 +289,7 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
         it = s->queue.erase(it);
     }
     if (nb == 0) return PLANB_OK;
+    run_copies(copies, (size_t)na * sizeof(planb_addr_t));
     if (s->launch.fn == nullptr) {  // first launch: the table set now knows fanout and key width
         int rc = tableset_plan(s->ts, maxb, &s->launch);
         if (rc != PLANB_OK) return rc;
@@ -381,7 +420,7 @@ int planb_server_submit(planb_server_t* s, uint32_t table, const planb_addr_t* a
     p.tag = tag;
     p.table = table;
     p.n = n;
-    p.addrs.assign(addrs, addrs + n);
+    p.addrs = addrs;
     p.out = out;
     p.submit_us = now_us();
     s->queue.push_back(std::move(p));

@@ -558,7 +558,7 @@ class Server:
         a = _host(addrs, np.uint64, (2,))
         if out.dtype != np.uint16 or not out.flags.c_contiguous or out.shape[0] < a.shape[0]:
             raise ValueError("out must be a contiguous uint16 array of at least n elements")
-        self._keep[tag] = out
+        self._keep[tag] = (a, out)  # both must outlive the burst
         _check(_lib.planb_server_submit(self.ptr, table_id, a.ctypes.data, a.shape[0], out.ctypes.data, tag))
 
     def poll(self, block: bool = False):
