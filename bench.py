@@ -163,7 +163,10 @@ def learned_leg(P, fib, h_plain, d, n, out, args, plain_glps):
     same = bool(torch.equal(lout, out))
     ts = time_steps(lambda: P.planb_lookup_learned(h, d, n, lout), max(3, args.steps // 2), 1)
     glps = n / (sum(ts) / len(ts)) / 1e9
+    achieved = BYTES_PER_LOOKUP * glps  # GB/s of algorithmic bytes (16 B in, 2 B out per lookup)
     return {"glps": round(glps, 3), "ms_per_step": round(sum(ts) / len(ts) * 1e3, 3),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
             "speedup_vs_plain": round(glps / plain_glps, 4), "fallback_rate": round(fallbacks / n, 6),
             "identical_to_plain": same, "mean_eps": round(rep["mean_eps"], 1), "max_eps": rep["max_eps"],
             "train_seconds": round(train_s, 2), "train_steps": rep["steps"], "fanout": info["fanout"]}
@@ -246,6 +249,29 @@ def cpu_leg(fib, addrs, got):
     return ({"value": round(addrs.shape[0] / dt / 1e9, 5), "unit": "GLPS", "cores": thr, "kind": "oracle",
              "sample": f"the whole batch ({addrs.shape[0]} addresses), binary-trie oracle, {thr} threads, "
                        f"{dt:.1f} s"}, int((got != want).sum()))
+
+
+def cpu_btree_leg(fib, addrs, got):
+    """CPU linearized B+-tree baseline (the same image the GPU descends, searched
+    by the paper's batched branch-free CPU descent) on the host cores: the whole
+    batch on every core used, and one core on a 2^24-address sample."""
+    from paper_2604_14650_amd import planb as P
+    from oracle.trie import default_threads
+    thr = default_threads()
+    tree = P.CpuTree(fib.prefixes, fib.lengths, fib.next_hops, fanout=16)
+    tree.lookup(addrs[:1 << 20], thr)  # warm-up
+    t0 = time.perf_counter()
+    res = tree.lookup(addrs, thr)
+    dt = time.perf_counter() - t0
+    one = addrs[:1 << 24]
+    t1 = time.perf_counter()
+    tree.lookup(one, 1)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(addrs.shape[0] / dt / 1e9, 4), "unit": "GLPS", "cores": thr,
+            "kind": "linearized B+-tree (planb_cpu_lookup, fanout 16, 64-bit keys)",
+            "sample": f"the whole batch ({addrs.shape[0]} addresses), {thr} threads, {dt:.2f} s",
+            "single_core_mlps": round(one.shape[0] / dt1 / 1e6, 1),
+            "mismatches_vs_gpu": int((res != got).sum())}
 
 
 def main():
@@ -336,6 +362,8 @@ def main():
         cb, mism = cpu_leg(fib, addrs, got)
         result["cpu_baseline"] = cb
         result["mismatches_vs_oracle"] = mism
+        result["cpu_btree_baseline"] = cpu_btree_leg(fib, addrs, got)
+        log(f"cpu B+-tree: {result['cpu_btree_baseline']}")
     print(json.dumps(result), flush=True)
 
 

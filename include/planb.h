@@ -469,6 +469,17 @@ long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout
 long long planb_build_image(const planb_addr_t* starts, const uint16_t* next_hops, size_t m, uint32_t fanout,
                             uint32_t key_bits, void* image, size_t cap_bytes, planb_info_t* info);
 
+/*
+ * planb_cpu_lookup -- host-core baseline: the linearized B+-tree lookup of
+ * Section 3 (Algorithm 1, with the paper's batching and branch-free node
+ * search) run on the CPU over the image planb_build_image returns (info: the
+ * shape it reported).  addrs/out: host arrays of n records.  threads <= 0
+ * uses every hardware thread.  For measurements beside the GPU kernel only;
+ * no GPU entry point calls it.  Returns PLANB_OK or PLANB_EINVAL.
+ */
+int planb_cpu_lookup(const void* image, const planb_info_t* info, const planb_addr_t* addrs, size_t n,
+                     uint16_t* out, int threads);
+
 #ifdef __cplusplus
 }
 #endif

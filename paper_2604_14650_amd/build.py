@@ -18,7 +18,9 @@ LIB = os.path.join(PKG, "libplanb.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["lookup.hip", "learned.hip", "batches.hip", "multi.hip"]
-CXX_SOURCES = ["api.cpp", "builder.cpp", "server.cpp"]
+CXX_SOURCES = ["api.cpp", "builder.cpp", "server.cpp", "cpu_btree.cpp"]
+# host code of the CPU baseline: AVX2 vector compares (any x86-64 server since 2015)
+EXTRA_FLAGS = {"cpu_btree.cpp": ["-mavx2"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
@@ -31,7 +33,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *HIP_ONLY, *COMMON, "-c", path, "-o", obj]
     else:  # host C++ that calls the HIP runtime: compiled as host-only HIP code
-        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+        cmd = [HIPCC, *COMMON, *EXTRA_FLAGS.get(src, []), "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -125,6 +125,7 @@ _sig("planb_set_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_build_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz, ctypes.c_uint32, _vp, _vp, _sz)
 _sig("planb_build_keys", ctypes.c_longlong, _vp, _sz, ctypes.c_uint32, _vp, _sz, ctypes.POINTER(planb_info_t))
+_sig("planb_cpu_lookup", ctypes.c_int, _vp, ctypes.POINTER(planb_info_t), _vp, _sz, _vp, ctypes.c_int)
 _sig("planb_build_image", ctypes.c_longlong, _vp, _vp, _sz, ctypes.c_uint32, ctypes.c_uint32, _vp, _sz,
      ctypes.POINTER(planb_info_t))
 _sig("planb_lookup_batches", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
@@ -354,6 +355,25 @@ def planb_build_image(starts, next_hops, fanout: int = 16, key_bits: int = 0):
     img = np.empty(need, dtype=np.uint8)
     _check(_lib.planb_build_image(*args, img.ctypes.data, need, None))
     return img, _info_dict(info)
+
+
+class CpuTree:
+    """Host-core linearized B+-tree baseline over a FIB's device image (planb_cpu_lookup)."""
+
+    def __init__(self, prefixes, lengths, next_hops, fanout: int = 8, key_bits: int = 0):
+        starts, nh = planb_build_intervals(prefixes, lengths, next_hops)
+        self.image, info = planb_build_image(starts, nh, fanout, key_bits)
+        self.info = planb_info_t()
+        _check(_lib.planb_build_image(starts.ctypes.data, nh.ctypes.data, starts.shape[0], fanout, key_bits,
+                                      None, 0, ctypes.byref(self.info)))
+        self.shape = info
+
+    def lookup(self, addrs, threads: int = 0) -> np.ndarray:
+        a = _host(addrs, np.uint64, (2,))
+        out = np.empty(a.shape[0], dtype=np.uint16)
+        _check(_lib.planb_cpu_lookup(self.image.ctypes.data, ctypes.byref(self.info), a.ctypes.data, a.shape[0],
+                                     out.ctypes.data, threads))
+        return out
 
 
 def batch_array(batches):

@@ -375,3 +375,20 @@ def test_device_image_key_width_choice():
         P.planb_build_image(S.from_ints(vals), nh, 8, 64)
     with pytest.raises(P.PlanbError):
         P.planb_build_image(S.from_ints([1, 2]), nh[:2], 8, 0)  # starts[0] must be 0
+
+
+# ------------------------------------------------------------- CPU baseline
+@pytest.mark.parametrize("b", [8, 16, 32])
+@pytest.mark.parametrize("key_bits", [0, 128])
+def test_cpu_btree_baseline_matches_oracle(b, key_bits):
+    """The host-core linearized B+-tree (planb_cpu_lookup over the device image)
+    returns the oracle's next hops."""
+    from oracle.trie import Trie
+    fib = S.make_fib(S.vrf_spec(3000), 31 + b)
+    addrs = S.mixed_traffic(fib, 20000, 0.5, 7 + b)
+    addrs = np.concatenate([addrs, S.from_ints([0, 1, (1 << 128) - 1, (1 << 128) - 2])])
+    tree = P.CpuTree(fib.prefixes, fib.lengths, fib.next_hops, fanout=b, key_bits=key_bits)
+    assert tree.shape["key_bits"] == (key_bits or 64)
+    want = Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(addrs)
+    for threads in (1, 3):
+        assert np.array_equal(tree.lookup(addrs, threads), want)
