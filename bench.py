@@ -208,34 +208,51 @@ def batches_leg(P, h, d, n, out, seed=1044, count=96):
 
 
 def serving_leg(P, log_fn, n_tables=16, bursts_per_level=3000):
+    """16 VRF tables behind the serving runtime, plain and learned: capacity
+    (every burst at once, after an untimed warm-up pass that pays one-time
+    costs such as first touches of pinned staging), then open-loop Poisson
+    arrivals at 25/50/80 % of the plain capacity, the same arrival sequences
+    for both modes."""
     import planb_synth as S
     from paper_2604_14650_amd import serve
     t0 = time.time()
     tabs = S.vrf_tables(n_tables, seed=5000)
     log_fn(f"serving: {n_tables} tables, {sum(len(t) for t in tabs)} prefixes ({time.time() - t0:.1f} s)")
-    srv = P.Server(max_tables=n_tables, streams=3, max_bursts=256, max_lookups=1 << 18, fanout=16, key_bits=64)
-    for k, t in enumerate(tabs):
-        srv.set_table(k, t.prefixes, t.lengths, t.next_hops)
-        srv.admit(k)
     rng = np.random.default_rng(77)
     sizes = S.log_uniform_sizes(rng, bursts_per_level, 32, 4096)
     tids = rng.integers(0, n_tables, size=bursts_per_level)
     addrs = [S.mixed_traffic(tabs[t], int(m), 0.5, int(rng.integers(0, 2**62))) for t, m in zip(tids, sizes)]
-    # capacity: every burst arrives at once (after one untimed warm-up pass: the
-    # first pass pays one-time costs such as first touches of pinned staging)
-    serve.replay_native(srv, np.zeros(len(sizes)), tids, addrs)
-    lat, wall, _ = serve.replay_native(srv, np.zeros(len(sizes)), tids, addrs)
-    cap = serve.summary(lat, sizes, wall)
-    res = {"tables": n_tables, "prefixes": int(sum(len(t) for t in tabs)), "capacity_glps": round(cap["glps"], 4)}
     mean_burst = float(np.mean(sizes))
-    for load in (0.25, 0.5, 0.8):
-        rate = load * cap["glps"] * 1e9 / mean_burst  # bursts per second
-        arr = np.cumsum(rng.exponential(1.0 / rate, size=len(sizes)))
-        lat, wall, outs = serve.replay_native(srv, arr, tids, addrs)
-        s = serve.summary(lat, sizes, wall)
-        res[f"load_{int(load * 100)}"] = {k: round(v, 3) if isinstance(v, float) else v for k, v in s.items()}
-    res["stats"] = srv.stats()
-    srv.close()
+    res = {"tables": n_tables, "prefixes": int(sum(len(t) for t in tabs))}
+    arrivals = {}
+    for mode in ("plain", "learned"):
+        srv = P.Server(max_tables=n_tables, streams=3, max_bursts=256, max_lookups=1 << 18, fanout=16, key_bits=64,
+                       learned=(mode == "learned"))
+        t1 = time.time()
+        for k, t in enumerate(tabs):
+            srv.set_table(k, t.prefixes, t.lengths, t.next_hops)
+            srv.admit(k)  # builds (and, learned, trains) the table
+        admit_s = time.time() - t1
+        serve.replay_native(srv, np.zeros(len(sizes)), tids, addrs)
+        lat, wall, outs = serve.replay_native(srv, np.zeros(len(sizes)), tids, addrs)
+        cap = serve.summary(lat, sizes, wall)
+        r = {"capacity_glps": round(cap["glps"], 4), "admit_seconds": round(admit_s, 2)}
+        if mode == "plain":
+            plain_outs = outs
+            for load in (0.25, 0.5, 0.8):
+                rate = load * cap["glps"] * 1e9 / mean_burst  # bursts per second
+                arrivals[load] = np.cumsum(np.random.default_rng(int(load * 100)).exponential(1.0 / rate, size=len(sizes)))
+        else:
+            r["identical_to_plain"] = all(np.array_equal(a, b) for a, b in zip(outs, plain_outs))
+        for load, arr in arrivals.items():
+            lat, wall, _ = serve.replay_native(srv, arr, tids, addrs)
+            sm = serve.summary(lat, sizes, wall)
+            r[f"load_{int(load * 100)}"] = {k: round(v, 3) if isinstance(v, float) else v for k, v in sm.items()}
+        r["stats"] = srv.stats()
+        srv.close()
+        res[mode] = r
+        log_fn(f"serving {mode}: {r}")
+    res["capacity_glps"] = res["plain"]["capacity_glps"]
     return res
 
 

@@ -353,6 +353,15 @@ int planb_tableset_set_tuning(planb_tableset_t* ts, uint32_t keys_per_lane, uint
 /* 4 * (max_bursts + block_threads + 1) bytes of LDS must fit a workgroup. */
 int planb_lookup_multi(const planb_tableset_t* ts, const planb_burst_t* bursts, const uint32_t* n_bursts,
                        uint32_t max_bursts, void* stream);
+/* The learned lookup (planb_lookup_learned) for each burst whose FIB has a
+ * trained model (the model as it was when the FIB was set into the slot: set
+ * it again after training), the tree descent for the others; results are
+ * those of planb_lookup_multi.  fallback_count (device u32, may be NULL) is
+ * increased by the number of learned lookups that fell back to the tree.
+ * Descriptors as for planb_lookup_multi; LDS: 4 * (max_bursts + 257) + 3072
+ * bytes must fit a workgroup. */
+int planb_lookup_multi_learned(const planb_tableset_t* ts, const planb_burst_t* bursts, const uint32_t* n_bursts,
+                               uint32_t max_bursts, uint32_t* fallback_count, void* stream);
 void planb_tableset_free(planb_tableset_t* ts);
 
 /*
@@ -379,6 +388,9 @@ typedef struct planb_server_cfg {
     uint32_t fanout;        /* fanout of every table (0 -> 16) */
     uint32_t key_bits;      /* 64 or 128 for every table (0 -> 128) */
     uint64_t memory_budget; /* device bytes for resident trees (0 = unlimited) */
+    uint32_t learned;       /* 1: train a learned model for every table when it is admitted and
+                               serve bursts with planb_lookup_multi_learned (0: planb_lookup_multi) */
+    uint32_t reserved;      /* 0 */
 } planb_server_cfg_t;
 
 typedef struct planb_completion {

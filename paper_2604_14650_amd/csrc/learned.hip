@@ -18,7 +18,9 @@
 #include <vector>
 
 #include "api_internal.hpp"
+#include "burst_tiles.hpp"
 #include "descent.hpp"
+#include "learned.hpp"
 
 namespace planb {
 
@@ -43,13 +45,6 @@ __host__ __device__ inline uint16_t f2bf(float f)
 }
 
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-struct ModelDesc {
-    const uint16_t* wb;  // bfloat16 copy of the flat parameter vector (W1, W2, w3 are read from it)
-    const float* w;      // float32 master vector (biases are read from it)
-    const uint32_t* eps; // per-segment error bound, kEmpty = no training point predicts there
-    uint32_t segments;
-};
 
 // Per-lane MFMA A operands of the two weight matrices (40 VGPRs).
 struct MlpRegs {
@@ -184,68 +179,134 @@ __device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_
 
 constexpr int kLearnBlock = 256;
 
-// Learned lookup: 64 addresses per wavefront step (4 MFMA tiles of 16), then
-// one lane per address for the window search, verification and fallback.
+// One wavefront step of the learned lookup: addresses [base, base + 64) of a
+// batch of n (4 MFMA tiles of 16), then one lane per address for the window
+// search, verification and fallback.  R holds the model's weight operands and
+// sb1/sb2/sw3 its biases and output weights as float.
+template <int B, bool WIDE>
+__device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const MlpRegs& R, const float* sb1,
+                                    const float* sb2, const float* sw3, float b3, const u64x2* addrs, uint64_t base,
+                                    uint64_t n, uint16_t* out, uint32_t* fallbacks)
+{
+    using KF = KeyFmt<WIDE>;
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const uint64_t m = t.m_minus_1 + 1;
+    float y = 0.f;
+    uint64_t xhi = 0, xlo = 0;
+#pragma unroll
+    for (int tile = 0; tile < 4; ++tile) {
+        const uint64_t i = base + 16 * tile + c;
+        const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
+        Activations A;
+        const float yt = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
+        if (g == tile) {
+            y = yt;
+            xhi = a.x;
+            xlo = a.y;
+        }
+    }
+    // this lane's address is base + 16g + c = base + l
+    const uint64_t p = predict_position(y, m);
+    const uint32_t seg = (uint32_t)(p * M.segments / m);
+    const uint32_t e0 = M.eps[seg];
+    bool ok = e0 != kEmpty;
+    // widen the bound by half plus 16: interior addresses can err a little
+    // more than the sampled points; each doubling costs one probe
+    const uint64_t e = ok ? (uint64_t)e0 + (e0 >> 1) + 16 : 0;
+    uint64_t j = 0;
+    if (ok) {
+        uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
+        ok = KF::le(leaf_key<B, WIDE>(t, lo), xhi, xlo) &&
+             (hi == m - 1 || !KF::le(leaf_key<B, WIDE>(t, hi + 1), xhi, xlo));
+        if (ok) {  // last index in [lo, hi] whose key is <= x
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi + 1) >> 1;
+                if (KF::le(leaf_key<B, WIDE>(t, mid), xhi, xlo)) lo = mid; else hi = mid - 1;
+            }
+            j = lo;
+        }
+    }
+    const uint64_t i = base + l;
+    const bool need = !ok && i < n;
+    if (need) j = descend_lane<B, WIDE>(t, xhi, xlo);
+    if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
+    if (fallbacks) {
+        const uint64_t mask = __ballot(need);
+        if (l == 0 && mask) atomicAdd(fallbacks, (uint32_t)__popcll(mask));
+    }
+}
+
+// Learned lookup of one batch (grid stride over 64-address wavefront steps).
 template <int B, bool WIDE>
 __global__ void __launch_bounds__(kLearnBlock)
 learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out,
                uint32_t* __restrict__ fallbacks)
 {
-    using KF = KeyFmt<WIDE>;
     __shared__ float sb1[kH], sb2[kH], sw3[kH];
     stage_small(M, sb1, sb2, sw3);
     __syncthreads();
     MlpRegs R;
     load_regs(M.wb, R);
     const float b3 = M.w[ob3];
-    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
-    const uint64_t m = t.m_minus_1 + 1;
     const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
-    for (uint64_t base = wave * 64; base < n; base += nwaves * 64) {
-        float y = 0.f;
-        uint64_t xhi = 0, xlo = 0;
-#pragma unroll
-        for (int tile = 0; tile < 4; ++tile) {
-            const uint64_t i = base + 16 * tile + c;
-            const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
-            Activations A;
-            const float yt = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
-            if (g == tile) {
-                y = yt;
-                xhi = a.x;
-                xlo = a.y;
+    for (uint64_t base = wave * 64; base < n; base += nwaves * 64)
+        learned_step<B, WIDE>(t, M, R, sb1, sb2, sw3, b3, addrs, base, n, out, fallbacks);
+}
+
+// Learned lookups of bursts that each name a table: tiles of 64 addresses
+// (one wavefront step) never cross a burst, so every step runs one table's
+// model.  A wavefront reloads the weight operands, and restages the biases in
+// its own LDS area, when its tile's table changes; a table without a model
+// is searched by the tree descent.
+template <int B, bool WIDE>
+__global__ void __launch_bounds__(kLearnBlock)
+multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __restrict__ models, uint32_t n_tables,
+                     const BurstRec* __restrict__ bursts, const uint32_t* __restrict__ count, uint32_t max_bursts,
+                     uint32_t* __restrict__ fallbacks)
+{
+    extern __shared__ uint32_t lds_u32[];
+    uint32_t* tile_off = lds_u32;                                   // max_bursts + 1
+    uint32_t* part = tile_off + max_bursts + 1;                     // kLearnBlock
+    float* small = reinterpret_cast<float*>(part + kLearnBlock) + (threadIdx.x >> 6) * 3 * kH;  // this wave's
+    float *sb1 = small, *sb2 = small + kH, *sw3 = small + 2 * kH;
+    auto live = [&](uint32_t tb) { return tb < n_tables && tables[tb].depth != 0; };
+    const uint32_t nb = plan_burst_tiles<kLearnBlock>(bursts, count, max_bursts, 64, live, tile_off, part);
+    const uint32_t total = tile_off[nb];
+    const uint32_t nwaves = gridDim.x * (kLearnBlock / 64);
+    const int l = threadIdx.x & 63;
+    MlpRegs R;
+    float b3 = 0.f;
+    uint32_t loaded = 0xFFFFFFFFu;  // table whose model R and the staged vectors hold
+    for (uint32_t tile = blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6); tile < total; tile += nwaves) {
+        const uint32_t k = burst_of_tile(tile_off, nb, tile);
+        const BurstRec br = bursts[k];
+        const TreeDesc& t = tables[br.table];
+        const ModelDesc M = models[br.table];
+        const uint64_t base = (uint64_t)(tile - tile_off[k]) * 64;
+        const u64x2* addrs = br.addrs;
+        uint16_t* out = static_cast<uint16_t*>(br.out);
+        if (M.wb == nullptr) {  // no model: the tree descent, one lane per address
+            const uint64_t i = base + l;
+            if (i < br.n) {
+                const u64x2 a = __builtin_nontemporal_load(addrs + i);
+                __builtin_nontemporal_store(t.vals[descend_lane<B, WIDE>(t, a.x, a.y)], out + i);
             }
+            continue;
         }
-        // this lane's address is base + 16g + c = base + l
-        const uint64_t p = predict_position(y, m);
-        const uint32_t seg = (uint32_t)(p * M.segments / m);
-        const uint32_t e0 = M.eps[seg];
-        bool ok = e0 != kEmpty;
-        // widen the bound by half plus 16: interior addresses can err a little
-        // more than the sampled points; each doubling costs one probe
-        const uint64_t e = ok ? (uint64_t)e0 + (e0 >> 1) + 16 : 0;
-        uint64_t j = 0;
-        if (ok) {
-            uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
-            ok = KF::le(leaf_key<B, WIDE>(t, lo), xhi, xlo) &&
-                 (hi == m - 1 || !KF::le(leaf_key<B, WIDE>(t, hi + 1), xhi, xlo));
-            if (ok) {  // last index in [lo, hi] whose key is <= x
-                while (lo < hi) {
-                    const uint64_t mid = (lo + hi + 1) >> 1;
-                    if (KF::le(leaf_key<B, WIDE>(t, mid), xhi, xlo)) lo = mid; else hi = mid - 1;
-                }
-                j = lo;
-            }
+        if (br.table != loaded) {  // uniform across the wavefront
+            load_regs(M.wb, R);
+            b3 = M.w[ob3];
+            sb1[l] = M.w[ob1 + l];
+            sb2[l] = M.w[ob2 + l];
+            sw3[l] = bf2f(M.wb[ow3 + l]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            loaded = br.table;
         }
-        const uint64_t i = base + l;
-        const bool need = !ok && i < n;
-        if (need) j = descend_lane<B, WIDE>(t, xhi, xlo);
-        if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
-        if (fallbacks) {
-            const uint64_t mask = __ballot(need);
-            if (l == 0 && mask) atomicAdd(fallbacks, (uint32_t)__popcll(mask));
-        }
+        learned_step<B, WIDE>(t, M, R, sb1, sb2, sw3, b3, addrs, base, br.n, out, fallbacks);
+        __builtin_amdgcn_wave_barrier();  // the next tile may restage the vectors
     }
 }
 
@@ -697,6 +758,57 @@ void release_learned(planb_fib_t* f)
         if (p) (void)hipFree(p);
     delete L;
     f->learned = nullptr;
+}
+
+size_t learned_model_bytes(uint32_t segments)
+{
+    if (segments == 0) segments = 4096;
+    return (size_t)kParams * (3 * 4 + 2) + (size_t)segments * 4 + (size_t)LearnedModel{}.max_parts * kParams * 4;
+}
+
+ModelDesc ready_model_desc(const planb_fib_t* f)
+{
+    if (!f || !f->learned || !f->learned->has_eps) return ModelDesc{nullptr, nullptr, nullptr, 0};
+    return model_desc(f->learned);
+}
+
+namespace {
+
+template <int B, bool W>
+struct MultiLearnedKernel {
+    static const void* get() { return reinterpret_cast<const void*>(multi_learned_kernel<B, W>); }
+};
+
+}  // namespace
+
+int plan_multi_learned(int fanout, bool wide, uint32_t max_bursts, MultiLaunch* L)
+{
+    const void* fn = nullptr;
+    switch (fanout) {
+    case 8: fn = wide ? MultiLearnedKernel<8, true>::get() : MultiLearnedKernel<8, false>::get(); break;
+    case 16: fn = wide ? MultiLearnedKernel<16, true>::get() : MultiLearnedKernel<16, false>::get(); break;
+    case 32: fn = wide ? MultiLearnedKernel<32, true>::get() : MultiLearnedKernel<32, false>::get(); break;
+    default: return fail(PLANB_EINVAL, "no learned multi-FIB kernel for this fanout");
+    }
+    DevProps p;
+    hipError_t e = dev_props(&p);
+    if (e != hipSuccess) return fail_hip(e, "device properties");
+    L->fn = fn;
+    L->block = kLearnBlock;
+    L->lds = ((size_t)max_bursts + 1 + kLearnBlock) * 4 + (size_t)(kLearnBlock / 64) * 3 * kH * 4;
+    if (L->lds > (size_t)p.max_lds) return fail(PLANB_ERANGE, "too many bursts per launch for the LDS");
+    int nb = 1;
+    if ((e = occupancy(fn, kLearnBlock, L->lds, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
+    L->grid = (unsigned)(p.cus * nb);
+    return PLANB_OK;
+}
+
+hipError_t launch_multi_learned(const MultiLaunch& L, const TreeDesc* tables, const ModelDesc* models,
+                                uint32_t n_tables, const BurstRec* bursts, const uint32_t* count,
+                                uint32_t max_bursts, uint32_t* fallbacks, hipStream_t stream)
+{
+    void* args[] = {&tables, &models, &n_tables, &bursts, &count, &max_bursts, &fallbacks};
+    return hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, L.lds, stream);
 }
 
 }  // namespace planb

@@ -5,7 +5,9 @@
 // the uneven-batch kernel, and every tile descends its burst's table with all
 // levels read through the caches (no per-table LDS staging).
 #include "api_internal.hpp"
+#include "burst_tiles.hpp"
 #include "descent.hpp"
+#include "learned.hpp"
 #include "multi.hpp"
 
 namespace planb {
@@ -19,43 +21,15 @@ multi_kernel(const TreeDesc* __restrict__ tables, uint32_t n_tables, const Burst
     extern __shared__ uint32_t lds_u32[];
     uint32_t* tile_off = lds_u32;                 // max_bursts + 1
     uint32_t* part = tile_off + max_bursts + 1;   // BS
-    const uint32_t nb = min(*count, max_bursts);
-    const uint32_t per = (nb + BS - 1) / BS;
-    const uint32_t b0 = min(threadIdx.x * per, nb), b1 = min(b0 + per, nb);
-    auto tiles_of = [&](uint32_t b) -> uint32_t {  // bursts naming an empty or unknown slot are skipped
-        const uint32_t tb = bursts[b].table;
-        return tb < n_tables && tables[tb].depth ? (uint32_t)((bursts[b].n + D::kStep - 1) / D::kStep) : 0u;
-    };
-    uint32_t local = 0;
-    for (uint32_t b = b0; b < b1; ++b) local += tiles_of(b);
-    part[threadIdx.x] = local;
-    __syncthreads();
-    for (uint32_t o = 1; o < BS; o <<= 1) {
-        uint32_t v = part[threadIdx.x];
-        if (threadIdx.x >= o) v += part[threadIdx.x - o];
-        __syncthreads();
-        part[threadIdx.x] = v;
-        __syncthreads();
-    }
-    uint32_t acc = part[threadIdx.x] - local;
-    for (uint32_t b = b0; b < b1; ++b) {
-        tile_off[b] = acc;
-        acc += tiles_of(b);
-    }
-    if (threadIdx.x == BS - 1) tile_off[nb] = part[BS - 1];
-    __syncthreads();
-
+    auto live = [&](uint32_t tb) { return tb < n_tables && tables[tb].depth != 0; };
+    const uint32_t nb = plan_burst_tiles<BS>(bursts, count, max_bursts, D::kStep, live, tile_off, part);
     const uint32_t total = tile_off[nb];
     const uint32_t nwaves = gridDim.x * (BS / 64);
     for (uint32_t tile = blockIdx.x * (BS / 64) + (threadIdx.x >> 6); tile < total; tile += nwaves) {
-        uint32_t lo = 0, hi = nb;  // tile_off[lo] <= tile < tile_off[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (tile_off[mid] <= tile) lo = mid; else hi = mid;
-        }
-        const BurstRec br = bursts[lo];
+        const uint32_t k = burst_of_tile(tile_off, nb, tile);
+        const BurstRec br = bursts[k];
         const TreeDesc& t = tables[br.table];
-        D::step(t, nullptr, br.addrs, (uint64_t)(tile - tile_off[lo]) * D::kStep, br.n, br.out, 0);
+        D::step(t, nullptr, br.addrs, (uint64_t)(tile - tile_off[k]) * D::kStep, br.n, br.out, 0);
     }
 }
 
@@ -100,6 +74,7 @@ struct planb_tableset {
     TreeDesc* dev = nullptr;         // max_tables descriptors (depth 0 = empty slot)
     std::vector<TreeDesc> host;
     std::vector<const planb_fib_t*> fibs;
+    ModelDesc* dev_models = nullptr; // max_tables model descriptors (wb == NULL: no model)
     uint32_t max_tables = 0;
     int fanout = 0;                  // shared by every FIB of the set (0 until the first)
     int key_bytes = 0;
@@ -130,9 +105,12 @@ planb_tableset_t* planb_tableset_create(uint32_t max_tables)
     hipError_t e = hipGetDevice(&ts->device);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ts->dev), sizeof(TreeDesc) * max_tables);
     if (e == hipSuccess) e = hipMemset(ts->dev, 0, sizeof(TreeDesc) * max_tables);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ts->dev_models), sizeof(ModelDesc) * max_tables);
+    if (e == hipSuccess) e = hipMemset(ts->dev_models, 0, sizeof(ModelDesc) * max_tables);
     if (e != hipSuccess) {
         fail_hip(e, "creating a table set");
         if (ts->dev) (void)hipFree(ts->dev);
+        if (ts->dev_models) (void)hipFree(ts->dev_models);
         delete ts;
         return nullptr;
     }
@@ -144,6 +122,7 @@ void planb_tableset_free(planb_tableset_t* ts)
     if (!ts) return;
     (void)hipDeviceSynchronize();
     if (ts->dev) (void)hipFree(ts->dev);
+    if (ts->dev_models) (void)hipFree(ts->dev_models);
     delete ts;
 }
 
@@ -167,7 +146,9 @@ int planb_tableset_set(planb_tableset_t* ts, uint32_t slot, const planb_fib_t* f
         d.lds_levels = 0;
         d.lds_slots = 0;
     }
+    const ModelDesc md = ready_model_desc(fib);
     hipError_t e = hipMemcpy(ts->dev + slot, &d, sizeof(TreeDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ts->dev_models + slot, &md, sizeof(ModelDesc), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail_hip(e, "writing a table descriptor");
     ts->host[slot] = d;
     ts->fibs[slot] = fib;
@@ -204,10 +185,32 @@ int planb_lookup_multi(const planb_tableset_t* ts, const planb_burst_t* bursts, 
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "multi-FIB launch");
 }
 
+int planb_lookup_multi_learned(const planb_tableset_t* ts, const planb_burst_t* bursts, const uint32_t* n_bursts,
+                               uint32_t max_bursts, uint32_t* fallback_count, void* stream)
+{
+    if (!ts) return fail(PLANB_EINVAL, "NULL table set");
+    if (max_bursts == 0 || ts->fanout == 0) return PLANB_OK;
+    if (!bursts || !n_bursts || reinterpret_cast<uintptr_t>(bursts) % 8 ||
+        reinterpret_cast<uintptr_t>(n_bursts) % 4 || reinterpret_cast<uintptr_t>(fallback_count) % 4)
+        return fail(PLANB_EINVAL, "NULL or misaligned descriptor pointer");
+    MultiLaunch L;
+    int rc = plan_multi_learned(ts->fanout, ts->key_bytes == 16, max_bursts, &L);
+    if (rc != PLANB_OK) return rc;
+    hipError_t e = launch_multi_learned(L, ts->dev, ts->dev_models, ts->max_tables,
+                                        reinterpret_cast<const BurstRec*>(bursts), n_bursts, max_bursts,
+                                        fallback_count, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "learned multi-FIB launch");
+}
+
 }  // extern "C"
 
 namespace planb {
 const TreeDesc* tableset_device(const planb_tableset_t* ts) { return ts->dev; }
+const ModelDesc* tableset_models(const planb_tableset_t* ts) { return ts->dev_models; }
+int tableset_plan_learned(const planb_tableset_t* ts, uint32_t max_bursts, MultiLaunch* L)
+{
+    return plan_multi_learned(ts->fanout ? ts->fanout : 16, ts->key_bytes == 16, max_bursts, L);
+}
 uint32_t tableset_capacity(const planb_tableset_t* ts) { return ts->max_tables; }
 int tableset_plan(const planb_tableset_t* ts, uint32_t max_bursts, MultiLaunch* L)
 {

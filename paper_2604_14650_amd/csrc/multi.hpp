@@ -25,6 +25,9 @@ hipError_t launch_multi(const MultiLaunch& L, const TreeDesc* tables, uint32_t n
                         const uint32_t* count, uint32_t max_bursts, hipStream_t stream);
 
 const TreeDesc* tableset_device(const planb_tableset_t* ts);
+struct ModelDesc;
+const ModelDesc* tableset_models(const planb_tableset_t* ts);
+int tableset_plan_learned(const planb_tableset_t* ts, uint32_t max_bursts, MultiLaunch* L);
 uint32_t tableset_capacity(const planb_tableset_t* ts);
 int tableset_plan(const planb_tableset_t* ts, uint32_t max_bursts, MultiLaunch* L);
 

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "api_internal.hpp"
+#include "learned.hpp"
 #include "multi.hpp"
 
 using namespace planb;
@@ -119,7 +120,7 @@ void server_release(planb_server_t* s)
 }
 
 // Device bytes planb_build will allocate for the table (same layout arithmetic).
-size_t table_bytes(const Table& t, uint32_t fanout, uint32_t key_bits)
+size_t table_bytes(const Table& t, uint32_t fanout, uint32_t key_bits, bool learned)
 {
     const int kb = (int)key_bits / 8;
     Layout lay;
@@ -127,7 +128,7 @@ size_t table_bytes(const Table& t, uint32_t fanout, uint32_t key_bits)
     if (plan_layout(t.m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, kb),
                     (uint32_t)leaf_slots_for((int)fanout, kb), true, &lay, &err) != 0)
         return SIZE_MAX;
-    return lay.total_slots() * kb + (t.m + 63) / 64 * 64 * 2;
+    return lay.total_slots() * kb + (t.m + 63) / 64 * 64 * 2 + (learned ? learned_model_bytes(0) : 0);
 }
 
 // Make table `id` resident; false if the budget cannot be met right now
@@ -138,7 +139,7 @@ int admit(planb_server_t* s, uint32_t id, bool* ok)
     *ok = true;
     if (t.fib) return PLANB_OK;
     const uint64_t budget = s->cfg.memory_budget;
-    const size_t need = table_bytes(t, s->cfg.fanout, s->cfg.key_bits);
+    const size_t need = table_bytes(t, s->cfg.fanout, s->cfg.key_bits, s->cfg.learned != 0);
     if (budget) {
         if (need > budget) return fail(PLANB_ERANGE, "table " + std::to_string(id) + " alone exceeds the budget");
         while (s->used_bytes + need > budget) {
@@ -167,13 +168,18 @@ int admit(planb_server_t* s, uint32_t id, bool* ok)
     p.key_bits = s->cfg.key_bits;
     planb_fib_t* f = planb_build_ex(t.pfx.data(), t.len.data(), t.nh.data(), t.len.size(), &p);
     if (!f) return planb_last_status() ? planb_last_status() : PLANB_EDEVICE;
-    int rc = planb_tableset_set(s->ts, id, f);
+    int rc = PLANB_OK;
+    if (s->cfg.learned && (rc = planb_train(f, nullptr, nullptr, nullptr)) != PLANB_OK) {
+        free_fib_nosync(f);
+        return rc;
+    }
+    rc = planb_tableset_set(s->ts, id, f);
     if (rc != PLANB_OK) {
         free_fib_nosync(f);
         return rc;
     }
     t.fib = f;
-    t.bytes = f->key_bytes + f->value_bytes;
+    t.bytes = f->key_bytes + f->value_bytes + (f->learned ? learned_model_bytes(0) : 0);
     s->used_bytes += t.bytes;
     ++s->stats.admissions;
     return PLANB_OK;
@@ -291,17 +297,20 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
     if (nb == 0) return PLANB_OK;
     run_copies(copies, (size_t)na * sizeof(planb_addr_t));
     if (s->launch.fn == nullptr) {  // first launch: the table set now knows fanout and key width
-        int rc = tableset_plan(s->ts, maxb, &s->launch);
+        int rc = s->cfg.learned ? tableset_plan_learned(s->ts, maxb, &s->launch) : tableset_plan(s->ts, maxb, &s->launch);
         if (rc != PLANB_OK) return rc;
     }
+    const BurstRec* d_bursts = reinterpret_cast<const BurstRec*>(sl.d_desc + 16);
+    const uint32_t* d_count = reinterpret_cast<const uint32_t*>(sl.d_desc);
     std::memcpy(sl.h_desc, &nb, sizeof(uint32_t));
     hipError_t e;
     if ((e = hipMemcpyAsync(sl.d_in, sl.h_in, (size_t)na * 16, hipMemcpyHostToDevice, sl.st)) != hipSuccess ||
         (e = hipMemcpyAsync(sl.d_desc, sl.h_desc, 16 + (size_t)nb * sizeof(BurstRec), hipMemcpyHostToDevice, sl.st)) !=
             hipSuccess ||
-        (e = launch_multi(s->launch, tableset_device(s->ts), tableset_capacity(s->ts),
-                          reinterpret_cast<const BurstRec*>(sl.d_desc + 16), reinterpret_cast<const uint32_t*>(sl.d_desc),
-                          maxb, sl.st)) != hipSuccess ||
+        (e = s->cfg.learned ? launch_multi_learned(s->launch, tableset_device(s->ts), tableset_models(s->ts),
+                                                   tableset_capacity(s->ts), d_bursts, d_count, maxb, nullptr, sl.st)
+                            : launch_multi(s->launch, tableset_device(s->ts), tableset_capacity(s->ts), d_bursts,
+                                           d_count, maxb, sl.st)) != hipSuccess ||
         (e = hipMemcpyAsync(sl.h_out, sl.d_out, (size_t)na * 2, hipMemcpyDeviceToHost, sl.st)) != hipSuccess ||
         (e = hipEventRecord(sl.done, sl.st)) != hipSuccess)
         return fail_hip(e, "server launch");
@@ -334,7 +343,7 @@ planb_server_t* planb_server_create(const planb_server_cfg_t* cfg_in)
         fail(PLANB_EINVAL, "server fanout must be 8/16/32 and key_bits 64 or 128");
         return nullptr;
     }
-    if (cfg.streams > 8 || cfg.max_tables > 65536 || cfg.max_bursts > 16384) {
+    if (cfg.streams > 8 || cfg.max_tables > 65536 || cfg.max_bursts > 16384 || cfg.learned > 1 || cfg.reserved) {
         fail(PLANB_EINVAL, "server configuration out of range");
         return nullptr;
     }

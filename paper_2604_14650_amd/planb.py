@@ -85,7 +85,7 @@ class planb_burst_t(ctypes.Structure):
 class planb_server_cfg_t(ctypes.Structure):
     _fields_ = [("max_tables", ctypes.c_uint32), ("streams", ctypes.c_uint32), ("max_bursts", ctypes.c_uint32),
                 ("max_lookups", ctypes.c_uint32), ("fanout", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
-                ("memory_budget", ctypes.c_uint64)]
+                ("memory_budget", ctypes.c_uint64), ("learned", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class planb_completion_t(ctypes.Structure):
@@ -148,6 +148,7 @@ _sig("planb_tableset_create", _vp, ctypes.c_uint32)
 _sig("planb_tableset_set", ctypes.c_int, _vp, ctypes.c_uint32, _vp)
 _sig("planb_tableset_set_tuning", ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32)
 _sig("planb_lookup_multi", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
+_sig("planb_lookup_multi_learned", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp, _vp)
 _sig("planb_tableset_free", None, _vp)
 _sig("planb_server_create", _vp, ctypes.POINTER(planb_server_cfg_t))
 _sig("planb_server_free", None, _vp)
@@ -553,12 +554,20 @@ def planb_lookup_multi(ts: TableSet, bursts_dev, n_bursts_dev, max_bursts: int, 
                                    max_bursts, _stream_handle(stream)))
 
 
+def planb_lookup_multi_learned(ts: TableSet, bursts_dev, n_bursts_dev, max_bursts: int, fallback_count=None,
+                               stream=None):
+    fb = _dev_ptr(fallback_count, "fallback_count") if fallback_count is not None else None
+    _check(_lib.planb_lookup_multi_learned(ts.ptr, _dev_ptr(bursts_dev, "bursts"), _dev_ptr(n_bursts_dev, "n_bursts"),
+                                           max_bursts, fb, _stream_handle(stream)))
+
+
 class Server:
     """Owner of a planb_server_t* (see planb.h for the semantics)."""
 
     def __init__(self, max_tables=16, streams=2, max_bursts=1024, max_lookups=1 << 20, fanout=16, key_bits=128,
-                 memory_budget=0):
-        self.cfg = planb_server_cfg_t(max_tables, streams, max_bursts, max_lookups, fanout, key_bits, memory_budget)
+                 memory_budget=0, learned=False):
+        self.cfg = planb_server_cfg_t(max_tables, streams, max_bursts, max_lookups, fanout, key_bits, memory_budget,
+                                      1 if learned else 0, 0)
         self.ptr = _lib.planb_server_create(ctypes.byref(self.cfg))
         if not self.ptr:
             raise PlanbError(planb_last_status(), planb_last_error())

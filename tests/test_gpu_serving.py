@@ -66,6 +66,57 @@ def test_multi_fib_launch(P, vrfs):
                 assert np.array_equal(seg, tries[tids[i]].lookup(addrs[i])), (kpl, i)
 
 
+def test_multi_fib_learned_launch(P, vrfs):
+    """Learned multi-FIB lookups equal the oracle burst by burst, tables with
+    and without a trained model mixed in one launch (one slot empty)."""
+    import torch
+    tabs, tries = vrfs
+    ts = P.TableSet(8)
+    fibs = [P.planb_build(t.prefixes, t.lengths, t.next_hops, fanout=16) for t in tabs]
+    for k, f in enumerate(fibs):
+        if k % 2 == 0:
+            P.planb_train(f, seed=k)
+        ts.set(k, f)  # set after training: the slot takes the model as it is now
+    sizes, tids, addrs = _bursts(tabs, 200, 6)
+    sizes[4] = 0
+    addrs[4] = addrs[4][:0]
+    tids[7] = 7  # an empty slot: skipped
+    flat = np.concatenate(addrs)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    d = to_dev(flat)
+    out = torch.full((len(flat),), -1, dtype=torch.int16, device="cuda")
+    rows = [(int(tids[i]), d[offs[i]:], out[offs[i]:], int(sizes[i])) if sizes[i] else (int(tids[i]), 0, 0, 0)
+            for i in range(len(sizes))]
+    desc = torch.from_numpy(np.frombuffer(bytes(P.burst_array(rows)), dtype=np.uint8).copy()).cuda()
+    cnt = torch.tensor([len(rows)], dtype=torch.int32, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.planb_lookup_multi_learned(ts, desc, cnt, len(rows), fb)
+    got = host_u16(out, len(flat))
+    say(f"learned multi-FIB fallbacks {int(fb.item())} of {len(flat)}")
+    for i in range(len(sizes)):
+        seg = got[offs[i]:offs[i + 1]]
+        if tids[i] == 7:
+            assert np.all(seg == 0xFFFF)
+        elif sizes[i]:
+            assert np.array_equal(seg, tries[tids[i]].lookup(addrs[i])), i
+
+
+def test_learned_server_equals_oracle(P, vrfs):
+    tabs, tries = vrfs
+    srv = P.Server(max_tables=len(tabs), streams=2, max_bursts=64, max_lookups=1 << 16, fanout=16, key_bits=64,
+                   learned=True)
+    for k, t in enumerate(tabs):
+        srv.set_table(k, t.prefixes, t.lengths, t.next_hops)
+    sizes, tids, addrs = _bursts(tabs, 200, 7)
+    outs, done = _serve(P, srv, tabs, sizes, tids, addrs)
+    st = srv.stats()
+    say(f"learned server stats {st}")
+    assert st["bursts"] == len(addrs) and st["admissions"] == len(tabs)
+    for i in range(len(addrs)):
+        assert np.array_equal(outs[i], tries[tids[i]].lookup(addrs[i])), i
+    srv.close()
+
+
 def _serve(P, srv, tabs, sizes, tids, addrs, poll_every=3):
     outs = [np.full(len(a), 0xFFFF, np.uint16) for a in addrs]
     done = {}
