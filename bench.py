@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-batches", action="store_true")
+    ap.add_argument("--skip-ablation", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     return ap.parse_args()
 
@@ -268,6 +269,40 @@ def cpu_leg(fib, addrs, got):
                        f"{dt:.1f} s"}, int((got != want).sum()))
 
 
+def ablation_leg(P, fib, d, n, out, got, steps=3):
+    """The design ladder on the headline FIB and batch (the GPU analogue of the
+    paper's Section 4 ablation): binary search over the sorted starts, then
+    the tree with one lane per lookup and no LDS, lane groups per lookup,
+    LDS-staged top levels, binary search by one lane in the LDS levels (the
+    headline shape), and the persistent kernel replayed from a graph.  Every
+    rung's output is checked against the headline result."""
+    import torch
+    rungs = []
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
+    o = torch.empty_like(out)
+
+    def timed(name, fn, note):
+        o.fill_(0)
+        ts = time_steps(fn, steps, 1)
+        torch.cuda.synchronize()
+        same = bool(np.array_equal(o.cpu().numpy().view(np.uint16), got))
+        rungs.append({"rung": name, "glps": round(n / (sum(ts) / len(ts)) / 1e9, 3), "identical": same, "shape": note})
+        log(f"ablation {name}: {rungs[-1]}")
+
+    timed("sorted-array binary search", lambda: P.planb_lookup_bsearch(h, d, n, o), "one lane per lookup")
+    for name, tu in (("tree, one lane per lookup, no LDS", (8, 0, 2, 512, 0)),
+                     ("tree, 4 lanes per lookup, no LDS", (2, 0, 2, 512, 0)),
+                     ("+ top 5 levels in LDS", (2, 5, 2, 512, 0)),
+                     ("+ one-lane binary search in the LDS levels (headline)", (2, 5, 2, 512, 1))):
+        P.planb_set_tuning(h, *tu)
+        timed(name, lambda: P.planb_lookup(h, d, n, o), dict(zip(("keys_per_lane", "lds_levels", "lookups_per_group",
+                                                                   "block_threads", "lds_search"), tu)))
+    g = P.Graph(h, 4)
+    timed("persistent kernel, graph replay, one batch", lambda: g.launch([(d, o, n)]), "headline shape")
+    g.close()
+    return rungs
+
+
 def cpu_btree_leg(fib, addrs, got):
     """CPU linearized B+-tree baseline (the same image the GPU descends, searched
     by the paper's batched branch-free CPU descent) on the host cores: the whole
@@ -366,6 +401,8 @@ def main():
         if not args.skip_learned:
             result["learned"] = learned_leg(P, fib, h, d, n, out, args, glps)
             log(f"learned: {result['learned']}")
+        if not args.skip_ablation:
+            result["ablation"] = ablation_leg(P, fib, d, n, out, got)
         if not args.skip_batches:
             result["batch_latency"] = batches_leg(P, h, d, n, out)
             result["p99_batch_latency_us"] = result["batch_latency"]["graph"]["p99_us"]

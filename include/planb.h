@@ -129,6 +129,15 @@ const char* planb_last_error(void);
  * after a call that returns NULL.  Reset by planb_build* calls. */
 int planb_last_status(void);
 
+/*
+ * The same answers as planb_lookup by plain binary search over the sorted
+ * interval starts, one lane per address, then a read of the next-hop array:
+ * the GPU analogue of the std::lower_bound baseline of the paper's ablation
+ * (Section 4), for comparing the tree against it.  Arguments and errors as
+ * planb_lookup.
+ */
+int planb_lookup_bsearch(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out, void* stream);
+
 /* m, the number of elementary intervals (Section 3: at most 2n + 1). */
 size_t planb_num_intervals(const planb_fib_t* fib);
 

@@ -301,6 +301,14 @@ int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
 
+int planb_lookup_bsearch(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out, void* stream)
+{
+    int rc = check_lookup_args(fib, addrs, n, out, 2);
+    if (rc != PLANB_OK || n == 0) return rc;
+    hipError_t e = launch_bsearch(fib->desc, addrs, n, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "binary-search launch");
+}
+
 size_t planb_num_intervals(const planb_fib_t* fib) { return fib ? fib->iv.starts.size() : 0; }
 
 long long planb_export_intervals(const planb_fib_t* fib, planb_addr_t* starts, uint16_t* next_hops, size_t cap)

@@ -364,6 +364,16 @@ struct Descent {
     }
 };
 
+// Key i of the dense interval order, read from the leaf level of the tree.
+template <int B, bool WIDE>
+__device__ inline typename KeyFmt<WIDE>::T leaf_key(const TreeDesc& t, uint64_t i)
+{
+    constexpr int kb = (int)sizeof(typename KeyFmt<WIDE>::T);
+    constexpr uint64_t LC = leaf_cap_for(B, kb), LS = leaf_slots_for(B, kb);
+    const auto* keys = static_cast<const typename KeyFmt<WIDE>::T*>(t.keys);
+    return keys[t.leaf_base + (i / LC) * LS + leaf_key_slot((uint32_t)(i % LC), kb)];
+}
+
 // Picks KernelOf<B, KPL, R, W, BS, BIN>::get() for runtime values among the
 // compiled-in variants: B in {8, 16, 32}, KPL in {1, 2, 4, 8, 16} with B/KPL
 // in [1, 32], R in {1, 2, 4}, W (wide keys), BS in {512, 1024}, and BIN

@@ -144,15 +144,6 @@ __device__ inline uint64_t predict_position(float y, uint64_t m)
     return p < m ? p : m - 1;
 }
 
-// Key i of the dense interval order, read from the leaf level of the tree.
-template <int B, bool WIDE>
-__device__ inline typename KeyFmt<WIDE>::T leaf_key(const TreeDesc& t, uint64_t i)
-{
-    constexpr int kb = (int)sizeof(typename KeyFmt<WIDE>::T);
-    constexpr uint64_t LC = leaf_cap_for(B, kb), LS = leaf_slots_for(B, kb);
-    const auto* keys = static_cast<const typename KeyFmt<WIDE>::T*>(t.keys);
-    return keys[t.leaf_base + (i / LC) * LS + leaf_key_slot((uint32_t)(i % LC), kb)];
-}
 
 // Plain one-lane descent (every key of each node), used for fallbacks.
 template <int B, bool WIDE>

@@ -42,6 +42,30 @@ lookup_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __r
         D::step(t, lds_keys, addrs, base, n, out, index_out);
 }
 
+// Binary search over the sorted interval starts, one lane per address: the
+// GPU analogue of the paper's std::lower_bound baseline (Section 4's
+// ablation), kept as the first rung of the design ladder.  Every probe is a
+// dependent read of one key (about log2(m) of them), then one read of the
+// next-hop array.  Keys are read in place from the leaves.
+template <int B, bool WIDE>
+__global__ void __launch_bounds__(256)
+bsearch_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out)
+{
+    using KF = KeyFmt<WIDE>;
+    const uint64_t m = t.m_minus_1 + 1;
+    uint64_t top = 1;
+    while (top * 2 <= m) top *= 2;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const u64x2 a = __builtin_nontemporal_load(addrs + i);
+        uint64_t c = 0;  // starts <= x (starts[0] = 0 <= x, so c >= 1)
+        for (uint64_t step = top; step >= 1; step >>= 1) {
+            const uint64_t probe = c + step - 1;
+            if (probe < m && KF::le(leaf_key<B, WIDE>(t, probe), a.x, a.y)) c += step;
+        }
+        __builtin_nontemporal_store(t.vals[c - 1], out + i);
+    }
+}
+
 namespace {
 
 template <int B, int KPL, int R, bool W, int BS, bool BIN>
@@ -118,6 +142,26 @@ int max_lds_bytes()
     DevProps p;
     if (dev_props(&p) != hipSuccess) return 64 * 1024;
     return p.max_lds;
+}
+
+hipError_t launch_bsearch(const TreeDesc& t, const void* addrs, uint64_t n, uint16_t* out, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    using Fn = void (*)(TreeDesc, const u64x2*, uint64_t, uint16_t*);
+    const bool wide = t.key_bytes == 16;
+    Fn fn = t.fanout == 8 ? (wide ? bsearch_kernel<8, true> : bsearch_kernel<8, false>)
+          : t.fanout == 16 ? (wide ? bsearch_kernel<16, true> : bsearch_kernel<16, false>)
+          : t.fanout == 32 ? (wide ? bsearch_kernel<32, true> : bsearch_kernel<32, false>) : nullptr;
+    if (!fn) return hipErrorInvalidValue;
+    DevProps p;
+    hipError_t e = dev_props(&p);
+    if (e != hipSuccess) return e;
+    int nb = 1;
+    if ((e = occupancy(reinterpret_cast<const void*>(fn), 256, 0, &nb)) != hipSuccess) return e;
+    const uint64_t want = (n + 255) / 256, cap = (uint64_t)p.cus * nb;
+    hipLaunchKernelGGL(fn, dim3((unsigned)(want < cap ? want : cap)), dim3(256), 0, stream, t,
+                       static_cast<const u64x2*>(addrs), n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,

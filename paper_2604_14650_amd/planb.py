@@ -115,6 +115,7 @@ _sig("planb_build", _vp, _vp, _vp, _vp, _sz)
 _sig("planb_build_ex", _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(planb_params_t))
 _sig("planb_lookup", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_lookup_index", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
+_sig("planb_lookup_bsearch", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_free", None, _vp)
 _sig("planb_last_error", ctypes.c_char_p)
 _sig("planb_last_status", ctypes.c_int)
@@ -270,6 +271,15 @@ def planb_lookup_index(fib: Fib, addrs, n: int | None = None, out=None, stream=N
         n = addrs.shape[0]
     _check(_lib.planb_lookup_index(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"),
                                    _stream_handle(stream)))
+    return out
+
+
+def planb_lookup_bsearch(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
+    """Binary search over the sorted interval starts (ablation baseline); same results as planb_lookup."""
+    if n is None:
+        n = addrs.shape[0]
+    _check(_lib.planb_lookup_bsearch(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"),
+                                     _stream_handle(stream)))
     return out
 
 

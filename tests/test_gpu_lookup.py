@@ -238,3 +238,38 @@ def test_brute_force_agrees_on_a_sample(P, tiny):
     fib, addrs, want = tiny
     got, _ = gpu_lookup(P, fib, addrs[:3000])
     assert np.array_equal(got, lpm_bruteforce(fib.prefixes, fib.lengths, fib.next_hops, addrs[:3000]))
+
+
+@pytest.mark.parametrize("fanout", [8, 16, 32])
+@pytest.mark.parametrize("name", sorted(_edge_fibs()))
+def test_bsearch_baseline_edge_cases(P, fanout, name):
+    """The sorted-array binary search baseline gives the oracle's answers."""
+    rules = _edge_fibs()[name]
+    rng = np.random.default_rng(9)
+    p = S.from_ints([r[0] for r in rules]) if rules else np.zeros((0, 2), np.uint64)
+    L = np.array([r[1] for r in rules], np.uint8)
+    nh = np.array([r[2] for r in rules], np.uint16)
+    q = _edge_queries(rules, rng)
+    want = lpm_bruteforce(p, L, nh, q)
+    for key_bits in (0, 128):
+        say(f"bsearch edge {name} fanout={fanout} key_bits={key_bits}")
+        h = P.planb_build(p, L, nh, fanout=fanout, key_bits=key_bits)
+        out = out_u16(q.shape[0])
+        P.planb_lookup_bsearch(h, to_dev(q), q.shape[0], out)
+        assert np.array_equal(host_u16(out, q.shape[0]), want)
+
+
+@pytest.mark.parametrize("key_bits", [0, 128])
+def test_bsearch_baseline_tiny_and_backbone(P, tiny, key_bits):
+    fib, addrs, want = tiny
+    for fanout in (8, 16, 32):
+        h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
+        out = out_u16(addrs.shape[0])
+        P.planb_lookup_bsearch(h, to_dev(addrs), addrs.shape[0], out)
+        assert np.array_equal(host_u16(out, addrs.shape[0]), want), fanout
+    bb = fib_of("backbone", 22)
+    a = S.backbone_traffic(bb, 1 << 21, seed=2023)
+    h = P.planb_build(bb.prefixes, bb.lengths, bb.next_hops, fanout=8, key_bits=key_bits)
+    out = out_u16(a.shape[0])
+    P.planb_lookup_bsearch(h, to_dev(a), a.shape[0], out)
+    assert np.array_equal(host_u16(out, a.shape[0]), oracle_trie("backbone", 22).lookup(a))
