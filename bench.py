@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-batches", action="store_true")
     ap.add_argument("--skip-ablation", action="store_true")
+    ap.add_argument("--skip-rebuild", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     return ap.parse_args()
 
@@ -303,6 +304,42 @@ def ablation_leg(P, fib, d, n, out, got, steps=3):
     return rungs
 
 
+def rebuild_leg(P, reps=3):
+    """Full rebuild of a FIB from its rules (Section 3.6 rebuilds the whole
+    structure on every update; the paper reports 850 ms for 1M prefixes on
+    its CPU): the host build (rules in host memory, tree uploaded) and the
+    device build (rules already in device memory), median of `reps`."""
+    import torch
+    import planb_synth as S
+    res = {}
+    for name, spec, seed in (("backbone_200k", S.BACKBONE, 22), ("large_1m", S.LARGE, 33)):
+        fib = S.make_fib(spec, seed)
+        dp = torch.from_numpy(np.ascontiguousarray(fib.prefixes).view(np.int64)).cuda()
+        dL = torch.from_numpy(np.ascontiguousarray(fib.lengths)).cuda()
+        dn = torch.from_numpy(np.ascontiguousarray(fib.next_hops).view(np.int16)).cuda()
+        th, td = [], []
+        for r in range(reps + 1):  # the first of each is a warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hb = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=16)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            db = P.planb_build_device(dp, dL, dn, fanout=16)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if r:
+                th.append(t1 - t0)
+                td.append(t2 - t1)
+            same = bool(np.array_equal(P.planb_export_image(hb), P.planb_export_image(db)))
+            hb.close()
+            db.close()
+        res[name] = {"prefixes": len(fib), "host_ms": round(1e3 * float(np.median(th)), 2),
+                     "device_ms": round(1e3 * float(np.median(td)), 2), "identical_image": same}
+        log(f"rebuild {name}: {res[name]}")
+    res["paper_cpu_ms_1m"] = 850
+    return res
+
+
 def cpu_btree_leg(fib, addrs, got):
     """CPU linearized B+-tree baseline (the same image the GPU descends, searched
     by the paper's batched branch-free CPU descent) on the host cores: the whole
@@ -403,6 +440,8 @@ def main():
             log(f"learned: {result['learned']}")
         if not args.skip_ablation:
             result["ablation"] = ablation_leg(P, fib, d, n, out, got)
+        if not args.skip_rebuild:
+            result["rebuild"] = rebuild_leg(P)
         if not args.skip_batches:
             result["batch_latency"] = batches_leg(P, h, d, n, out)
             result["p99_batch_latency_us"] = result["batch_latency"]["graph"]["p99_us"]

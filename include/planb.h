@@ -93,6 +93,19 @@ typedef struct planb_params {
  */
 planb_fib_t* planb_build(const planb_addr_t* prefixes, const uint8_t* lengths,
                          const uint16_t* next_hops, size_t n);
+
+/*
+ * The same build run on the device (Section 3.6 rebuilds the structure from
+ * the rule set on every update; this keeps that rebuild next to the lookups).
+ * prefixes (16-byte aligned), lengths and next_hops are DEVICE arrays of n
+ * rules; params as for planb_build_ex; the work runs on `stream` and the call
+ * returns when the FIB is ready (it synchronises the stream twice, to size the
+ * tree and to copy the intervals back for planb_export_intervals and
+ * training).  The result -- intervals, tree image, next hops, errors -- is the
+ * one planb_build_ex gives for the same rules.  At most 2^30 - 1 rules.
+ */
+planb_fib_t* planb_build_device(const planb_addr_t* prefixes, const uint8_t* lengths, const uint16_t* next_hops,
+                                size_t n, const planb_params_t* params, void* stream);
 planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths,
                             const uint16_t* next_hops, size_t n, const planb_params_t* params);
 
@@ -145,6 +158,12 @@ size_t planb_num_intervals(const planb_fib_t* fib);
  * how many were written (or a negative status).  Either array may be NULL. */
 long long planb_export_intervals(const planb_fib_t* fib, planb_addr_t* starts,
                                  uint16_t* next_hops, size_t cap);
+
+/* Copies the FIB's device slot array (the image planb_build_image describes)
+ * to host memory and returns its size in bytes, or only returns the size when
+ * image is NULL or cap_bytes is too small; negative status on error.
+ * Synchronous. */
+long long planb_export_image(const planb_fib_t* fib, void* image, size_t cap_bytes);
 
 #define PLANB_MAX_LEVELS 16
 

@@ -140,6 +140,21 @@ void build_image(const Intervals& iv, const Layout& lay, int key_bytes, std::vec
     }
 }
 
+int finish_fib(planb_fib_t* f, const planb_params_t& p)
+{
+    planb_tuning_t tu{};
+    tu.keys_per_lane = p.keys_per_lane ? p.keys_per_lane : default_kpl(p.fanout);
+    tu.lds_levels = p.lds_levels > 0 ? p.lds_levels : -1;
+    tu.lookups_per_group = 2;
+    tu.block_threads = 512;
+    int32_t lds_ok = 0;
+    int rc = validate_tuning(f, tu, &f->tune, &lds_ok);
+    if (rc != PLANB_OK) return rc;
+    f->lds_levels = lds_ok;
+    refresh_desc(f);
+    return PLANB_OK;
+}
+
 // Key width for a set of interval starts: 8 bytes when asked (and exact) or
 // when every start has a zero low word and nothing was asked; else 16.
 int choose_key_bytes(const Intervals& iv, uint32_t key_bits, int* key_bytes)
@@ -242,18 +257,10 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
         planb_free(f);
         return nullptr;
     }
-    planb_tuning_t tu{};
-    tu.keys_per_lane = p.keys_per_lane ? p.keys_per_lane : default_kpl(p.fanout);
-    tu.lds_levels = p.lds_levels > 0 ? p.lds_levels : -1;
-    tu.lookups_per_group = 2;
-    tu.block_threads = 512;
-    int32_t lds_ok = 0;
-    if ((rc = validate_tuning(f, tu, &f->tune, &lds_ok)) != PLANB_OK) {
+    if (finish_fib(f, p) != PLANB_OK) {
         planb_free(f);
         return nullptr;
     }
-    f->lds_levels = lds_ok;
-    refresh_desc(f);
     return f;
 }
 
@@ -320,6 +327,16 @@ long long planb_export_intervals(const planb_fib_t* fib, planb_addr_t* starts, u
     return (long long)m;
 }
 
+
+long long planb_export_image(const planb_fib_t* fib, void* image, size_t cap_bytes)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (!image || cap_bytes < fib->key_bytes) return (long long)fib->key_bytes;
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    hipError_t e = hipMemcpy(image, fib->d_keys, fib->key_bytes, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? (long long)fib->key_bytes : fail_hip(e, "copying the tree image");
+}
 
 long long planb_build_intervals(const planb_addr_t* prefixes, const uint8_t* lengths, const uint16_t* next_hops,
                                 size_t n, uint32_t flags, planb_addr_t* starts, uint16_t* next_hops_out, size_t cap)

@@ -37,5 +37,9 @@ int fail_hip(hipError_t e, const char* what);
 int check_current_device(const planb_fib_t* fib);
 void refresh_desc(planb_fib_t* f);
 void release_learned(planb_fib_t* f);  // frees the learned model, if any
+// Default launch shape (params' keys per lane / LDS levels, if set) and descriptor.
+int finish_fib(planb_fib_t* f, const planb_params_t& p);
+// Layout of a FIB's tree over m intervals with key_bytes-wide slots.
+int plan_fib_layout(uint64_t m, uint32_t fanout, int key_bytes, Layout* lay, std::string* err);
 
 }  // namespace planb

@@ -113,6 +113,7 @@ def _sig(name, res, *args):
 
 _sig("planb_build", _vp, _vp, _vp, _vp, _sz)
 _sig("planb_build_ex", _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(planb_params_t))
+_sig("planb_build_device", _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(planb_params_t), _vp)
 _sig("planb_lookup", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_lookup_index", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_lookup_bsearch", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
@@ -127,6 +128,7 @@ _sig("planb_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(planb_tuning_t))
 _sig("planb_build_intervals", ctypes.c_longlong, _vp, _vp, _vp, _sz, ctypes.c_uint32, _vp, _vp, _sz)
 _sig("planb_build_keys", ctypes.c_longlong, _vp, _sz, ctypes.c_uint32, _vp, _sz, ctypes.POINTER(planb_info_t))
 _sig("planb_cpu_lookup", ctypes.c_int, _vp, ctypes.POINTER(planb_info_t), _vp, _sz, _vp, ctypes.c_int)
+_sig("planb_export_image", ctypes.c_longlong, _vp, _vp, _sz)
 _sig("planb_build_image", ctypes.c_longlong, _vp, _vp, _sz, ctypes.c_uint32, ctypes.c_uint32, _vp, _sz,
      ctypes.POINTER(planb_info_t))
 _sig("planb_lookup_batches", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
@@ -232,6 +234,22 @@ def planb_build(prefixes, lengths, next_hops, fanout: int = 16, keys_per_lane: i
     n = L.shape[0]
     ptr = _lib.planb_build_ex(p.ctypes.data if n else None, L.ctypes.data if n else None,
                               nh.ctypes.data if n else None, n, ctypes.byref(params))
+    if not ptr:
+        raise PlanbError(planb_last_status(), planb_last_error())
+    return Fib(ptr)
+
+
+def planb_build_device(prefixes, lengths, next_hops, n: int | None = None, fanout: int = 16, keys_per_lane: int = 0,
+                       lds_levels: int = 0, flags: int = 0, key_bits: int = 0, stream=None) -> Fib:
+    """Device-side build: prefixes (n, 2) int64, lengths (n,) uint8 and
+    next_hops (n,) int16/uint16 are device tensors (or device pointers with n)."""
+    if n is None:
+        n = lengths.shape[0]
+    params = planb_params_t(fanout, keys_per_lane, lds_levels, flags, key_bits)
+    ptr = _lib.planb_build_device(_dev_ptr(prefixes, "prefixes") if n else None,
+                                  _dev_ptr(lengths, "lengths") if n else None,
+                                  _dev_ptr(next_hops, "next_hops") if n else None, n, ctypes.byref(params),
+                                  _stream_handle(stream))
     if not ptr:
         raise PlanbError(planb_last_status(), planb_last_error())
     return Fib(ptr)
@@ -352,6 +370,14 @@ def planb_build_keys(starts, fanout: int = 16):
     keys = np.empty((need, 2), dtype=np.uint64)
     _check(_lib.planb_build_keys(s.ctypes.data, s.shape[0], fanout, keys.ctypes.data, need, None))
     return keys, _info_dict(info)
+
+
+def planb_export_image(fib: Fib) -> np.ndarray:
+    """The FIB's device slot array, copied to host memory (uint8)."""
+    need = _check(_lib.planb_export_image(fib, None, 0))
+    img = np.empty(need, dtype=np.uint8)
+    _check(_lib.planb_export_image(fib, img.ctypes.data, need))
+    return img
 
 
 def planb_build_image(starts, next_hops, fanout: int = 16, key_bits: int = 0):
