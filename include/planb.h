@@ -61,12 +61,16 @@ typedef struct planb_params {
     int32_t lds_levels;     /* initial lookup tuning, see planb_tuning_t (0 -> default) */
     uint32_t flags;         /* PLANB_FLAG_* */
     uint32_t key_bits;      /* stored key width: 0 = automatic, 128 = always the full
-                               16-byte key, 64 = only the high 64 bits (8-byte slots).
-                               64 is exact, and chosen automatically, exactly when every
-                               interval start has a zero low word -- e.g. when no
-                               prefix is longer than /64 (the paper's own key width,
-                               Section 3 "Parameter Tuning"); asking for 64 otherwise
-                               fails with PLANB_EINVAL. */
+                               16-byte key, 64 = only the high 64 bits (8-byte slots),
+                               32 = only the top 32 bits (4-byte slots).
+                               64 is exact exactly when every interval start has a
+                               zero low word -- e.g. when no prefix is longer than /64
+                               (the paper's own key width, Section 3 "Parameter
+                               Tuning"); 32 exactly when every start's low 96 bits are
+                               zero -- e.g. IPv4 rules placed in the top 32 bits
+                               (planb_lookup_v4).  Automatic picks the narrowest exact
+                               width; asking for an inexact one fails with
+                               PLANB_EINVAL. */
 } planb_params_t;
 
 /* Merge neighbouring elementary intervals that resolve to the same next hop.
@@ -143,6 +147,15 @@ const char* planb_last_error(void);
 int planb_last_status(void);
 
 /*
+ * IPv4: planb_lookup over n 4-byte addresses (device, 4-byte aligned), each
+ * standing for the 128-bit address with those 32 bits on top, for a FIB built
+ * from rules of at most /32 placed the same way (so its keys are 32-bit;
+ * PLANB_EINVAL otherwise).  The same kernel with 4-byte key slots and 4-byte
+ * address loads: 6 bytes of HBM traffic per lookup instead of 18.
+ */
+int planb_lookup_v4(const planb_fib_t* fib, const uint32_t* addrs, size_t n, uint16_t* out, void* stream);
+
+/*
  * The same answers as planb_lookup by plain binary search over the sorted
  * interval starts, one lane per address, then a read of the next-hop array:
  * the GPU analogue of the std::lower_bound baseline of the paper's ablation
@@ -173,8 +186,11 @@ long long planb_export_image(const planb_fib_t* fib, void* image, size_t cap_byt
  * the same slot array from slot leaf_base on, each leaf_slots slots long and
  * holding leaf_keys interval starts (interval i in leaf i / leaf_keys).  In a
  * built FIB a leaf also carries the next hops of its intervals: leaf_keys
- * uint16 values right after its keys (byte leaf_keys * key_bits / 8 of the
- * leaf), so that a lookup reads its answer from the line it already loaded.
+ * uint16 values beside its keys, so that a lookup reads its answer from the
+ * line it already loaded: with 128-bit slots right after the keys (byte
+ * leaf_keys * 16 of the leaf); with 64-bit slots in 32-byte blocks of three
+ * keys and their three hops; with 32-bit slots in 32-byte blocks of five keys
+ * and their five hops.
  * A FIB's leaf is max(b slots, 128 bytes) long and leaf_keys is the number
  * of (key, next hop) pairs that fit; in the paper's layout (planb_layout)
  * leaves are ordinary nodes: leaf_keys = b - 1, leaf_slots = slots.
@@ -184,7 +200,7 @@ typedef struct planb_info {
     uint32_t fanout;                    /* b */
     uint32_t slots;                     /* key slots per internal node (b: k keys + 1 sentinel) */
     uint32_t depth;                     /* D: levels including the leaf level */
-    uint32_t key_bits;                  /* 128 or 64, see planb_params_t */
+    uint32_t key_bits;                  /* 128, 64 or 32, see planb_params_t */
     uint64_t level_nodes[PLANB_MAX_LEVELS];      /* allocated nodes per level (leaves last) */
     uint64_t level_offset[PLANB_MAX_LEVELS + 1]; /* first node of each level (internal levels) */
     uint64_t key_bytes;                 /* device bytes of the slot array (keys + in-leaf next hops) */
@@ -414,7 +430,7 @@ typedef struct planb_server_cfg {
     uint32_t max_bursts;    /* bursts per launch (0 -> 1024) */
     uint32_t max_lookups;   /* addresses per launch (0 -> 2^20) */
     uint32_t fanout;        /* fanout of every table (0 -> 16) */
-    uint32_t key_bits;      /* 64 or 128 for every table (0 -> 128) */
+    uint32_t key_bits;      /* 32, 64 or 128 for every table (0 -> 128) */
     uint64_t memory_budget; /* device bytes for resident trees (0 = unlimited) */
     uint32_t learned;       /* 1: train a learned model for every table when it is admitted and
                                serve bursts with planb_lookup_multi_learned (0: planb_lookup_multi) */
@@ -496,12 +512,13 @@ long long planb_build_keys(const planb_addr_t* starts, size_t m, uint32_t fanout
 /*
  * planb_build_image -- the exact device slot array planb_build uploads for m
  * strictly increasing interval starts (starts[0] == 0) and their next hops:
- * the key array above in key_bits-wide slots (64: the high word of each key;
- * 0 picks 64 when every start's low word is zero, as planb_build does) with
- * every leaf carrying its next hops (see planb_info_t).  With 64-bit slots a
- * leaf is a run of 32-byte blocks of three keys and their three uint16 next
- * hops; with 128-bit slots the keys come first, then the next hops.  Slots
- * past the last interval hold the all-ones sentinel and next hop 0xFFFF.
+ * the key array above in key_bits-wide slots (64: the high word of each key,
+ * 32: its top 32 bits; 0 picks the narrowest exact width, as planb_build
+ * does) with every leaf carrying its next hops (see planb_info_t).  With
+ * 64-bit slots a leaf is a run of 32-byte blocks of three keys and their
+ * three uint16 next hops, with 32-bit slots of five keys and five hops; with
+ * 128-bit slots the keys come first, then the next hops.  Slots past the last
+ * interval hold the all-ones sentinel and next hop 0xFFFF.
  * image: host, cap_bytes bytes; info (may be NULL) receives the shape.
  * Returns the image size in bytes (may exceed cap_bytes, then nothing is
  * written) or a negative status.

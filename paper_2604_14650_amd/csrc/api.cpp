@@ -116,14 +116,17 @@ int plan_fib_layout(uint64_t m, uint32_t fanout, int key_bytes, Layout* lay, std
 }
 
 // The device slot array of a FIB: the keys of fill_keys in key_bytes-wide
-// slots (8: the hi word of every key), and each leaf's next hops written
+// slots (8: the hi word of every key, 4: its top 32 bits), and each leaf's next hops written
 // where the leaf format puts them (kNoRoute past the last interval).
 void build_image(const Intervals& iv, const Layout& lay, int key_bytes, std::vector<uint8_t>* image)
 {
     std::vector<U128> keys;
     fill_keys(iv, lay, key_bytes, &keys);
     image->assign(keys.size() * key_bytes, 0);
-    if (key_bytes == 8) {
+    if (key_bytes == 4) {
+        uint32_t* d = reinterpret_cast<uint32_t*>(image->data());
+        for (size_t i = 0; i < keys.size(); ++i) d[i] = (uint32_t)(keys[i].hi >> 32);
+    } else if (key_bytes == 8) {
         uint64_t* d = reinterpret_cast<uint64_t*>(image->data());
         for (size_t i = 0; i < keys.size(); ++i) d[i] = keys[i].hi;
     } else {
@@ -155,17 +158,29 @@ int finish_fib(planb_fib_t* f, const planb_params_t& p)
     return PLANB_OK;
 }
 
-// Key width for a set of interval starts: 8 bytes when asked (and exact) or
-// when every start has a zero low word and nothing was asked; else 16.
+// Key width for a set of interval starts: the width asked for when it is
+// exact, else (nothing asked) the narrowest exact one: 4 bytes when every
+// start's low 96 bits are zero, 8 when every low word is zero, else 16.
+int choose_key_bytes(bool lo_zero, bool low96_zero, uint32_t key_bits, int* key_bytes)
+{
+    if (key_bits != 0 && key_bits != 32 && key_bits != 64 && key_bits != 128)
+        return fail(PLANB_EINVAL, "key_bits must be 0, 32, 64 or 128");
+    if (key_bits == 64 && !lo_zero)
+        return fail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
+    if (key_bits == 32 && !low96_zero)
+        return fail(PLANB_EINVAL, "32-bit keys are exact only when every interval start has zero low 96 bits");
+    *key_bytes = key_bits == 32 ? 4 : key_bits == 64 ? 8 : key_bits == 128 ? 16 : low96_zero ? 4 : lo_zero ? 8 : 16;
+    return PLANB_OK;
+}
+
 int choose_key_bytes(const Intervals& iv, uint32_t key_bits, int* key_bytes)
 {
-    if (key_bits != 0 && key_bits != 64 && key_bits != 128) return fail(PLANB_EINVAL, "key_bits must be 0, 64 or 128");
-    bool all_lo_zero = true;
-    for (const U128& k : iv.starts) all_lo_zero &= (k.lo == 0);
-    if (key_bits == 64 && !all_lo_zero)
-        return fail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
-    *key_bytes = key_bits == 64 || (key_bits == 0 && all_lo_zero) ? 8 : 16;
-    return PLANB_OK;
+    bool lo_zero = true, low96_zero = true;
+    for (const U128& k : iv.starts) {
+        lo_zero &= (k.lo == 0);
+        low96_zero &= (k.lo == 0 && (k.hi & 0xFFFFFFFFull) == 0);
+    }
+    return choose_key_bytes(lo_zero, low96_zero, key_bits, key_bytes);
 }
 
 }  // namespace planb
@@ -298,6 +313,23 @@ int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, ui
     if (rc != PLANB_OK || n == 0) return rc;
     hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, false, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
+}
+
+int planb_lookup_v4(const planb_fib_t* fib, const uint32_t* addrs, size_t n, uint16_t* out, void* stream)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (fib->key_bytes_per_slot != 4)
+        return fail(PLANB_EINVAL, "the FIB's keys are not 32-bit: build it from rules of at most /32 placed in the top "
+                                  "32 bits (key_bits 0 or 32)");
+    if (n == 0) return PLANB_OK;
+    if (n >= (1ull << 40)) return fail(PLANB_ERANGE, "batch too large (n must be < 2^40)");
+    if (!addrs || !out) return fail(PLANB_EINVAL, "NULL device pointer");
+    if (reinterpret_cast<uintptr_t>(addrs) % 4 || reinterpret_cast<uintptr_t>(out) % 2)
+        return fail(PLANB_EINVAL, "misaligned pointer");
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
+    hipError_t e = launch_lookup_v4(fib->desc, fib->tune, addrs, n, out, false, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PLANB_OK : fail_hip(e, "IPv4 lookup launch");
 }
 
 int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint32_t* out, void* stream)

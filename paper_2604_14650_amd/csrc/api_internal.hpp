@@ -39,6 +39,10 @@ void refresh_desc(planb_fib_t* f);
 void release_learned(planb_fib_t* f);  // frees the learned model, if any
 // Default launch shape (params' keys per lane / LDS levels, if set) and descriptor.
 int finish_fib(planb_fib_t* f, const planb_params_t& p);
+// Key slot width (4, 8 or 16) for starts whose low words are all zero
+// (lo_zero) and whose low 96 bits are all zero (low96_zero); key_bits as in
+// planb_params_t.  Sets the error on failure.
+int choose_key_bytes(bool lo_zero, bool low96_zero, uint32_t key_bits, int* key_bytes);
 // Layout of a FIB's tree over m intervals with key_bytes-wide slots.
 int plan_fib_layout(uint64_t m, uint32_t fanout, int key_bytes, Layout* lay, std::string* err);
 

@@ -25,12 +25,12 @@ struct BatchRec {  // same layout as planb_batch_t
 };
 static_assert(sizeof(BatchRec) == sizeof(planb_batch_t), "planb_batch_t layout");
 
-template <int B, int KPL, int R, bool WIDE, int BS, bool BIN>
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
 __global__ void __launch_bounds__(BS)
 batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t* __restrict__ count,
                uint32_t max_batches, int index_out)
 {
-    using D = Descent<B, KPL, R, WIDE, BIN>;
+    using D = Descent<B, KPL, R, KB, BIN>;
     extern __shared__ uint4 lds_raw[];
     uint32_t* tile_off = reinterpret_cast<uint32_t*>(lds_raw + D::lds_bytes(t) / 16);  // max_batches + 1
     uint32_t* part = tile_off + max_batches + 1;                                       // BS
@@ -74,10 +74,10 @@ batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t*
 
 namespace {
 
-template <int B, int KPL, int R, bool W, int BS, bool BIN>
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
 struct BatchesKernel {
     using Fn = void (*)(TreeDesc, const BatchRec*, const uint32_t*, uint32_t, int);
-    static Fn get() { return batches_kernel<B, KPL, R, W, BS, BIN>; }
+    static Fn get() { return batches_kernel<B, KPL, R, KB, BS, BIN>; }
 };
 
 struct BatchesLaunch {
@@ -90,7 +90,7 @@ int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
 {
     const TreeDesc& t = fib->desc;
     const LookupTuning& tu = fib->tune;
-    L->fn = VariantTable<BatchesKernel>::pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block, tu.bin);
+    L->fn = VariantTable<BatchesKernel>::pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
     if (!L->fn) return fail(PLANB_EINVAL, "no batches kernel for this tuning");
     DevProps p;
     hipError_t e = dev_props(&p);

@@ -45,6 +45,7 @@ struct BuildState {  // device-side results, read back once
     uint32_t dup;           // some (prefix, length) repeated after masking
     uint32_t dummies;       // rules whose range ends at 2^128
     uint32_t any_lo;        // some interval start has a nonzero low word
+    uint32_t any_mid;       // some interval start has nonzero bits 64..95
     uint32_t unbalanced;    // a negative stack depth (cannot happen for valid input)
     uint32_t zero_missing;  // no event at address 0
     uint64_t groups;        // distinct event addresses
@@ -230,12 +231,24 @@ __global__ void finish_kernel(const u64x2* __restrict__ starts, uint32_t m, Buil
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) st->m = m;
     if (i < m && starts[i].y != 0) st->any_lo = 1;
+    if (i < m && (starts[i].x & 0xFFFFFFFFull) != 0) st->any_mid = 1;
 }
 
 __global__ void count_kernel(const uint32_t* __restrict__ keep, const uint32_t* __restrict__ kpos, uint32_t m,
                              BuildState* st)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->m = m ? (uint64_t)kpos[m - 1] + keep[m - 1] : 0;
+}
+
+// A key in a slot of kb bytes: {hi, lo}, hi, or hi's top 32 bits.
+__device__ inline void write_key(uint8_t* slot, u64x2 v, int kb)
+{
+    if (kb == 4) {
+        *reinterpret_cast<uint32_t*>(slot) = (uint32_t)(v.x >> 32);
+    } else {
+        reinterpret_cast<uint64_t*>(slot)[0] = v.x;
+        if (kb == 16) reinterpret_cast<uint64_t*>(slot)[1] = v.y;
+    }
 }
 
 // Leaf keys and next hops.
@@ -246,10 +259,7 @@ __global__ void leaves_kernel(const u64x2* __restrict__ starts, const uint16_t* 
     if (i >= m) return;
     const uint32_t q = i / lc, s = i % lc;
     uint8_t* leaf = image + (leaf_base + (uint64_t)q * ls) * kb;
-    const u64x2 v = starts[i];
-    uint64_t* slot = reinterpret_cast<uint64_t*>(leaf + (uint64_t)leaf_key_slot(s, kb) * kb);
-    slot[0] = v.x;
-    if (kb == 16) slot[1] = v.y;
+    write_key(leaf + (uint64_t)leaf_key_slot(s, kb) * kb, starts[i], kb);
     *reinterpret_cast<uint16_t*>(leaf + leaf_hop_byte(s, kb, (int)lc)) = nh[i];
 }
 
@@ -263,10 +273,7 @@ __global__ void separators_kernel(const u64x2* __restrict__ starts, uint64_t nod
     const uint64_t q = t / (b - 1), j = t % (b - 1) + 1;
     const uint64_t leaf = (q * b + j) * span;
     if (leaf >= leaves) return;
-    const u64x2 v = starts[leaf * lc];
-    uint64_t* slot = reinterpret_cast<uint64_t*>(image + ((node_off + q) * b + j - 1) * kb);
-    slot[0] = v.x;
-    if (kb == 16) slot[1] = v.y;
+    write_key(image + ((node_off + q) * b + j - 1) * kb, starts[leaf * lc], kb);
 }
 
 unsigned blocks_for(uint64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -395,8 +402,8 @@ extern "C" planb_fib_t* planb_build_device(const planb_addr_t* prefixes, const u
         fail(PLANB_EINVAL, "fanout must be 8, 16 or 32");
         return nullptr;
     }
-    if (p.key_bits != 0 && p.key_bits != 64 && p.key_bits != 128) {
-        fail(PLANB_EINVAL, "key_bits must be 0, 64 or 128");
+    if (p.key_bits != 0 && p.key_bits != 32 && p.key_bits != 64 && p.key_bits != 128) {
+        fail(PLANB_EINVAL, "key_bits must be 0, 32, 64 or 128");
         return nullptr;
     }
     if (n > 0 && (!prefixes || !lengths || !next_hops)) {
@@ -487,13 +494,15 @@ extern "C" planb_fib_t* planb_build_device(const planb_addr_t* prefixes, const u
         m = h.m;
     }
     hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(m)), dim3(kThreads), 0, st, d_starts, (uint32_t)m, d_st);
-    uint32_t any_lo = 0;
-    if ((e = hipMemcpyAsync(&any_lo, &d_st->any_lo, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+    uint32_t flags[2] = {0, 0};  // any_lo, any_mid
+    if ((e = hipMemcpyAsync(flags, &d_st->any_lo, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return bail(PLANB_EDEVICE, std::string("device build: ") + hipGetErrorString(e));
-    if (p.key_bits == 64 && any_lo)
-        return bail(PLANB_EINVAL, "64-bit keys are exact only when every interval start has a zero low word");
-    const int kb = p.key_bits == 64 || (p.key_bits == 0 && !any_lo) ? 8 : 16;
+    int kb = 16;
+    if (choose_key_bytes(flags[0] == 0, flags[0] == 0 && flags[1] == 0, p.key_bits, &kb) != PLANB_OK) {
+        planb_free(f);
+        return nullptr;
+    }
     f->key_bytes_per_slot = (uint32_t)kb;
     std::string err;
     int rc = plan_fib_layout(m, p.fanout, kb, &f->lay, &err);

@@ -28,12 +28,18 @@ struct Tree {
     uint64_t last[PLANB_MAX_LEVELS];  // last node of each level
 };
 
-// keys <= x among the first S slots at p (KB: 8 = high words only, 16 = {hi, lo})
+// keys <= x among the first S slots at p (KB: 4 = top 32 bits, 8 = high
+// words only, 16 = {hi, lo})
 template <int KB, int S>
 inline uint32_t count_keys(const uint8_t* p, uint64_t xh, uint64_t xl)
 {
     uint32_t c = 0;
-    if constexpr (KB == 8) {
+    if constexpr (KB == 4) {
+        uint32_t k[S];
+        std::memcpy(k, p, sizeof(k));
+        const uint32_t x = (uint32_t)(xh >> 32);
+        for (int s = 0; s < S; ++s) c += k[s] <= x;
+    } else if constexpr (KB == 8) {
         uint64_t k[S];
         std::memcpy(k, p, sizeof(k));
         for (int s = 0; s < S; ++s) c += k[s] <= xh;
@@ -71,7 +77,13 @@ void lookup_range(const Tree& t, const planb_addr_t* a, uint16_t* out, size_t lo
         for (int i = 0; i < G; ++i) {
             const uint8_t* leaf = t.img + (t.leaf_base + q[i] * LS) * KB;
             uint32_t c;
-            if constexpr (KB == 8) {  // blocks of three keys and their next hops
+            if constexpr (KB == 4) {  // blocks of five keys and their next hops
+                uint32_t k[LS];
+                std::memcpy(k, leaf, sizeof(k));
+                const uint32_t x = (uint32_t)(xh[i] >> 32);
+                c = 0;
+                for (int s = 0; s < LS; ++s) c += (s % 8 < 5) & (k[s] <= x);
+            } else if constexpr (KB == 8) {  // blocks of three keys and their next hops
                 uint64_t k[LS];
                 std::memcpy(k, leaf, sizeof(k));
                 c = 0;
@@ -101,14 +113,15 @@ extern "C" int planb_cpu_lookup(const void* image, const planb_info_t* info, con
                                 uint16_t* out, int threads)
 {
     if (!image || !info || (n && (!addrs || !out))) return PLANB_EINVAL;
-    if ((info->key_bits != 64 && info->key_bits != 128) || info->depth == 0 || info->depth > PLANB_MAX_LEVELS ||
+    if ((info->key_bits != 32 && info->key_bits != 64 && info->key_bits != 128) || info->depth == 0 ||
+        info->depth > PLANB_MAX_LEVELS ||
         (info->fanout != 8 && info->fanout != 16 && info->fanout != 32) || info->leaf_keys == 0 ||
         info->intervals == 0)
         return PLANB_EINVAL;
     const int kb = (int)info->key_bits / 8, b = (int)info->fanout;
     if (info->leaf_keys != (uint32_t)planb::leaf_cap_for(b, kb) || info->leaf_slots != (uint32_t)planb::leaf_slots_for(b, kb))
         return PLANB_EINVAL;
-    const RangeFn fn = kb == 8 ? pick_b<8>(info->fanout) : pick_b<16>(info->fanout);
+    const RangeFn fn = kb == 4 ? pick_b<4>(info->fanout) : kb == 8 ? pick_b<8>(info->fanout) : pick_b<16>(info->fanout);
     Tree t{};
     t.img = static_cast<const uint8_t*>(image);
     t.depth = info->depth;

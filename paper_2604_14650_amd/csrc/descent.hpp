@@ -15,10 +15,11 @@
 
 namespace planb {
 
-template <int B, int KPL, int R, bool WIDE, bool BIN = false>
+template <int B, int KPL, int R, int KB, bool BIN = false>
 struct Descent {
-    using KF = KeyFmt<WIDE>;
+    using KF = KeyFmt<KB>;
     using K = typename KF::T;
+    static constexpr bool WIDE = KB == 16;
     static constexpr int G = B / KPL;   // lanes per lookup in the cache-resident levels
     static constexpr int LPW = 64 / G;  // lookups per wavefront per round there
     // Hybrid mode (BIN with KPL < B): every lane owns R lookups and walks the
@@ -41,6 +42,45 @@ struct Descent {
         for (uint32_t i = tid; i < units; i += nthreads) lds_raw[i] = src[i];
     }
 
+    // NW consecutive 32-bit words at p, with the widest loads their alignment
+    // allows (p is aligned to NW * 4 bytes, or to 16 when NW is a multiple of 4).
+    template <int NW>
+    static __device__ __forceinline__ void load_words(const void* p, uint32_t* w)
+    {
+        if constexpr (NW % 4 == 0) {
+            const uint4* q = static_cast<const uint4*>(p);
+#pragma unroll
+            for (int s = 0; s < NW / 4; ++s) {
+                const uint4 v = q[s];
+                w[4 * s] = v.x;
+                w[4 * s + 1] = v.y;
+                w[4 * s + 2] = v.z;
+                w[4 * s + 3] = v.w;
+            }
+        } else if constexpr (NW % 2 == 0) {
+            const uint2* q = static_cast<const uint2*>(p);
+#pragma unroll
+            for (int s = 0; s < NW / 2; ++s) {
+                const uint2 v = q[s];
+                w[2 * s] = v.x;
+                w[2 * s + 1] = v.y;
+            }
+        } else {
+            const uint32_t* q = static_cast<const uint32_t*>(p);
+#pragma unroll
+            for (int s = 0; s < NW; ++s) w[s] = q[s];
+        }
+    }
+
+    // key s of a run of narrow keys held as words (KB 8: two words, KB 4: one) <= x
+    static __device__ __forceinline__ int word_key_le(const uint32_t* w, int s, uint64_t xhi)
+    {
+        if constexpr (KB == 8)
+            return (((uint64_t)w[2 * s + 1] << 32) | w[2 * s]) <= xhi;
+        else
+            return w[s] <= (uint32_t)(xhi >> 32);
+    }
+
     // Keys <= x in the node whose first slot is keys[node0], summed over the
     // lookup's G lanes (lane j of the group is `j`).
     template <bool FROM_LDS>
@@ -59,17 +99,16 @@ struct Descent {
             return c;
         }
         int cnt = 0;
-        if constexpr (!WIDE && KPL >= 2) {
-            // 8-byte keys: each lane reads its KPL keys as contiguous 16-byte
-            // pairs, so a group covers its node with G x KPL/2 full-width loads
-            const uint4* p = reinterpret_cast<const uint4*>(keys + node0 + (size_t)j * KPL);
+        if constexpr (!WIDE && KPL * KB >= 8) {
+            // narrow keys: each lane reads its KPL keys contiguously with
+            // full-width loads, so a group covers its node with few loads
+            constexpr int NW = KPL * KB / 4;
+            uint32_t w[NW];
+            load_words<NW>(keys + node0 + (size_t)j * KPL, w);
 #pragma unroll
-            for (int s = 0; s < KPL / 2; ++s) {
-                const uint4 v = p[s];
-                cnt += ((((uint64_t)v.y << 32) | v.x) <= xhi) + ((((uint64_t)v.w << 32) | v.z) <= xhi);
-            }
+            for (int s = 0; s < KPL; ++s) cnt += word_key_le(w, s, xhi);
         } else {
-            // 16-byte keys (or one 8-byte key per lane): key s*G + j, so one
+            // 16-byte keys (or one 4-byte key per lane): key s*G + j, so one
             // load instruction covers G consecutive keys of each group's node
 #pragma unroll
             for (int s = 0; s < KPL; ++s) cnt += KF::le(keys[node0 + s * G + j], xhi, xlo);
@@ -84,7 +123,7 @@ struct Descent {
     // in the same leaf, so the lane that loaded it picks the word out of its
     // registers and the group reads it with one cross-lane shuffle.
     static constexpr int kb = (int)sizeof(K);
-    static constexpr bool kContig = !WIDE && kLPER >= 2;
+    static constexpr bool kContig = !WIDE && kLPER * kb >= 8;
     static constexpr int kW = kLPER * kb / 4;  // 32-bit words of a leaf per lane
 
     // lane of the group, and word of that lane, that hold byte `byte` of a leaf
@@ -115,15 +154,7 @@ struct Descent {
     static __device__ __forceinline__ void leaf_load(const K* keys, size_t node0, int j, LeafWords& L)
     {
         if constexpr (kContig) {
-            const uint4* p = reinterpret_cast<const uint4*>(keys + node0 + (size_t)j * kLPER);
-#pragma unroll
-            for (int s = 0; s < kLPER / 2; ++s) {
-                const uint4 v = p[s];
-                L.w[4 * s] = v.x;
-                L.w[4 * s + 1] = v.y;
-                L.w[4 * s + 2] = v.z;
-                L.w[4 * s + 3] = v.w;
-            }
+            load_words<kW>(keys + node0 + (size_t)j * kLPER, L.w);
         } else {
 #pragma unroll
             for (int s = 0; s < kLPER; ++s) {
@@ -133,9 +164,11 @@ struct Descent {
                     L.w[4 * s + 1] = k.y;
                     L.w[4 * s + 2] = k.z;
                     L.w[4 * s + 3] = k.w;
-                } else {
+                } else if constexpr (KB == 8) {
                     L.w[2 * s] = (uint32_t)k;
                     L.w[2 * s + 1] = (uint32_t)(k >> 32);
+                } else {
+                    L.w[s] = k;
                 }
             }
         }
@@ -152,7 +185,7 @@ struct Descent {
             if constexpr (WIDE)
                 le = KF::le(make_uint4(L.w[4 * s], L.w[4 * s + 1], L.w[4 * s + 2], L.w[4 * s + 3]), xhi, xlo);
             else
-                le = (((uint64_t)L.w[2 * s + 1] << 32) | L.w[2 * s]) <= xhi;
+                le = word_key_le(L.w, s, xhi);
             cnt += leaf_slot_is_key(slot, kb, kLC) ? le : 0;
         }
         return cnt;
@@ -238,7 +271,22 @@ struct Descent {
             __builtin_nontemporal_store(hop, static_cast<uint16_t*>(out) + i);
     }
 
-    static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const K* lds_keys, const u64x2* addrs,
+    // Address i of a batch: 16-byte {hi, lo} records, or 4-byte IPv4
+    // addresses, which stand for the 128-bit address with those 32 bits on top.
+    static __device__ __forceinline__ void fetch(const u64x2* a, uint64_t i, uint64_t& hi, uint64_t& lo)
+    {
+        const u64x2 v = __builtin_nontemporal_load(a + i);
+        hi = v.x;
+        lo = v.y;
+    }
+    static __device__ __forceinline__ void fetch(const uint32_t* a, uint64_t i, uint64_t& hi, uint64_t& lo)
+    {
+        hi = (uint64_t)__builtin_nontemporal_load(a + i) << 32;
+        lo = 0;
+    }
+
+    template <typename A>
+    static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const K* lds_keys, const A* addrs,
                                                        uint64_t base, uint64_t n, void* out, int index_out)
     {
         const int lane = threadIdx.x & 63;
@@ -247,9 +295,7 @@ struct Descent {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t i = base + (uint64_t)r * 64 + lane;
-            const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
-            xh[r] = a.x;
-            xl[r] = a.y;
+            fetch(addrs, i < n ? i : n - 1, xh[r], xl[r]);
             q[r] = 0;
         }
         // LDS-staged levels, one lane per lookup
@@ -313,7 +359,8 @@ struct Descent {
 
     // Lookups [base, base + kStep) of a batch of n >= 1 addresses.  Every lane
     // of the wavefront must call this together (DPP crosses lanes).
-    static __device__ __forceinline__ void step(const TreeDesc& t, const K* lds_keys, const u64x2* addrs,
+    template <typename A>
+    static __device__ __forceinline__ void step(const TreeDesc& t, const K* lds_keys, const A* addrs,
                                                 uint64_t base, uint64_t n, void* out, int index_out)
     {
         if constexpr (kHybrid) {
@@ -329,9 +376,7 @@ struct Descent {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t i = base + (uint64_t)r * LPW + grp;
-            const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
-            xhi[r] = a.x;
-            xlo[r] = a.y;
+            fetch(addrs, i < n ? i : n - 1, xhi[r], xlo[r]);
             q[r] = 0;
         }
         for (uint32_t l = 0; l + 1 < t.depth; ++l) {
@@ -365,66 +410,77 @@ struct Descent {
 };
 
 // Key i of the dense interval order, read from the leaf level of the tree.
-template <int B, bool WIDE>
-__device__ inline typename KeyFmt<WIDE>::T leaf_key(const TreeDesc& t, uint64_t i)
+template <int B, int KB>
+__device__ inline typename KeyFmt<KB>::T leaf_key(const TreeDesc& t, uint64_t i)
 {
-    constexpr int kb = (int)sizeof(typename KeyFmt<WIDE>::T);
+    constexpr int kb = KB;
     constexpr uint64_t LC = leaf_cap_for(B, kb), LS = leaf_slots_for(B, kb);
-    const auto* keys = static_cast<const typename KeyFmt<WIDE>::T*>(t.keys);
+    const auto* keys = static_cast<const typename KeyFmt<KB>::T*>(t.keys);
     return keys[t.leaf_base + (i / LC) * LS + leaf_key_slot((uint32_t)(i % LC), kb)];
 }
 
-// Picks KernelOf<B, KPL, R, W, BS, BIN>::get() for runtime values among the
+// Picks KernelOf<B, KPL, R, KB, BS, BIN>::get() for runtime values among the
 // compiled-in variants: B in {8, 16, 32}, KPL in {1, 2, 4, 8, 16} with B/KPL
-// in [1, 32], R in {1, 2, 4}, W (wide keys), BS in {512, 1024}, and BIN
-// (binary search by one lane per lookup in the LDS levels; with KPL < B the
-// lower levels are then shared by B/KPL lanes, for B/KPL in {2, 4}).
-template <template <int, int, int, bool, int, bool> class KernelOf>
+// in [1, 32], R in {1, 2, 4}, KB (key slot bytes) in {4, 8, 16}, BS in
+// {512, 1024}, and BIN (binary search by one lane per lookup in the LDS
+// levels; with KPL < B the lower levels are then shared by B/KPL lanes, for
+// B/KPL in {2, 4}).
+template <template <int, int, int, int, int, bool> class KernelOf>
 struct VariantTable {
-    using Fn = typename KernelOf<8, 1, 1, true, 512, false>::Fn;
+    using Fn = typename KernelOf<8, 1, 1, 16, 512, false>::Fn;
 
-    template <int B, int KPL, bool W, int BS, bool BIN>
+    template <int B, int KPL, int KB, int BS, bool BIN>
     static Fn by_r(int R)
     {
         switch (R) {
-        case 1: return KernelOf<B, KPL, 1, W, BS, BIN>::get();
-        case 2: return KernelOf<B, KPL, 2, W, BS, BIN>::get();
-        case 4: return KernelOf<B, KPL, 4, W, BS, BIN>::get();
+        case 1: return KernelOf<B, KPL, 1, KB, BS, BIN>::get();
+        case 2: return KernelOf<B, KPL, 2, KB, BS, BIN>::get();
+        case 4: return KernelOf<B, KPL, 4, KB, BS, BIN>::get();
         default: return nullptr;
         }
     }
-    template <int B, bool W, int BS>
+    template <int B, int KB, int BS>
     static Fn by_kpl(int kpl, int R, bool bin)
     {
         if (bin) {
-            if (kpl == B) return by_r<B, B, W, BS, true>(R);
-            if (kpl == B / 2) return by_r<B, B / 2, W, BS, true>(R);
-            if (kpl == B / 4) return by_r<B, B / 4, W, BS, true>(R);
+            if (kpl == B) return by_r<B, B, KB, BS, true>(R);
+            if (kpl == B / 2) return by_r<B, B / 2, KB, BS, true>(R);
+            if (kpl == B / 4) return by_r<B, B / 4, KB, BS, true>(R);
             return nullptr;
         }
         switch (kpl) {
-        case 1: return by_r<B, 1, W, BS, false>(R);
-        case 2: return by_r<B, 2, W, BS, false>(R);
-        case 4: return by_r<B, 4, W, BS, false>(R);
-        case 8: return by_r<B, 8, W, BS, false>(R);
-        case 16: if constexpr (B >= 16) return by_r<B, 16, W, BS, false>(R); else return nullptr;
+        case 1: return by_r<B, 1, KB, BS, false>(R);
+        case 2: return by_r<B, 2, KB, BS, false>(R);
+        case 4: return by_r<B, 4, KB, BS, false>(R);
+        case 8: return by_r<B, 8, KB, BS, false>(R);
+        case 16: if constexpr (B >= 16) return by_r<B, 16, KB, BS, false>(R); else return nullptr;
         default: return nullptr;
         }
     }
-    template <bool W, int BS>
+    template <int KB, int BS>
     static Fn by_b(int B, int kpl, int R, bool bin)
     {
         switch (B) {
-        case 8: return by_kpl<8, W, BS>(kpl, R, bin);
-        case 16: return by_kpl<16, W, BS>(kpl, R, bin);
-        case 32: return by_kpl<32, W, BS>(kpl, R, bin);
+        case 8: return by_kpl<8, KB, BS>(kpl, R, bin);
+        case 16: return by_kpl<16, KB, BS>(kpl, R, bin);
+        case 32: return by_kpl<32, KB, BS>(kpl, R, bin);
         default: return nullptr;
         }
     }
-    static Fn pick(int B, int kpl, int R, bool wide, int bs, bool bin = false)
+    template <int BS>
+    static Fn by_kb(int B, int kpl, int R, int kb, bool bin)
     {
-        if (bs == 512) return wide ? by_b<true, 512>(B, kpl, R, bin) : by_b<false, 512>(B, kpl, R, bin);
-        if (bs == 1024) return wide ? by_b<true, 1024>(B, kpl, R, bin) : by_b<false, 1024>(B, kpl, R, bin);
+        switch (kb) {
+        case 4: return by_b<4, BS>(B, kpl, R, bin);
+        case 8: return by_b<8, BS>(B, kpl, R, bin);
+        case 16: return by_b<16, BS>(B, kpl, R, bin);
+        default: return nullptr;
+        }
+    }
+    static Fn pick(int B, int kpl, int R, int kb, int bs, bool bin = false)
+    {
+        if (bs == 512) return by_kb<512>(B, kpl, R, kb, bin);
+        if (bs == 1024) return by_kb<1024>(B, kpl, R, kb, bin);
         return nullptr;
     }
 };

@@ -29,14 +29,17 @@ struct TreeDesc {
     uint32_t last[kDevMaxLevels];  // last allocated node of each level (the leaf level last)
 };
 
-// Key formats.  Wide: the 16-byte record {hi, lo}, compared as a 128-bit
-// unsigned integer.  Narrow: only hi is stored, which a tree uses when every
-// key's lo word is zero; then key <= x exactly when key.hi <= x.hi.
-template <bool WIDE>
+// Key formats by slot width KB.  16: the record {hi, lo}, compared as a
+// 128-bit unsigned integer.  8: only hi is stored, which a tree uses when
+// every key's lo word is zero; then key <= x exactly when key.hi <= x.hi.
+// 4: only the top 32 bits are stored, when every key's low 96 bits are zero
+// (every prefix at most /32, e.g. IPv4 rules placed in the top 32 bits);
+// then key <= x exactly when those 32 bits of the key are <= x's.
+template <int KB>
 struct KeyFmt;
 
 template <>
-struct KeyFmt<true> {
+struct KeyFmt<16> {
     using T = uint4;
     static __device__ __forceinline__ int le(uint4 k, uint64_t xhi, uint64_t xlo)
     {
@@ -47,12 +50,16 @@ struct KeyFmt<true> {
 };
 
 template <>
-struct KeyFmt<false> {
+struct KeyFmt<8> {
     using T = uint64_t;
     static __device__ __forceinline__ int le(uint64_t k, uint64_t xhi, uint64_t) { return k <= xhi; }
 };
 
-__device__ __forceinline__ int key_le(uint4 k, uint64_t xhi, uint64_t xlo) { return KeyFmt<true>::le(k, xhi, xlo); }
+template <>
+struct KeyFmt<4> {
+    using T = uint32_t;
+    static __device__ __forceinline__ int le(uint32_t k, uint64_t xhi, uint64_t) { return k <= (uint32_t)(xhi >> 32); }
+};
 
 // Sum of v over aligned groups of G consecutive lanes; every lane of a group
 // receives the group's total.  G <= 16 stays inside one DPP row.

@@ -146,10 +146,10 @@ __device__ inline uint64_t predict_position(float y, uint64_t m)
 
 
 // Plain one-lane descent (every key of each node), used for fallbacks.
-template <int B, bool WIDE>
+template <int B, int KB>
 __device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_t xlo)
 {
-    using KF = KeyFmt<WIDE>;
+    using KF = KeyFmt<KB>;
     const auto* keys = static_cast<const typename KF::T*>(t.keys);
     uint32_t q = 0;
     for (uint32_t l = 0; l + 1 < t.depth; ++l) {
@@ -174,12 +174,12 @@ constexpr int kLearnBlock = 256;
 // batch of n (4 MFMA tiles of 16), then one lane per address for the window
 // search, verification and fallback.  R holds the model's weight operands and
 // sb1/sb2/sw3 its biases and output weights as float.
-template <int B, bool WIDE>
+template <int B, int KB>
 __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const MlpRegs& R, const float* sb1,
                                     const float* sb2, const float* sw3, float b3, const u64x2* addrs, uint64_t base,
                                     uint64_t n, uint16_t* out, uint32_t* fallbacks)
 {
-    using KF = KeyFmt<WIDE>;
+    using KF = KeyFmt<KB>;
     const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
     const uint64_t m = t.m_minus_1 + 1;
     float y = 0.f;
@@ -207,19 +207,19 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     uint64_t j = 0;
     if (ok) {
         uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
-        ok = KF::le(leaf_key<B, WIDE>(t, lo), xhi, xlo) &&
-             (hi == m - 1 || !KF::le(leaf_key<B, WIDE>(t, hi + 1), xhi, xlo));
+        ok = KF::le(leaf_key<B, KB>(t, lo), xhi, xlo) &&
+             (hi == m - 1 || !KF::le(leaf_key<B, KB>(t, hi + 1), xhi, xlo));
         if (ok) {  // last index in [lo, hi] whose key is <= x
             while (lo < hi) {
                 const uint64_t mid = (lo + hi + 1) >> 1;
-                if (KF::le(leaf_key<B, WIDE>(t, mid), xhi, xlo)) lo = mid; else hi = mid - 1;
+                if (KF::le(leaf_key<B, KB>(t, mid), xhi, xlo)) lo = mid; else hi = mid - 1;
             }
             j = lo;
         }
     }
     const uint64_t i = base + l;
     const bool need = !ok && i < n;
-    if (need) j = descend_lane<B, WIDE>(t, xhi, xlo);
+    if (need) j = descend_lane<B, KB>(t, xhi, xlo);
     if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
     if (fallbacks) {
         const uint64_t mask = __ballot(need);
@@ -228,7 +228,7 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
 }
 
 // Learned lookup of one batch (grid stride over 64-address wavefront steps).
-template <int B, bool WIDE>
+template <int B, int KB>
 __global__ void __launch_bounds__(kLearnBlock)
 learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out,
                uint32_t* __restrict__ fallbacks)
@@ -242,7 +242,7 @@ learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_
     const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
     for (uint64_t base = wave * 64; base < n; base += nwaves * 64)
-        learned_step<B, WIDE>(t, M, R, sb1, sb2, sw3, b3, addrs, base, n, out, fallbacks);
+        learned_step<B, KB>(t, M, R, sb1, sb2, sw3, b3, addrs, base, n, out, fallbacks);
 }
 
 // Learned lookups of bursts that each name a table: tiles of 64 addresses
@@ -250,7 +250,7 @@ learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_
 // model.  A wavefront reloads the weight operands, and restages the biases in
 // its own LDS area, when its tile's table changes; a table without a model
 // is searched by the tree descent.
-template <int B, bool WIDE>
+template <int B, int KB>
 __global__ void __launch_bounds__(kLearnBlock)
 multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __restrict__ models, uint32_t n_tables,
                      const BurstRec* __restrict__ bursts, const uint32_t* __restrict__ count, uint32_t max_bursts,
@@ -281,7 +281,7 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
             const uint64_t i = base + l;
             if (i < br.n) {
                 const u64x2 a = __builtin_nontemporal_load(addrs + i);
-                __builtin_nontemporal_store(t.vals[descend_lane<B, WIDE>(t, a.x, a.y)], out + i);
+                __builtin_nontemporal_store(t.vals[descend_lane<B, KB>(t, a.x, a.y)], out + i);
             }
             continue;
         }
@@ -296,7 +296,7 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             loaded = br.table;
         }
-        learned_step<B, WIDE>(t, M, R, sb1, sb2, sw3, b3, addrs, base, br.n, out, fallbacks);
+        learned_step<B, KB>(t, M, R, sb1, sb2, sw3, b3, addrs, base, br.n, out, fallbacks);
         __builtin_amdgcn_wave_barrier();  // the next tile may restage the vectors
     }
 }
@@ -570,17 +570,23 @@ struct LearnedModel {
 
 namespace {
 
-template <int B, bool W>
+template <int B, int KB>
 struct LearnedKernel {
-    static void* get() { return reinterpret_cast<void*>(learned_kernel<B, W>); }
+    static void* get() { return reinterpret_cast<void*>(learned_kernel<B, KB>); }
 };
 
-void* pick_learned(int B, bool wide)
+template <int B>
+void* learned_by_kb(int kb)
+{
+    return kb == 4 ? LearnedKernel<B, 4>::get() : kb == 8 ? LearnedKernel<B, 8>::get() : LearnedKernel<B, 16>::get();
+}
+
+void* pick_learned(int B, int kb)
 {
     switch (B) {
-    case 8: return wide ? LearnedKernel<8, true>::get() : LearnedKernel<8, false>::get();
-    case 16: return wide ? LearnedKernel<16, true>::get() : LearnedKernel<16, false>::get();
-    case 32: return wide ? LearnedKernel<32, true>::get() : LearnedKernel<32, false>::get();
+    case 8: return learned_by_kb<8>(kb);
+    case 16: return learned_by_kb<16>(kb);
+    case 32: return learned_by_kb<32>(kb);
     default: return nullptr;
     }
 }
@@ -765,20 +771,27 @@ ModelDesc ready_model_desc(const planb_fib_t* f)
 
 namespace {
 
-template <int B, bool W>
+template <int B, int KB>
 struct MultiLearnedKernel {
-    static const void* get() { return reinterpret_cast<const void*>(multi_learned_kernel<B, W>); }
+    static const void* get() { return reinterpret_cast<const void*>(multi_learned_kernel<B, KB>); }
 };
+
+template <int B>
+const void* multi_learned_by_kb(int kb)
+{
+    return kb == 4 ? MultiLearnedKernel<B, 4>::get() : kb == 8 ? MultiLearnedKernel<B, 8>::get()
+                                                               : MultiLearnedKernel<B, 16>::get();
+}
 
 }  // namespace
 
-int plan_multi_learned(int fanout, bool wide, uint32_t max_bursts, MultiLaunch* L)
+int plan_multi_learned(int fanout, int kb, uint32_t max_bursts, MultiLaunch* L)
 {
     const void* fn = nullptr;
     switch (fanout) {
-    case 8: fn = wide ? MultiLearnedKernel<8, true>::get() : MultiLearnedKernel<8, false>::get(); break;
-    case 16: fn = wide ? MultiLearnedKernel<16, true>::get() : MultiLearnedKernel<16, false>::get(); break;
-    case 32: fn = wide ? MultiLearnedKernel<32, true>::get() : MultiLearnedKernel<32, false>::get(); break;
+    case 8: fn = multi_learned_by_kb<8>(kb); break;
+    case 16: fn = multi_learned_by_kb<16>(kb); break;
+    case 32: fn = multi_learned_by_kb<32>(kb); break;
     default: return fail(PLANB_EINVAL, "no learned multi-FIB kernel for this fanout");
     }
     DevProps p;
@@ -1019,7 +1032,7 @@ int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size
         return fail(PLANB_EINVAL, "misaligned pointer");
     int rc = check_current_device(fib);
     if (rc != PLANB_OK) return rc;
-    void* fn = pick_learned((int)fib->desc.fanout, fib->desc.key_bytes == 16);
+    void* fn = pick_learned((int)fib->desc.fanout, (int)fib->desc.key_bytes);
     if (!fn) return fail(PLANB_EINVAL, "no learned kernel for this fanout");
     DevProps p;
     hipError_t e = dev_props(&p);

@@ -24,7 +24,7 @@ ModelDesc ready_model_desc(const planb_fib_t* f);
 
 // Learned multi-FIB launch: per burst, the table's model and error table
 // (or the tree descent where the table has no model).
-int plan_multi_learned(int fanout, bool wide, uint32_t max_bursts, MultiLaunch* L);
+int plan_multi_learned(int fanout, int kb, uint32_t max_bursts, MultiLaunch* L);
 hipError_t launch_multi_learned(const MultiLaunch& L, const TreeDesc* tables, const ModelDesc* models,
                                 uint32_t n_tables, const BurstRec* bursts, const uint32_t* count,
                                 uint32_t max_bursts, uint32_t* fallbacks, hipStream_t stream);

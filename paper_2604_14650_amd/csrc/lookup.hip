@@ -27,11 +27,28 @@
 
 namespace planb {
 
-template <int B, int KPL, int R, bool WIDE, int BS, bool BIN>
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
 __global__ void __launch_bounds__(BS)
 lookup_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
 {
-    using D = Descent<B, KPL, R, WIDE, BIN>;
+    using D = Descent<B, KPL, R, KB, BIN>;
+    extern __shared__ uint4 lds_raw[];
+    D::stage(t, lds_raw, threadIdx.x, BS);
+    __syncthreads();
+    const uint64_t wave = (uint64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (BS / 64);
+    const auto* lds_keys = reinterpret_cast<const typename D::K*>(lds_raw);
+    for (uint64_t base = wave * D::kStep; base < n; base += nwaves * D::kStep)
+        D::step(t, lds_keys, addrs, base, n, out, index_out);
+}
+
+// The same over 4-byte IPv4 addresses (each standing for the 128-bit address
+// with those 32 bits on top), for trees with 32-bit key slots.
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
+__global__ void __launch_bounds__(BS)
+lookup_v4_kernel(TreeDesc t, const uint32_t* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
+{
+    using D = Descent<B, KPL, R, KB, BIN>;
     extern __shared__ uint4 lds_raw[];
     D::stage(t, lds_raw, threadIdx.x, BS);
     __syncthreads();
@@ -47,11 +64,11 @@ lookup_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __r
 // ablation), kept as the first rung of the design ladder.  Every probe is a
 // dependent read of one key (about log2(m) of them), then one read of the
 // next-hop array.  Keys are read in place from the leaves.
-template <int B, bool WIDE>
+template <int B, int KB>
 __global__ void __launch_bounds__(256)
 bsearch_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out)
 {
-    using KF = KeyFmt<WIDE>;
+    using KF = KeyFmt<KB>;
     const uint64_t m = t.m_minus_1 + 1;
     uint64_t top = 1;
     while (top * 2 <= m) top *= 2;
@@ -60,7 +77,7 @@ bsearch_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, uint16_t
         uint64_t c = 0;  // starts <= x (starts[0] = 0 <= x, so c >= 1)
         for (uint64_t step = top; step >= 1; step >>= 1) {
             const uint64_t probe = c + step - 1;
-            if (probe < m && KF::le(leaf_key<B, WIDE>(t, probe), a.x, a.y)) c += step;
+            if (probe < m && KF::le(leaf_key<B, KB>(t, probe), a.x, a.y)) c += step;
         }
         __builtin_nontemporal_store(t.vals[c - 1], out + i);
     }
@@ -68,17 +85,29 @@ bsearch_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, uint16_t
 
 namespace {
 
-template <int B, int KPL, int R, bool W, int BS, bool BIN>
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
 struct PlainKernel {
     using Fn = void (*)(TreeDesc, const u64x2*, uint64_t, void*, int);
-    static Fn get() { return lookup_kernel<B, KPL, R, W, BS, BIN>; }
+    static Fn get() { return lookup_kernel<B, KPL, R, KB, BS, BIN>; }
 };
 
-using KernelFn = PlainKernel<8, 1, 1, true, 512, false>::Fn;
+using KernelFn = PlainKernel<8, 1, 1, 16, 512, false>::Fn;
 
-KernelFn pick(int B, int kpl, int R, bool wide, int bs, bool bin)
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
+struct V4Kernel {  // instantiated for 32-bit key slots only
+    using Fn = void (*)(TreeDesc, const uint32_t*, uint64_t, void*, int);
+    static Fn get()
+    {
+        if constexpr (KB == 4)
+            return lookup_v4_kernel<B, KPL, R, KB, BS, BIN>;
+        else
+            return nullptr;
+    }
+};
+
+KernelFn pick(int B, int kpl, int R, int kb, int bs, bool bin)
 {
-    return VariantTable<PlainKernel>::pick(B, kpl, R, wide, bs, bin);
+    return VariantTable<PlainKernel>::pick(B, kpl, R, kb, bs, bin);
 }
 
 std::mutex g_mu;
@@ -135,7 +164,7 @@ hipError_t occupancy(const void* fn, int bs, size_t lds, int* blocks)
     return hipSuccess;
 }
 
-bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin) { return pick(B, kpl, R, true, bs, bin) != nullptr; }
+bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin) { return pick(B, kpl, R, 16, bs, bin) != nullptr; }
 
 int max_lds_bytes()
 {
@@ -148,10 +177,13 @@ hipError_t launch_bsearch(const TreeDesc& t, const void* addrs, uint64_t n, uint
 {
     if (n == 0) return hipSuccess;
     using Fn = void (*)(TreeDesc, const u64x2*, uint64_t, uint16_t*);
-    const bool wide = t.key_bytes == 16;
-    Fn fn = t.fanout == 8 ? (wide ? bsearch_kernel<8, true> : bsearch_kernel<8, false>)
-          : t.fanout == 16 ? (wide ? bsearch_kernel<16, true> : bsearch_kernel<16, false>)
-          : t.fanout == 32 ? (wide ? bsearch_kernel<32, true> : bsearch_kernel<32, false>) : nullptr;
+    auto by_kb = [&](auto b) -> Fn {
+        constexpr int Bc = decltype(b)::value;
+        return t.key_bytes == 4 ? bsearch_kernel<Bc, 4> : t.key_bytes == 8 ? bsearch_kernel<Bc, 8> : bsearch_kernel<Bc, 16>;
+    };
+    Fn fn = t.fanout == 8 ? by_kb(std::integral_constant<int, 8>{})
+          : t.fanout == 16 ? by_kb(std::integral_constant<int, 16>{})
+          : t.fanout == 32 ? by_kb(std::integral_constant<int, 32>{}) : nullptr;
     if (!fn) return hipErrorInvalidValue;
     DevProps p;
     hipError_t e = dev_props(&p);
@@ -164,11 +196,33 @@ hipError_t launch_bsearch(const TreeDesc& t, const void* addrs, uint64_t n, uint
     return hipGetLastError();
 }
 
+hipError_t launch_lookup_v4(const TreeDesc& t, const LookupTuning& tu, const uint32_t* addrs, uint64_t n, void* out,
+                            bool index_out, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    if (t.key_bytes != 4) return hipErrorInvalidValue;
+    V4Kernel<8, 1, 1, 4, 512, false>::Fn fn = VariantTable<V4Kernel>::pick((int)t.fanout, tu.kpl, tu.R, 4, tu.block, tu.bin);
+    if (!fn) return hipErrorInvalidValue;
+    DevProps p;
+    hipError_t e = dev_props(&p);
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)t.lds_slots * t.key_bytes;
+    if (lds > (size_t)p.max_lds) return hipErrorInvalidValue;
+    int nb = 1;
+    if ((e = occupancy(reinterpret_cast<const void*>(fn), tu.block, lds, &nb)) != hipSuccess) return e;
+    const uint64_t per_block = (uint64_t)(tu.block / 64) * lookups_per_wave_step((int)t.fanout, tu);
+    const uint64_t want = (n + per_block - 1) / per_block;
+    const uint64_t cap = (uint64_t)p.cus * nb;
+    const unsigned grid = (unsigned)(want < cap ? want : cap);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(tu.block), lds, stream, t, addrs, n, out, index_out ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
                          bool index_out, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    KernelFn fn = pick((int)t.fanout, tu.kpl, tu.R, t.key_bytes == 16, tu.block, tu.bin);
+    KernelFn fn = pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
     if (!fn) return hipErrorInvalidValue;
     DevProps p;
     hipError_t e = dev_props(&p);

@@ -44,6 +44,9 @@ hipError_t occupancy(const void* fn, int bs, size_t lds, int* blocks);
 // next hops, or uint32 interval indices when index_out.
 hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
                          bool index_out, hipStream_t stream);
+// The same over 4-byte IPv4 addresses, for trees with 32-bit key slots.
+hipError_t launch_lookup_v4(const TreeDesc& t, const LookupTuning& tu, const uint32_t* addrs, uint64_t n, void* out,
+                            bool index_out, hipStream_t stream);
 // Binary search over the sorted starts, one lane per address (ablation baseline).
 hipError_t launch_bsearch(const TreeDesc& t, const void* addrs, uint64_t n, uint16_t* out, hipStream_t stream);
 

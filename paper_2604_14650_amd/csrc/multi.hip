@@ -12,12 +12,12 @@
 
 namespace planb {
 
-template <int B, int KPL, int R, bool WIDE, int BS, bool BIN>
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
 __global__ void __launch_bounds__(BS)
 multi_kernel(const TreeDesc* __restrict__ tables, uint32_t n_tables, const BurstRec* __restrict__ bursts,
              const uint32_t* __restrict__ count, uint32_t max_bursts)
 {
-    using D = Descent<B, KPL, R, WIDE, BIN>;
+    using D = Descent<B, KPL, R, KB, BIN>;
     extern __shared__ uint32_t lds_u32[];
     uint32_t* tile_off = lds_u32;                 // max_bursts + 1
     uint32_t* part = tile_off + max_bursts + 1;   // BS
@@ -35,17 +35,17 @@ multi_kernel(const TreeDesc* __restrict__ tables, uint32_t n_tables, const Burst
 
 namespace {
 
-template <int B, int KPL, int R, bool W, int BS, bool BIN>
+template <int B, int KPL, int R, int KB, int BS, bool BIN>
 struct MultiKernel {
     using Fn = void (*)(const TreeDesc*, uint32_t, const BurstRec*, const uint32_t*, uint32_t);
-    static Fn get() { return multi_kernel<B, KPL, R, W, BS, BIN>; }
+    static Fn get() { return multi_kernel<B, KPL, R, KB, BS, BIN>; }
 };
 
 }  // namespace
 
-int plan_multi(int fanout, bool wide, const LookupTuning& tu, uint32_t max_bursts, MultiLaunch* L)
+int plan_multi(int fanout, int kb, const LookupTuning& tu, uint32_t max_bursts, MultiLaunch* L)
 {
-    L->fn = reinterpret_cast<const void*>(VariantTable<MultiKernel>::pick(fanout, tu.kpl, tu.R, wide, tu.block, false));
+    L->fn = reinterpret_cast<const void*>(VariantTable<MultiKernel>::pick(fanout, tu.kpl, tu.R, kb, tu.block, false));
     if (!L->fn) return fail(PLANB_EINVAL, "no multi-FIB kernel for this fanout / tuning");
     DevProps p;
     hipError_t e = dev_props(&p);
@@ -178,7 +178,7 @@ int planb_lookup_multi(const planb_tableset_t* ts, const planb_burst_t* bursts, 
         reinterpret_cast<uintptr_t>(n_bursts) % 4)
         return fail(PLANB_EINVAL, "NULL or misaligned descriptor pointer");
     MultiLaunch L;
-    int rc = plan_multi(ts->fanout, ts->key_bytes == 16, ts->tune, max_bursts, &L);
+    int rc = plan_multi(ts->fanout, ts->key_bytes ? ts->key_bytes : 16, ts->tune, max_bursts, &L);
     if (rc != PLANB_OK) return rc;
     hipError_t e = launch_multi(L, ts->dev, ts->max_tables, reinterpret_cast<const BurstRec*>(bursts), n_bursts,
                                 max_bursts, static_cast<hipStream_t>(stream));
@@ -194,7 +194,7 @@ int planb_lookup_multi_learned(const planb_tableset_t* ts, const planb_burst_t* 
         reinterpret_cast<uintptr_t>(n_bursts) % 4 || reinterpret_cast<uintptr_t>(fallback_count) % 4)
         return fail(PLANB_EINVAL, "NULL or misaligned descriptor pointer");
     MultiLaunch L;
-    int rc = plan_multi_learned(ts->fanout, ts->key_bytes == 16, max_bursts, &L);
+    int rc = plan_multi_learned(ts->fanout, ts->key_bytes ? ts->key_bytes : 16, max_bursts, &L);
     if (rc != PLANB_OK) return rc;
     hipError_t e = launch_multi_learned(L, ts->dev, ts->dev_models, ts->max_tables,
                                         reinterpret_cast<const BurstRec*>(bursts), n_bursts, max_bursts,
@@ -209,11 +209,11 @@ const TreeDesc* tableset_device(const planb_tableset_t* ts) { return ts->dev; }
 const ModelDesc* tableset_models(const planb_tableset_t* ts) { return ts->dev_models; }
 int tableset_plan_learned(const planb_tableset_t* ts, uint32_t max_bursts, MultiLaunch* L)
 {
-    return plan_multi_learned(ts->fanout ? ts->fanout : 16, ts->key_bytes == 16, max_bursts, L);
+    return plan_multi_learned(ts->fanout ? ts->fanout : 16, ts->key_bytes ? ts->key_bytes : 16, max_bursts, L);
 }
 uint32_t tableset_capacity(const planb_tableset_t* ts) { return ts->max_tables; }
 int tableset_plan(const planb_tableset_t* ts, uint32_t max_bursts, MultiLaunch* L)
 {
-    return plan_multi(ts->fanout ? ts->fanout : 16, ts->key_bytes == 16, ts->tune, max_bursts, L);
+    return plan_multi(ts->fanout ? ts->fanout : 16, ts->key_bytes ? ts->key_bytes : 16, ts->tune, max_bursts, L);
 }
 }  // namespace planb

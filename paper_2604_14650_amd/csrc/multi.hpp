@@ -20,7 +20,7 @@ struct MultiLaunch {
     size_t lds = 0;
 };
 
-int plan_multi(int fanout, bool wide, const LookupTuning& tu, uint32_t max_bursts, MultiLaunch* L);
+int plan_multi(int fanout, int kb, const LookupTuning& tu, uint32_t max_bursts, MultiLaunch* L);
 hipError_t launch_multi(const MultiLaunch& L, const TreeDesc* tables, uint32_t n_tables, const BurstRec* bursts,
                         const uint32_t* count, uint32_t max_bursts, hipStream_t stream);
 

@@ -339,8 +339,9 @@ planb_server_t* planb_server_create(const planb_server_cfg_t* cfg_in)
     if (cfg.max_lookups == 0) cfg.max_lookups = 1u << 20;
     if (cfg.fanout == 0) cfg.fanout = 16;
     if (cfg.key_bits == 0) cfg.key_bits = 128;
-    if ((cfg.key_bits != 64 && cfg.key_bits != 128) || (cfg.fanout != 8 && cfg.fanout != 16 && cfg.fanout != 32)) {
-        fail(PLANB_EINVAL, "server fanout must be 8/16/32 and key_bits 64 or 128");
+    if ((cfg.key_bits != 32 && cfg.key_bits != 64 && cfg.key_bits != 128) ||
+        (cfg.fanout != 8 && cfg.fanout != 16 && cfg.fanout != 32)) {
+        fail(PLANB_EINVAL, "server fanout must be 8/16/32 and key_bits 32, 64 or 128");
         return nullptr;
     }
     if (cfg.streams > 8 || cfg.max_tables > 65536 || cfg.max_bursts > 16384 || cfg.learned > 1 || cfg.reserved) {

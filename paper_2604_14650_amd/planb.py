@@ -117,6 +117,7 @@ _sig("planb_build_device", _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(planb_params_
 _sig("planb_lookup", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_lookup_index", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_lookup_bsearch", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
+_sig("planb_lookup_v4", ctypes.c_int, _vp, _vp, _sz, _vp, _vp)
 _sig("planb_free", None, _vp)
 _sig("planb_last_error", ctypes.c_char_p)
 _sig("planb_last_status", ctypes.c_int)
@@ -289,6 +290,14 @@ def planb_lookup_index(fib: Fib, addrs, n: int | None = None, out=None, stream=N
         n = addrs.shape[0]
     _check(_lib.planb_lookup_index(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"),
                                    _stream_handle(stream)))
+    return out
+
+
+def planb_lookup_v4(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
+    """addrs: device tensor (n,) int32 of IPv4 addresses; the FIB must hold 32-bit keys."""
+    if n is None:
+        n = addrs.shape[0]
+    _check(_lib.planb_lookup_v4(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), _stream_handle(stream)))
     return out
 
 

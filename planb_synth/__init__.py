@@ -25,6 +25,15 @@ Table 1 and its synthetic FIBs / traces in the evaluation section):
                 /128 host routes.
 * ``vrf``       a table of the ``tiny`` histogram with a given prefix count
                 (log-uniform 50k..500k across 16 tables) plus ::/0.
+* ``ipv4``      1,000,000 IPv4 prefixes shaped like a full BGP table: /24 58 %,
+                /22 11 %, /23 9 %, /21 5 %, /20 4 %, /19 3 %, /16 2.5 %,
+                /18 1.5 %, /17 1 %, /25-/32 4 % (uniform), and /8-/15 0.36 %
+                (rising from 0.002 % at /8 to 0.15 % at /15: there are only
+                2^L prefixes of length L); ~12 % nested up to depth 3; next
+                hops 0..65534.  IPv4 rules and addresses are placed in the top
+                32 bits of the 128-bit space (a 32-bit address a stands for
+                a << 96).
+* ``ipv4_tiny`` 2,000 prefixes of the ``ipv4`` histogram plus 0.0.0.0/0.
 """
 from __future__ import annotations
 
@@ -79,6 +88,19 @@ def _backbone_weights():
 
 
 BACKBONE_HIST = _backbone_weights()
+
+
+def _ipv4_weights():
+    d = {24: 0.58, 22: 0.11, 23: 0.09, 21: 0.05, 20: 0.04, 19: 0.03, 16: 0.025, 18: 0.015, 17: 0.01}
+    # short prefixes are few (there are only 2^L of each length L)
+    for L, p in {8: 2e-5, 9: 2e-5, 10: 5e-5, 11: 1e-4, 12: 3e-4, 13: 6e-4, 14: 1e-3, 15: 1.5e-3}.items():
+        d[L] = p
+    for L in range(25, 33):
+        d[L] = d.get(L, 0.0) + 0.04 / 8
+    return _hist(d)
+
+
+IPV4_HIST = _ipv4_weights()
 LARGE_HIST = BACKBONE_HIST * 0.95
 LARGE_HIST[128] += 0.05
 LARGE_HIST = LARGE_HIST / LARGE_HIST.sum()
@@ -93,11 +115,14 @@ class FibSpec:
     max_depth: int
     nh_max: int              # next hops drawn uniformly from 0..nh_max
     default_route: bool
+    v4: bool = False         # IPv4 rules (lengths <= 32) in the top 32 bits
 
 
 TINY = FibSpec("tiny", 1000, TINY_HIST, 0.15, 3, 255, True)
 BACKBONE = FibSpec("backbone", 200_000, BACKBONE_HIST, 0.12, 4, 65534, False)
 LARGE = FibSpec("large", 1_000_000, LARGE_HIST, 0.12, 4, 65534, False)
+IPV4 = FibSpec("ipv4", 1_000_000, IPV4_HIST, 0.12, 3, 65534, False, True)
+IPV4_TINY = FibSpec("ipv4_tiny", 2_000, IPV4_HIST, 0.15, 3, 255, True, True)
 
 
 def vrf_spec(n_prefixes: int) -> FibSpec:
@@ -130,6 +155,13 @@ def uniform_2000_3(rng, n):
     return out
 
 
+def uniform_v4(rng, n):
+    """n IPv4 addresses uniform over the 32-bit space, placed in the top 32 bits."""
+    out = np.zeros((n, 2), dtype=U64)
+    out[:, 0] = rng.integers(0, 1 << 32, size=n, dtype=U64) << U64(32)
+    return out
+
+
 def _apply_len(hi, lo, lens):
     """Zero the host bits of (hi, lo) for prefix lengths ``lens``."""
     return hi & ~HOST_HI[lens], lo & ~HOST_LO[lens]
@@ -154,7 +186,8 @@ def _draw_lengths(rng, hist, n, above=None):
 def make_fib(spec: FibSpec, seed: int) -> Fib:
     """Draw a FIB of ``spec.n_prefixes`` unique (prefix, length) rules.
 
-    Non-nested prefixes are uniform in 2000::/3.  A share ``spec.ext_share``
+    Non-nested prefixes are uniform in 2000::/3 (IPv4 specs: uniform over
+    the 32-bit space, in the top 32 bits).  A share ``spec.ext_share``
     are extensions: they copy a random existing prefix of depth < max_depth,
     draw their own length from the histogram conditioned on being longer, and
     randomise the bits between the two lengths.  Duplicates after masking are
@@ -166,10 +199,11 @@ def make_fib(spec: FibSpec, seed: int) -> Fib:
     maxlen = int(np.nonzero(hist)[0].max())
     n_ext = int(round(spec.ext_share * N))
     n_base = N - n_ext
+    space = uniform_v4 if spec.v4 else uniform_2000_3
 
     def base(n):
         L = _draw_lengths(rng, hist, n)
-        a = uniform_2000_3(rng, n)
+        a = space(rng, n)
         hi, lo = _apply_len(a[:, 0], a[:, 1], L)
         return hi, lo, L
 
@@ -185,7 +219,7 @@ def make_fib(spec: FibSpec, seed: int) -> Fib:
         par = elig[rng.integers(0, elig.size, size=nr)]
         Lp = L[par]
         Lc = _draw_lengths(rng, hist, nr, above=Lp)
-        r = uniform_2000_3(rng, nr)
+        r = space(rng, nr)
         # keep the parent's top Lp bits, randomise bits Lp..Lc-1, zero the rest
         chi = (hi[par] & ~HOST_HI[Lp]) | (r[:, 0] & HOST_HI[Lp])
         clo = (lo[par] & ~HOST_LO[Lp]) | (r[:, 1] & HOST_LO[Lp])
@@ -203,7 +237,7 @@ def make_fib(spec: FibSpec, seed: int) -> Fib:
         dup = np.setdiff1d(np.arange(hi.size), first)
         if dup.size == 0:
             break
-        a = uniform_2000_3(rng, dup.size)
+        a = space(rng, dup.size)
         hi[dup], lo[dup] = _apply_len(a[:, 0], a[:, 1], L[dup])
     else:  # pragma: no cover
         raise RuntimeError("could not draw a duplicate-free FIB")
@@ -278,6 +312,34 @@ def zipf_traffic(fib: Fib, n: int, seed: int, s: float = 1.1) -> np.ndarray:
     cdf /= cdf[-1]
     r = np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), N - 1)
     return inside_prefixes(rng, fib, rank_to_prefix[r])
+
+
+def ipv4_traffic(fib: Fib, n: int, inside_share: float, seed: int, chunk: int = 1 << 23) -> np.ndarray:
+    """``n`` 32-bit IPv4 addresses (uint32) for an IPv4 FIB: a share
+    ``inside_share`` inside a prefix chosen uniformly among the non-default
+    prefixes (prefix plus a uniform suffix), the rest uniform over 2^32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty(n, dtype=np.uint32)
+    cand = np.nonzero(fib.lengths > 0)[0]
+    top = (fib.prefixes[:, 0] >> U64(32)).astype(np.uint32)
+    for s in range(0, n, chunk):
+        c = min(chunk, n - s)
+        blk = rng.integers(0, 1 << 32, size=c, dtype=np.uint64).astype(np.uint32)
+        inside = rng.random(c) < inside_share
+        k = int(inside.sum())
+        if k and cand.size:
+            idx = cand[rng.integers(0, cand.size, size=k)]
+            host = (np.uint64(1) << (32 - fib.lengths[idx].astype(np.uint64))) - np.uint64(1)
+            blk[inside] = top[idx] | (blk[inside] & host.astype(np.uint32))
+        out[s:s + c] = blk
+    return out
+
+
+def v4_as_128(addrs: np.ndarray) -> np.ndarray:
+    """32-bit addresses as the (n, 2) uint64 records of the 128-bit space (a << 96)."""
+    out = np.zeros((addrs.shape[0], 2), dtype=U64)
+    out[:, 0] = addrs.astype(U64) << U64(32)
+    return out
 
 
 def log_uniform_sizes(rng, n: int, lo: int, hi: int) -> np.ndarray:

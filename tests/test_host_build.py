@@ -278,20 +278,27 @@ def test_descent_with_top_key_equal_to_sentinel():
 # (keys, slots) per leaf of a FIB's device image, written out per key width and
 # fanout: 64-bit slots: 32-byte blocks of 3 keys + their 3 next hops; 128-bit
 # slots: the keys, then their next hops.
-LEAF_SHAPE = {(64, 8): (12, 16), (64, 16): (12, 16), (64, 32): (24, 32),
+LEAF_SHAPE = {(32, 8): (20, 32), (32, 16): (20, 32), (32, 32): (20, 32),
+              (64, 8): (12, 16), (64, 16): (12, 16), (64, 32): (24, 32),
               (128, 8): (7, 8), (128, 16): (14, 16), (128, 32): (28, 32)}
 
 
 def _leaf_key_off(s, kbits, L):
+    if kbits == 32:  # 32-byte blocks of five keys, then their five hops
+        return (s // 5) * 32 + (s % 5) * 4
     return (s // 3) * 32 + (s % 3) * 8 if kbits == 64 else 16 * s
 
 
 def _leaf_hop_off(s, kbits, L):
+    if kbits == 32:
+        return (s // 5) * 32 + 20 + (s % 5) * 2
     return (s // 3) * 32 + 24 + (s % 3) * 2 if kbits == 64 else 16 * L + 2 * s
 
 
 def _slot_key(img, slot, kbits):
-    """Key in a slot of the image as a 128-bit integer (64-bit slots hold the high word)."""
+    """Key in a slot of the image as a 128-bit integer (narrow slots hold the top bits)."""
+    if kbits == 32:
+        return int.from_bytes(img[4 * slot:4 * slot + 4].tobytes(), "little") << 96
     if kbits == 64:
         return int.from_bytes(img[8 * slot:8 * slot + 8].tobytes(), "little") << 64
     hi = int.from_bytes(img[16 * slot:16 * slot + 8].tobytes(), "little")
@@ -305,7 +312,7 @@ def _image_lookup(img, info, x):
     off, nodes = info["level_offset"], info["level_nodes"]
     L, LS, base = info["leaf_keys"], info["leaf_slots"], info["leaf_base"]
     kb = kbits // 8
-    xk = x if kbits == 128 else (x >> 64) << 64  # 64-bit keys compare the high word
+    xk = x if kbits == 128 else (x >> (128 - kbits)) << (128 - kbits)  # narrow keys compare the top bits
     q = 0
     for l in range(D - 1):
         c = sum(1 for s in range(b) if _slot_key(img, (off[l] + q) * b + s, kbits) <= xk)
@@ -320,6 +327,8 @@ def _image_lookup(img, info, x):
 
 
 def _key_at(img, byte, kbits):
+    if kbits == 32:
+        return int.from_bytes(img[byte:byte + 4].tobytes(), "little") << 96
     if kbits == 64:
         return int.from_bytes(img[byte:byte + 8].tobytes(), "little") << 64
     return (int.from_bytes(img[byte:byte + 8].tobytes(), "little") << 64 |
@@ -327,16 +336,20 @@ def _key_at(img, byte, kbits):
 
 
 @pytest.mark.parametrize("b", [8, 16, 32])
-@pytest.mark.parametrize("kbits", [64, 128])
-@pytest.mark.parametrize("m", [1, 2, 11, 12, 13, 25, 700, 5000])
+@pytest.mark.parametrize("kbits", [32, 64, 128])
+@pytest.mark.parametrize("m", [1, 2, 11, 12, 13, 19, 20, 21, 25, 700, 5000])
 def test_device_image_structure_and_descent(b, kbits, m):
     rng = np.random.default_rng(7 * m + b + kbits)
-    his = sorted(set(int(v) for v in rng.integers(1, 2**63, size=m - 1)) | {0})
+    top = 31 if kbits == 32 else 63
+    his = sorted(set(int(v) for v in rng.integers(1, 2**top, size=m - 1)) | {0})
     while len(his) < m:
         his.append(his[-1] + 1)
     his = his[:m]
-    lo_mask = 0 if kbits == 64 else 0xFFFF
-    vals = [h << 64 | (h * 13 & lo_mask) for h in his]
+    if kbits == 32:
+        vals = [h << 96 for h in his]
+    else:
+        lo_mask = 0 if kbits == 64 else 0xFFFF
+        vals = [h << 64 | (h * 13 & lo_mask) for h in his]
     vals[0] = 0
     nh = rng.integers(0, 0xFFFF, size=m).astype(np.uint16)
     img, info = P.planb_build_image(S.from_ints(vals), nh, b, kbits)
@@ -370,14 +383,35 @@ def test_device_image_key_width_choice():
     _, info = P.planb_build_image(S.from_ints(vals), nh, 8, 0)
     assert info["key_bits"] == 128  # a start with a nonzero low word
     _, info = P.planb_build_image(S.from_ints(vals[:2]), nh[:2], 8, 0)
-    assert info["key_bits"] == 64
+    assert info["key_bits"] == 64  # nonzero bits below the top 32
+    _, info = P.planb_build_image(S.from_ints([0, 5 << 96]), nh[:2], 8, 0)
+    assert info["key_bits"] == 32  # only the top 32 bits are ever nonzero
+    for kb in (64, 128):
+        _, info = P.planb_build_image(S.from_ints([0, 5 << 96]), nh[:2], 8, kb)
+        assert info["key_bits"] == kb
     with pytest.raises(P.PlanbError):
         P.planb_build_image(S.from_ints(vals), nh, 8, 64)
+    with pytest.raises(P.PlanbError):
+        P.planb_build_image(S.from_ints(vals[:2]), nh[:2], 8, 32)
     with pytest.raises(P.PlanbError):
         P.planb_build_image(S.from_ints([1, 2]), nh[:2], 8, 0)  # starts[0] must be 0
 
 
 # ------------------------------------------------------------- CPU baseline
+@pytest.mark.parametrize("b", [8, 16, 32])
+@pytest.mark.parametrize("key_bits", [0, 128])
+def test_cpu_btree_baseline_ipv4(b, key_bits):
+    """The CPU baseline on an IPv4 FIB (32-bit key slots when automatic)."""
+    from oracle.trie import Trie
+    fib = S.make_fib(S.IPV4_TINY, 40 + b)
+    a4 = S.ipv4_traffic(fib, 20000, 0.7, 3 + b)
+    addrs = np.concatenate([S.v4_as_128(a4), S.from_ints([0, (1 << 128) - 1, 0xFFFFFFFF << 96])])
+    tree = P.CpuTree(fib.prefixes, fib.lengths, fib.next_hops, fanout=b, key_bits=key_bits)
+    assert tree.shape["key_bits"] == (key_bits or 32)
+    want = Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(addrs)
+    assert np.array_equal(tree.lookup(addrs, 2), want)
+
+
 @pytest.mark.parametrize("b", [8, 16, 32])
 @pytest.mark.parametrize("key_bits", [0, 128])
 def test_cpu_btree_baseline_matches_oracle(b, key_bits):
