@@ -93,7 +93,9 @@ typedef struct planb_params {
  * of a fanout-b tree whose internal separators are the minima of the child
  * subtrees.  The inputs are copied; the caller keeps ownership.
  * Errors: NULL with PLANB_EINVAL (length > 128, next hop 0xFFFF, NULL array
- * with n > 0), PLANB_EDUP, PLANB_ENOMEM, PLANB_EDEVICE.
+ * with n > 0), PLANB_EDUP, PLANB_ENOMEM, PLANB_EDEVICE, PLANB_ERANGE (2^31 or
+ * more intervals, or a slot array of 4 GiB or more: the kernels address it
+ * with 32-bit byte offsets).
  */
 planb_fib_t* planb_build(const planb_addr_t* prefixes, const uint8_t* lengths,
                          const uint16_t* next_hops, size_t n);

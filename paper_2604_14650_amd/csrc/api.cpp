@@ -111,8 +111,15 @@ uint32_t default_kpl(uint32_t b) { return b == 8 ? 2 : b == 16 ? 4 : 8; }
 
 int plan_fib_layout(uint64_t m, uint32_t fanout, int key_bytes, Layout* lay, std::string* err)
 {
-    return plan_layout(m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, key_bytes),
-                       (uint32_t)leaf_slots_for((int)fanout, key_bytes), true, lay, err);
+    const int rc = plan_layout(m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, key_bytes),
+                               (uint32_t)leaf_slots_for((int)fanout, key_bytes), true, lay, err);
+    // the kernels address the slot array with 32-bit byte offsets
+    if (rc == 0 && lay->total_slots() * (uint64_t)key_bytes > UINT32_MAX) {
+        *err = "tree image of " + std::to_string(lay->total_slots() * (uint64_t)key_bytes) +
+               " bytes: the slot array must stay below 4 GiB";
+        return -5;
+    }
+    return rc;
 }
 
 // The device slot array of a FIB: the keys of fill_keys in key_bytes-wide

@@ -11,6 +11,8 @@
 // (all ones in the compared width); that address's answer is the last interval.
 #pragma once
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace planb {
@@ -83,8 +85,19 @@ struct Descent {
 
     // Keys <= x in the node whose first slot is keys[node0], summed over the
     // lookup's G lanes (lane j of the group is `j`).
+    // Slot indexes of the global levels.  With 64-bit keys they are 32-bit
+    // and address the array by a 32-bit byte offset from its (uniform) base:
+    // the slot array stays below 4 GiB.  For the other widths the 64-bit
+    // form measured faster.
+    using SlotIdx = std::conditional_t<KB == 8, uint32_t, uint64_t>;
+    static __device__ __forceinline__ const K* slot_ptr(const K* keys, SlotIdx slot)
+    {
+        if constexpr (KB != 8) return keys + slot;
+        else return reinterpret_cast<const K*>(reinterpret_cast<const char*>(keys) + slot * (uint32_t)sizeof(K));
+    }
+
     template <bool FROM_LDS>
-    static __device__ __forceinline__ uint32_t node_count(const K* keys, size_t node0, int j, uint64_t xhi,
+    static __device__ __forceinline__ uint32_t node_count(const K* keys, SlotIdx node0, int j, uint64_t xhi,
                                                           uint64_t xlo)
     {
         if constexpr (BIN && FROM_LDS && KPL == B) {
@@ -104,14 +117,15 @@ struct Descent {
             // full-width loads, so a group covers its node with few loads
             constexpr int NW = KPL * KB / 4;
             uint32_t w[NW];
-            load_words<NW>(keys + node0 + (size_t)j * KPL, w);
+            load_words<NW>(slot_ptr(keys, node0 + (SlotIdx)(j * KPL)), w);
 #pragma unroll
             for (int s = 0; s < KPL; ++s) cnt += word_key_le(w, s, xhi);
         } else {
             // 16-byte keys (or one 4-byte key per lane): key s*G + j, so one
             // load instruction covers G consecutive keys of each group's node
+            const K* p = slot_ptr(keys, node0 + (SlotIdx)j);  // constant strides fold into the loads
 #pragma unroll
-            for (int s = 0; s < KPL; ++s) cnt += KF::le(keys[node0 + s * G + j], xhi, xlo);
+            for (int s = 0; s < KPL; ++s) cnt += KF::le(p[s * G], xhi, xlo);
         }
         return (uint32_t)group_sum<G>(cnt);
     }
@@ -151,14 +165,15 @@ struct Descent {
         uint32_t w[kW];
     };
 
-    static __device__ __forceinline__ void leaf_load(const K* keys, size_t node0, int j, LeafWords& L)
+    static __device__ __forceinline__ void leaf_load(const K* keys, SlotIdx node0, int j, LeafWords& L)
     {
         if constexpr (kContig) {
-            load_words<kW>(keys + node0 + (size_t)j * kLPER, L.w);
+            load_words<kW>(slot_ptr(keys, node0 + (SlotIdx)(j * kLPER)), L.w);
         } else {
+            const K* p = slot_ptr(keys, node0 + (SlotIdx)j);
 #pragma unroll
             for (int s = 0; s < kLPER; ++s) {
-                const K k = keys[node0 + s * G + j];
+                const K k = p[s * G];
                 if constexpr (WIDE) {  // uint4: the key's four words in memory order
                     L.w[4 * s] = k.x;
                     L.w[4 * s + 1] = k.y;
@@ -213,7 +228,35 @@ struct Descent {
         return (uint16_t)(sel >> (8 * (byte & 2)));
     }
 
-    // NR lookups' leaves by lane groups: all loads first, then the searches
+    // Each lane holds exactly one block of the blocked leaf format (64-bit
+    // keys, 32 bytes per lane): its keys and their next hops.  (With 32-bit
+    // keys the same pick measured slower than the generic one, and is off.)
+    static constexpr bool kBlockLane = kContig && kLPER * kb == 32 && kb == 8;
+    static constexpr uint32_t kBlockKeys = kb == 8 ? 3 : 5;   // keys per block
+    static constexpr uint32_t kBlockHop0 = kb == 8 ? 24 : 20;  // byte of the block's first next hop
+
+    // Next hop (low 16 bits) of the lane's own block for its key cl - 1, cl in
+    // 1..kBlockKeys (cl = 0 gives an unused value).  A byte permute of the
+    // word pair holding the hops takes bytes 2(cl-1) and 2(cl-1)+1 of it and
+    // zeroes the rest; with 32-bit keys the fifth hop is in the next word.
+    static __device__ __forceinline__ uint32_t block_hop(const LeafWords& L, uint32_t cl)
+    {
+        constexpr int w0 = kBlockHop0 / 4;
+        const uint32_t pick = __builtin_amdgcn_perm(L.w[w0 + 1], L.w[w0], cl * 0x202u + (0x0c0c0100u - 0x202u));
+        if constexpr (kb == 8) return pick;
+        else return cl == 5 ? L.w[w0 + 2] : pick;
+    }
+
+    // Whether x is all ones in the key width: it then counts the sentinel
+    // padding of the last leaf too, and its interval is the last one.
+    static __device__ __forceinline__ bool key_all_ones(uint64_t xhi, uint64_t xlo)
+    {
+        if constexpr (KB == 16) return (xhi & xlo) == ~0ull;
+        else if constexpr (KB == 8) return xhi == ~0ull;
+        else return (uint32_t)(xhi >> 32) == ~0u;
+    }
+
+    // NR lookups' leaves by lane groups: all loads first, then the searches.
     template <int NR>
     static __device__ __forceinline__ void leaf_groups(const TreeDesc& t, const K* keys, const uint32_t* q,
                                                        const uint64_t* xh, const uint64_t* xl, int j, int lane0,
@@ -221,12 +264,41 @@ struct Descent {
     {
         LeafWords L[NR];
 #pragma unroll
-        for (int u = 0; u < NR; ++u) leaf_load(keys, t.leaf_base + (size_t)q[u] * kLS, j, L[u]);
+        for (int u = 0; u < NR; ++u) leaf_load(keys, t.leaf_base + (SlotIdx)q[u] * kLS, j, L[u]);
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const uint32_t c = (uint32_t)group_sum<G>(leaf_lane_count(L[u], j, xh[u], xl[u]));
             idx[u] = leaf_index(t, q[u], c);
             hop[u] = leaf_pick_hop(L[u], idx[u] - q[u] * (uint32_t)kLC, lane0);
+        }
+    }
+
+    // The same when every lane holds one block (kBlockLane); res[u] is the
+    // interval index (index_out) or the next hop.
+    template <int NR>
+    static __device__ __forceinline__ void leaf_blocks(const TreeDesc& t, const K* keys, const uint32_t* q,
+                                                       const uint64_t* xh, const uint64_t* xl, int j, int lane0,
+                                                       int index_out, uint32_t* res)
+    {
+        LeafWords L[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) leaf_load(keys, t.leaf_base + (SlotIdx)q[u] * kLS, j, L[u]);
+        // The keys <= x are a prefix of the leaf's keys (unless x is all ones
+        // in the key width): the lanes before the last one holding such a key
+        // have all of theirs <= x, so that lane is the count of lanes with any,
+        // minus one, and its own count picks the hop in its block.  One group
+        // sum adds both counts: keys in the low byte, lanes above it.
+        const uint16_t last_hop = t.vals[t.m_minus_1];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const uint32_t cl = (uint32_t)leaf_lane_count(L[u], j, xh[u], xl[u]);
+            const uint32_t sum = (uint32_t)group_sum<G>((int)(cl + (min(cl, 1u) << 8)));
+            const uint32_t lanes = sum >> 8;  // >= 1: the leaf's first key is <= x
+            // the upper 16 bits of the hop are not part of it (hops are uint16)
+            const uint32_t got =
+                (uint32_t)__builtin_amdgcn_ds_bpermute((lane0 + (int)lanes - 1) << 2, (int)block_hop(L[u], cl));
+            const uint32_t hop = key_all_ones(xh[u], xl[u]) ? last_hop : got;
+            res[u] = index_out ? leaf_index(t, q[u], sum & 0xFFu) : hop;
         }
     }
 
@@ -335,11 +407,18 @@ struct Descent {
             const uint32_t off = t.off[l], lim = t.last[l + 1];
 #pragma unroll
             for (int u = 0; u < T; ++u)
-                p[u] = min(p[u] * B + node_count<false>(gkeys, (size_t)(off + p[u]) * B, j, yh[u], yl[u]), lim);
+                p[u] = min(p[u] * B + node_count<false>(gkeys, (SlotIdx)(off + p[u]) * B, j, yh[u], yl[u]), lim);
         }
-        uint32_t idx[T];
-        uint16_t hop[T];
-        leaf_groups<T>(t, gkeys, p, yh, yl, j, lane - j, idx, hop);
+        uint32_t res[T];
+        if constexpr (kBlockLane) {
+            leaf_blocks<T>(t, gkeys, p, yh, yl, j, lane - j, index_out, res);
+        } else {
+            uint32_t idx[T];
+            uint16_t hop[T];
+            leaf_groups<T>(t, gkeys, p, yh, yl, j, lane - j, idx, hop);
+#pragma unroll
+            for (int u = 0; u < T; ++u) res[u] = index_out ? idx[u] : hop[u];
+        }
         // hand every result back to the lane that owns its lookup, so each of
         // the R stores writes 64 consecutive results: owner lane L's lookup r
         // was round r*G + L/LPW, computed by group L%LPW
@@ -349,7 +428,7 @@ struct Descent {
             uint32_t v = 0;
 #pragma unroll
             for (int k = 0; k < G; ++k) {
-                const uint32_t got = (uint32_t)__shfl((int)(index_out ? idx[r * G + k] : hop[r * G + k]), src, 64);
+                const uint32_t got = (uint32_t)__shfl((int)res[r * G + k], src, 64);
                 v = k == g ? got : v;
             }
             const uint64_t i = base + (uint64_t)r * 64 + lane;
@@ -384,12 +463,25 @@ struct Descent {
             if (l < t.lds_levels) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    q[r] = min(q[r] * B + node_count<true>(lds_keys, (size_t)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
+                    q[r] = min(q[r] * B + node_count<true>(lds_keys, (SlotIdx)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    q[r] = min(q[r] * B + node_count<false>(gkeys, (size_t)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
+                    q[r] = min(q[r] * B + node_count<false>(gkeys, (SlotIdx)(off + q[r]) * B, j, xhi[r], xlo[r]), lim);
             }
+        }
+        if constexpr (kBlockLane) {
+            uint32_t res[R];
+            if (t.lds_levels < t.depth)
+                leaf_blocks<R>(t, gkeys, q, xhi, xlo, j, lane - j, index_out, res);
+            else
+                leaf_blocks<R>(t, lds_keys, q, xhi, xlo, j, lane - j, index_out, res);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t i = base + (uint64_t)r * LPW + grp;
+                if (j == 0 && i < n) store(out, index_out, i, res[r], (uint16_t)res[r]);
+            }
+            return;
         }
         uint32_t idx[R];
         uint16_t hop[R];

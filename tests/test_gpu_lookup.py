@@ -273,3 +273,45 @@ def test_bsearch_baseline_tiny_and_backbone(P, tiny, key_bits):
     out = out_u16(a.shape[0])
     P.planb_lookup_bsearch(h, to_dev(a), a.shape[0], out)
     assert np.array_equal(host_u16(out, a.shape[0]), oracle_trie("backbone", 22).lookup(a))
+
+
+@pytest.mark.parametrize("with_top_rule", [False, True])
+def test_top_of_space_narrow_keys(P, with_top_rule):
+    """64-bit key slots: an address whose high word is all ones counts the
+    sentinel padding of the last leaf too.  With a rule starting at
+    ffff:ffff:ffff:ffff:: a real key equals the sentinel as well.  Both the
+    next hop and the interval index must still be those of the last interval
+    at or below the address."""
+    import torch
+    H = (1 << 64) - 1
+    rules = [(0, 0, 1), (0xFFFF << 112, 16, 2), (0x2001 << 112, 16, 5), ((H - 1) << 64, 64, 4)]
+    if with_top_rule:
+        rules.append((H << 64, 64, 3))
+    p = S.from_ints([r[0] for r in rules])
+    L = np.array([r[1] for r in rules], np.uint8)
+    nh = np.array([r[2] for r in rules], np.uint16)
+    rng = np.random.default_rng(21)
+    his = [H, H - 1, H - 2, 0xFFFF << 48, (0xFFFF << 48) - 1, 0x2001 << 48, 0]
+    los = [0, 1, H, H - 1] + [int(v) for v in rng.integers(0, 2**63, size=4)]
+    q = S.from_ints(sorted({h << 64 | lo for h in his for lo in los}))
+    want = lpm_bruteforce(p, L, nh, q)
+    for fanout, kpl in ((8, 2), (16, 4), (32, 8), (8, 1), (16, 16)):
+        h = P.planb_build(p, L, nh, fanout=fanout)
+        assert P.planb_get_info(h)["key_bits"] == 64
+        starts, ivnh = P.planb_export_intervals(h)
+        depth = P.planb_get_info(h)["depth"]
+        for lds, R, bin_ in ((0, 2, 0), (-1, 1, 0), (max(0, depth - 1), 2, 1), (depth, 2, 1)):
+            say(f"top of space narrow fanout={fanout} kpl={kpl} lds={lds} R={R} bin={bin_} top={with_top_rule}")
+            try:
+                P.planb_set_tuning(h, kpl, lds, R, 512, bin_)
+            except P.PlanbError:
+                continue  # binary search needs fanout / keys_per_lane in {1, 2, 4}
+            out = out_u16(q.shape[0])
+            P.planb_lookup(h, to_dev(q), q.shape[0], out)
+            assert np.array_equal(host_u16(out, q.shape[0]), want)
+            idx = torch.full((q.shape[0],), -1, dtype=torch.int32, device="cuda")
+            P.planb_lookup_index(h, to_dev(q), q.shape[0], idx)
+            i = idx.cpu().numpy().astype(np.int64)
+            assert np.array_equal(ivnh[i], want)
+            # the interval is the last one whose start (high word) is <= the address's
+            assert np.array_equal(i, np.searchsorted(starts[:, 0], q[:, 0], side="right") - 1)
