@@ -118,7 +118,7 @@ def measured_traffic(per_launch_lookups: int, config: str):
 
 
 # Launch shapes the autotuner chose for this workload on MI355X (used with --no-autotune).
-KNOWN_TUNING = {0: {"fanout": 8, "tuning": (2, 5, 2, 512, 1)}, 128: {"fanout": 8, "tuning": (4, 5, 1, 1024, 1)}}
+KNOWN_TUNING = {0: {"fanout": 8, "tuning": (2, 5, 2, 1024, 2)}, 128: {"fanout": 8, "tuning": (4, 5, 1, 1024, 1)}}
 
 
 def plain_leg(P, fib, d, n, out, args):
@@ -275,9 +275,11 @@ def ablation_leg(P, fib, d, n, out, got, steps=3):
     """The design ladder on the headline FIB and batch (the GPU analogue of the
     paper's Section 4 ablation): binary search over the sorted starts, then
     the tree with one lane per lookup and no LDS, lane groups per lookup,
-    LDS-staged top levels, binary search by one lane in the LDS levels (the
-    headline shape), and the persistent kernel replayed from a graph.  Every
-    rung's output is checked against the headline result."""
+    LDS-staged top levels, binary search by one lane in the LDS levels, the
+    bottom internal level in LDS as 32-bit key tops (the headline shape), and
+    the persistent kernel replayed from a graph (which stages whole keys, as
+    the rung before the headline).  Every rung's output is checked against
+    the headline result."""
     import torch
     rungs = []
     h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
@@ -295,12 +297,15 @@ def ablation_leg(P, fib, d, n, out, got, steps=3):
     for name, tu in (("tree, one lane per lookup, no LDS", (8, 0, 2, 512, 0)),
                      ("tree, 4 lanes per lookup, no LDS", (2, 0, 2, 512, 0)),
                      ("+ top 5 levels in LDS", (2, 5, 2, 512, 0)),
-                     ("+ one-lane binary search in the LDS levels (headline)", (2, 5, 2, 512, 1))):
+                     ("+ one-lane binary search in the LDS levels", (2, 5, 2, 512, 1)),
+                     ("+ bottom internal level in LDS as 32-bit key tops (headline)", (2, 5, 2, 1024, 2))):
         P.planb_set_tuning(h, *tu)
         timed(name, lambda: P.planb_lookup(h, d, n, o), dict(zip(("keys_per_lane", "lds_levels", "lookups_per_group",
                                                                    "block_threads", "lds_search"), tu)))
+    P.planb_set_tuning(h, 2, 5, 2, 512, 1)
     g = P.Graph(h, 4)
-    timed("persistent kernel, graph replay, one batch", lambda: g.launch([(d, o, n)]), "headline shape")
+    timed("persistent kernel, graph replay, one batch", lambda: g.launch([(d, o, n)]),
+          "whole keys in the top 5 LDS levels (lds_search 1)")
     g.close()
     return rungs
 

@@ -227,7 +227,17 @@ int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
  *                      1: in the LDS-staged levels every lane walks its own
  *                      lookups by binary search inside the nodes; the lower
  *                      levels are then shared by fanout/keys_per_lane lanes
- *                      (1, 2 or 4), which take the lookups over by shuffles
+ *                      (1, 2 or 4), which take the lookups over by shuffles;
+ *                      2 (64-bit key slots; fanout/keys_per_lane 2 or 4): as 1,
+ *                      but planb_lookup and planb_lookup_index stage every
+ *                      internal level in LDS (ignoring lds_levels): the bottom
+ *                      one as the top 32 bits of each key, the levels above it
+ *                      whole, so that only the leaf is read from device memory;
+ *                      a lookup whose address ties a bottom key's top half
+ *                      re-reads that node whole.  Results are unchanged.  The other lookup paths (batches,
+ *                      graphs, many FIBs, IPv4) run this tuning as 1 with
+ *                      lds_levels.  PLANB_ERANGE when those tops exceed a
+ *                      workgroup's LDS.
  */
 typedef struct planb_tuning {
     uint32_t keys_per_lane;

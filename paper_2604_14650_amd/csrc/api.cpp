@@ -63,13 +63,25 @@ void refresh_desc(planb_fib_t* f)
 int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning* out, int32_t* lds_out)
 {
     const uint32_t b = f->lay.b, kpl = tu.keys_per_lane, R = tu.lookups_per_group, bs = tu.block_threads;
-    const bool bin = tu.lds_search != 0;
+    const bool bin = tu.lds_search != 0, tops = tu.lds_search == 2;
     if (kpl == 0 || (kpl & (kpl - 1)) || b % kpl || b / kpl > 32 || (bs != 512 && bs != 1024) ||
-        tu.lds_search > 1 || (bin && kpl != b && b / kpl != 2 && b / kpl != 4) ||
+        tu.lds_search > 2 || (bin && kpl != b && b / kpl != 2 && b / kpl != 4) ||
         !lookup_variant_exists((int)b, (int)kpl, (int)R, (int)bs, bin))
         return fail(PLANB_EINVAL, "unsupported tuning: keys_per_lane " + std::to_string(kpl) +
                                       ", lookups_per_group " + std::to_string(R) + ", block_threads " +
                                       std::to_string(bs) + " for fanout " + std::to_string(b));
+    if (tops) {
+        if (f->key_bytes_per_slot != 8 || kpl == b || !lookup_tops_variant_exists((int)b, (int)kpl, (int)R, (int)bs))
+            return fail(PLANB_EINVAL, "lds_search 2 needs 64-bit key slots and fanout / keys_per_lane of 2 or 4");
+        // exact levels above the bottom internal one, then that level's key tops (b - 1 per node)
+        const uint32_t D = f->lay.depth;
+        const size_t tb = D < 2 ? 0
+                                : f->lay.prefix_slots(D - 2) * (size_t)8 +
+                                      (size_t)f->lay.nodes[D - 2] * (b - 1) * 4;
+        if (tb > (size_t)max_lds_bytes())
+            return fail(PLANB_ERANGE, "the internal levels with the bottom one as key tops need " + std::to_string(tb) +
+                                          " bytes of LDS, more than a workgroup may allocate");
+    }
     int32_t lds_levels = tu.lds_levels;
     if (lds_levels < 0) lds_levels = deepest_lds_levels(f->lay, f->key_bytes_per_slot, 64 * 1024);
     if (lds_levels > (int32_t)f->lay.depth) return fail(PLANB_EINVAL, "lds_levels exceeds the tree depth");
@@ -81,6 +93,7 @@ int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning
     out->R = (int)R;
     out->block = (int)bs;
     out->bin = bin;
+    out->tops = tops;
     *lds_out = lds_levels;
     return PLANB_OK;
 }
@@ -505,7 +518,7 @@ int planb_get_tuning(const planb_fib_t* fib, planb_tuning_t* tuning)
     tuning->lds_levels = fib->lds_levels;
     tuning->lookups_per_group = (uint32_t)fib->tune.R;
     tuning->block_threads = (uint32_t)fib->tune.block;
-    tuning->lds_search = fib->tune.bin ? 1u : 0u;
+    tuning->lds_search = fib->tune.tops ? 2u : fib->tune.bin ? 1u : 0u;
     return PLANB_OK;
 }
 

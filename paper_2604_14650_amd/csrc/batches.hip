@@ -263,6 +263,11 @@ int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint3
                 for (uint32_t bs : {512u, 1024u})
                     for (int lds = std::max(0, deepest - 2); lds <= deepest; ++lds)
                         cands.push_back(planb_tuning_t{kpl, lds, R, bs, bin});
+        // the bottom internal level as key tops (64-bit key slots; skipped by
+        // planb_set_tuning when the levels do not fit a workgroup's LDS)
+        if (fib->key_bytes_per_slot == 8 && (b / kpl == 2 || b / kpl == 4))
+            for (uint32_t R : {1u, 2u, 4u})
+                for (uint32_t bs : {512u, 1024u}) cands.push_back(planb_tuning_t{kpl, deepest, R, bs, 2u});
     }
     uint16_t* out = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -44,6 +44,30 @@ struct Descent {
         for (uint32_t i = tid; i < units; i += nthreads) lds_raw[i] = src[i];
     }
 
+    // The bottom internal level (level t.depth - 2) in LDS as the top 32 bits
+    // of each of its keys, B - 1 per node (the sentinel slot is never
+    // probed), after the t.lds_slots exact slots of the levels above: 4 bytes
+    // per key instead of 8, so that this level fits beside them.
+    static __device__ __forceinline__ uint32_t bottom_level(const TreeDesc& t) { return t.depth - 2; }
+    static __device__ __forceinline__ uint32_t* bottom_tops(const void* lds, const TreeDesc& t)
+    {
+        return reinterpret_cast<uint32_t*>(const_cast<char*>(static_cast<const char*>(lds)) + (size_t)t.lds_slots * sizeof(K));
+    }
+    static __device__ void stage_bottom_tops(const TreeDesc& t, uint4* lds_raw, int tid, int nthreads)
+    {
+        static_assert(KB == 8, "key tops are defined for 64-bit key slots");
+        stage(t, lds_raw, tid, nthreads);
+        if (t.depth < 2) return;
+        const uint32_t lvl = bottom_level(t);
+        const uint32_t keys = (t.off[lvl + 1] - t.off[lvl]) * (uint32_t)(B - 1);
+        const uint32_t* src = static_cast<const uint32_t*>(t.keys);  // the high word of key i is word 2i + 1
+        uint32_t* tops = bottom_tops(lds_raw, t);
+        for (uint32_t i = tid; i < keys; i += nthreads) {
+            const uint32_t node = i / (uint32_t)(B - 1), s = i - node * (uint32_t)(B - 1);
+            tops[i] = src[2 * ((t.off[lvl] + node) * (uint32_t)B + s) + 1];
+        }
+    }
+
     // NW consecutive 32-bit words at p, with the widest loads their alignment
     // allows (p is aligned to NW * 4 bytes, or to 16 when NW is a multiple of 4).
     template <int NW>
@@ -328,6 +352,44 @@ struct Descent {
         return c;
     }
 
+    // The bottom internal level from its key tops, one lane per lookup: a
+    // binary search on the tops, where a key whose top half is below x's is
+    // <= x and one above is not.  A tie leaves the key open, so the search
+    // counts it as <= x and notes it; afterwards every lookup that met a tie
+    // recounts its node from the whole keys in device memory (one load round
+    // for the wavefront, taken by the tied lanes only).
+    static __device__ __forceinline__ void bottom_step(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
+                                                       uint32_t* q)
+    {
+        const uint32_t lvl = bottom_level(t), off = t.off[lvl], lim = t.last[lvl + 1];
+        uint32_t c[R];
+        bool tie[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
+            c[r] = 0;
+            tie[r] = false;
+#pragma unroll
+            for (int step = B / 2; step >= 1; step >>= 1) {
+                const uint32_t v = tops[n0 + c[r] + (uint32_t)(step - 1)];
+                tie[r] |= v == tx;
+                c[r] += v <= tx ? (uint32_t)step : 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (tie[r]) {
+                const K* node = slot_ptr(static_cast<const K*>(t.keys), (off + q[r]) * (uint32_t)B);
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int s = 0; s < B - 1; ++s) cnt += node[s] <= xh[r] ? 1u : 0u;
+                c[r] = cnt;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) q[r] = min(q[r] * B + c[r], lim);
+    }
+
     static __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
     {
         const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
@@ -357,10 +419,13 @@ struct Descent {
         lo = 0;
     }
 
-    template <typename A>
-    static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const K* lds_keys, const A* addrs,
+    // TOPS: lds holds the key tops of every internal level (stage_tops);
+    // else the first t.lds_levels levels' keys (stage).
+    template <typename A, bool TOPS = false>
+    static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const void* lds, const A* addrs,
                                                        uint64_t base, uint64_t n, void* out, int index_out)
     {
+        const K* lds_keys = static_cast<const K*>(lds);  // with TOPS: the exact levels above the bottom one
         const int lane = threadIdx.x & 63;
         uint64_t xh[R], xl[R];
         uint32_t q[R];
@@ -371,14 +436,20 @@ struct Descent {
             q[r] = 0;
         }
         // LDS-staged levels, one lane per lookup
-        const uint32_t lds_internal = t.lds_levels < t.depth - 1 ? t.lds_levels : t.depth - 1;
+        uint32_t lds_internal = t.lds_levels < t.depth - 1 ? t.lds_levels : t.depth - 1;
         for (uint32_t l = 0; l < lds_internal; ++l) {
             const uint32_t off = t.off[l], lim = t.last[l + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 q[r] = min(q[r] * B + lane_bincount<true>(lds_keys, (size_t)(off + q[r]) * B, xh[r], xl[r]), lim);
         }
-        if (t.lds_levels >= t.depth) {  // the whole tree is in LDS
+        if constexpr (TOPS) {  // lds_levels = depth - 2: the bottom internal level from its tops
+            if (t.depth >= 2) {
+                bottom_step(t, bottom_tops(lds, t), xh, q);
+                lds_internal = t.depth - 1;
+            }
+        }
+        if (!TOPS && t.lds_levels >= t.depth) {  // the whole tree is in LDS
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 uint32_t idx;

@@ -59,6 +59,26 @@ lookup_v4_kernel(TreeDesc t, const uint32_t* __restrict__ addrs, uint64_t n, voi
         D::step(t, lds_keys, addrs, base, n, out, index_out);
 }
 
+// Hybrid descent with the bottom internal level in LDS too, as the top 32
+// bits of its 64-bit keys (half the bytes: for trees like the 200k-prefix
+// backbone table that level then fits beside the exact levels above it, and
+// a lookup's only tree access outside the CU is its leaf, unless its address
+// ties a key's top half; then its lane re-reads that node whole).  Results
+// are those of lookup_kernel.
+template <int B, int KPL, int R, int BS>
+__global__ void __launch_bounds__(BS)
+lookup_tops_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
+{
+    using D = Descent<B, KPL, R, 8, true>;
+    extern __shared__ uint4 lds_raw[];
+    D::stage_bottom_tops(t, lds_raw, threadIdx.x, BS);
+    __syncthreads();
+    const uint64_t wave = (uint64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (BS / 64);
+    for (uint64_t base = wave * D::kStep; base < n; base += nwaves * D::kStep)
+        D::template step_hybrid<u64x2, true>(t, lds_raw, addrs, base, n, out, index_out);
+}
+
 // Binary search over the sorted interval starts, one lane per address: the
 // GPU analogue of the paper's std::lower_bound baseline (Section 4's
 // ablation), kept as the first rung of the design ladder.  Every probe is a
@@ -108,6 +128,28 @@ struct V4Kernel {  // instantiated for 32-bit key slots only
 KernelFn pick(int B, int kpl, int R, int kb, int bs, bool bin)
 {
     return VariantTable<PlainKernel>::pick(B, kpl, R, kb, bs, bin);
+}
+
+// Key-tops kernels: B in {8, 16, 32}, B / KPL in {2, 4}, R in {1, 2, 4}, BS in {512, 1024}.
+template <int B, int KPL>
+KernelFn pick_tops_r(int R, int bs)
+{
+    auto by_bs = [&](auto r) -> KernelFn {
+        constexpr int Rc = decltype(r)::value;
+        return bs == 512 ? lookup_tops_kernel<B, KPL, Rc, 512> : bs == 1024 ? lookup_tops_kernel<B, KPL, Rc, 1024> : nullptr;
+    };
+    return R == 1 ? by_bs(std::integral_constant<int, 1>{}) : R == 2 ? by_bs(std::integral_constant<int, 2>{})
+         : R == 4 ? by_bs(std::integral_constant<int, 4>{}) : nullptr;
+}
+
+KernelFn pick_tops(int B, int kpl, int R, int bs)
+{
+    if (kpl <= 0 || B % kpl) return nullptr;
+    const int G = B / kpl;
+    if (B == 8) return G == 2 ? pick_tops_r<8, 4>(R, bs) : G == 4 ? pick_tops_r<8, 2>(R, bs) : nullptr;
+    if (B == 16) return G == 2 ? pick_tops_r<16, 8>(R, bs) : G == 4 ? pick_tops_r<16, 4>(R, bs) : nullptr;
+    if (B == 32) return G == 2 ? pick_tops_r<32, 16>(R, bs) : G == 4 ? pick_tops_r<32, 8>(R, bs) : nullptr;
+    return nullptr;
 }
 
 std::mutex g_mu;
@@ -166,6 +208,8 @@ hipError_t occupancy(const void* fn, int bs, size_t lds, int* blocks)
 
 bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin) { return pick(B, kpl, R, 16, bs, bin) != nullptr; }
 
+bool lookup_tops_variant_exists(int B, int kpl, int R, int bs) { return pick_tops(B, kpl, R, bs) != nullptr; }
+
 int max_lds_bytes()
 {
     DevProps p;
@@ -218,16 +262,29 @@ hipError_t launch_lookup_v4(const TreeDesc& t, const LookupTuning& tu, const uin
     return hipGetLastError();
 }
 
-hipError_t launch_lookup(const TreeDesc& t, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
+hipError_t launch_lookup(const TreeDesc& td, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
                          bool index_out, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    KernelFn fn = pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
+    TreeDesc t = td;
+    KernelFn fn = nullptr;
+    size_t slot_bytes = t.key_bytes;
+    size_t extra = 0;
+    if (tu.tops) {
+        if (t.key_bytes != 8) return hipErrorInvalidValue;
+        // exact levels above the bottom internal one, then that level's key tops
+        t.lds_levels = t.depth >= 2 ? t.depth - 2 : 0;
+        t.lds_slots = t.off[t.lds_levels] * t.fanout;
+        if (t.depth >= 2) extra = (size_t)(t.off[t.depth - 1] - t.off[t.depth - 2]) * (t.fanout - 1) * 4;
+        fn = pick_tops((int)t.fanout, tu.kpl, tu.R, tu.block);
+    } else {
+        fn = pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
+    }
     if (!fn) return hipErrorInvalidValue;
     DevProps p;
     hipError_t e = dev_props(&p);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)t.lds_slots * t.key_bytes;
+    const size_t lds = (size_t)t.lds_slots * slot_bytes + extra;
     if (lds > (size_t)p.max_lds) return hipErrorInvalidValue;
     int nb = 1;
     if ((e = occupancy(reinterpret_cast<const void*>(fn), tu.block, lds, &nb)) != hipSuccess) return e;

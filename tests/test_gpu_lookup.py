@@ -315,3 +315,99 @@ def test_top_of_space_narrow_keys(P, with_top_rule):
             assert np.array_equal(ivnh[i], want)
             # the interval is the last one whose start (high word) is <= the address's
             assert np.array_equal(i, np.searchsorted(starts[:, 0], q[:, 0], side="right") - 1)
+
+
+TOPS_SHAPES = [(8, 2, 1), (8, 2, 2), (8, 4, 2), (8, 4, 4), (16, 4, 2), (16, 8, 1), (32, 8, 2), (32, 16, 4)]
+
+
+@pytest.mark.parametrize("fanout,kpl,R", TOPS_SHAPES)
+def test_key_tops_in_lds_tiny(P, tiny, fanout, kpl, R):
+    """lds_search 2: every internal level in LDS as 32-bit key tops, exact on
+    ties; next hops and interval indices equal the oracle's."""
+    import torch
+    fib, addrs, want = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    starts, ivnh = P.planb_export_intervals(h)
+    d = to_dev(addrs)
+    for block in (512, 1024):
+        say(f"tops tiny fanout={fanout} kpl={kpl} R={R} block={block}")
+        P.planb_set_tuning(h, kpl, -1, R, block, 2)
+        assert P.planb_get_tuning(h)["lds_search"] == 2
+        out = out_u16(addrs.shape[0])
+        P.planb_lookup(h, d, addrs.shape[0], out)
+        assert np.array_equal(host_u16(out, addrs.shape[0]), want)
+    n = 1 << 16
+    idx = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    P.planb_lookup_index(h, to_dev(addrs[:n]), n, idx)
+    i = idx.cpu().numpy().astype(np.int64)
+    assert np.array_equal(i, np.searchsorted(starts[:, 0], addrs[:n, 0], side="right") - 1)
+
+
+@pytest.mark.parametrize("fanout", [8, 16])
+def test_key_tops_in_lds_backbone(P, fanout):
+    """The backbone-shaped table: its addresses inside /48 prefixes often tie
+    a boundary's top 32 bits, so the exact re-read is exercised heavily."""
+    fib = fib_of("backbone", 22)
+    a = S.backbone_traffic(fib, 1 << 21, seed=77)
+    want = oracle_trie("backbone", 22).lookup(a)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    for kpl, R, block in ((fanout // 4, 2, 1024), (fanout // 2, 1, 512)):
+        say(f"tops backbone fanout={fanout} kpl={kpl} R={R} block={block}")
+        try:
+            P.planb_set_tuning(h, kpl, -1, R, block, 2)
+        except P.PlanbError as e:
+            assert e.code == P.PLANB_ERANGE  # the tops exceed a workgroup's LDS
+            continue
+        out = out_u16(a.shape[0])
+        P.planb_lookup(h, to_dev(a), a.shape[0], out)
+        assert np.array_equal(host_u16(out, a.shape[0]), want)
+
+
+@pytest.mark.parametrize("name", ["empty", "default_only", "nested_shared_start_64", "top_64"])
+def test_key_tops_in_lds_edges(P, name):
+    H = (1 << 64) - 1
+    base = 0x20010DB8 << 96
+    rules = {
+        "empty": [],
+        "default_only": [(0, 0, 42)],
+        "nested_shared_start_64": [(base, 32, 1), (base, 48, 2), (base, 64, 3), (base | (5 << 70), 60, 4),
+                                   (base | (1 << 64), 64, 5), (base | (2 << 64), 63, 6)],
+        "top_64": [(0, 0, 1), (0xFFFF << 112, 16, 2), ((H - 1) << 64, 64, 4), (H << 64, 64, 3),
+                   ((H - 7) << 64, 61, 9)],
+    }[name]
+    p = S.from_ints([r[0] for r in rules]) if rules else np.zeros((0, 2), np.uint64)
+    L = np.array([r[1] for r in rules], np.uint8)
+    nh = np.array([r[2] for r in rules], np.uint16)
+    rng = np.random.default_rng(5)
+    q = _edge_queries(rules, rng)
+    # addresses sharing the top 32 bits of every boundary, above and below it
+    extra = set()
+    for Pv, Lv, _ in rules:
+        for v in (Pv, Pv + (1 << (128 - Lv))):
+            hi = (v >> 64) & H
+            for d in (-(1 << 40), -1, 0, 1, 1 << 31):
+                h2 = hi + d
+                if 0 <= h2 <= H and (h2 >> 32) == (hi >> 32):
+                    extra.add(h2 << 64 | int(rng.integers(0, 2**63)))
+    q = S.from_ints(sorted({S.to_int(r) for r in q} | extra)) if extra else q
+    want = lpm_bruteforce(p, L, nh, q)
+    for fanout in (8, 16, 32):
+        h = P.planb_build(p, L, nh, fanout=fanout, key_bits=64)  # automatic would pick 32 for the first two
+        for kpl, R in ((fanout // 2, 2), (fanout // 4, 1)):
+            say(f"tops edge {name} fanout={fanout} kpl={kpl} R={R}")
+            P.planb_set_tuning(h, kpl, -1, R, 1024, 2)
+            out = out_u16(q.shape[0])
+            P.planb_lookup(h, to_dev(q), q.shape[0], out)
+            assert np.array_equal(host_u16(out, q.shape[0]), want)
+
+
+def test_key_tops_refused_for_wide_keys(P, tiny):
+    fib, _, _ = tiny
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8, key_bits=128)
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_set_tuning(h, 2, -1, 2, 1024, 2)
+    assert e.value.code == P.PLANB_EINVAL
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
+    with pytest.raises(P.PlanbError) as e:  # one lane per lookup in every level: no such shape
+        P.planb_set_tuning(h, 8, -1, 2, 1024, 2)
+    assert e.value.code == P.PLANB_EINVAL
