@@ -277,9 +277,8 @@ def ablation_leg(P, fib, d, n, out, got, steps=3):
     the tree with one lane per lookup and no LDS, lane groups per lookup,
     LDS-staged top levels, binary search by one lane in the LDS levels, the
     bottom internal level in LDS as 32-bit key tops (the headline shape), and
-    the persistent kernel replayed from a graph (which stages whole keys, as
-    the rung before the headline).  Every rung's output is checked against
-    the headline result."""
+    the persistent kernel replayed from a graph in the last two shapes.  Every
+    rung's output is checked against the headline result."""
     import torch
     rungs = []
     h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
@@ -302,11 +301,12 @@ def ablation_leg(P, fib, d, n, out, got, steps=3):
         P.planb_set_tuning(h, *tu)
         timed(name, lambda: P.planb_lookup(h, d, n, o), dict(zip(("keys_per_lane", "lds_levels", "lookups_per_group",
                                                                    "block_threads", "lds_search"), tu)))
-    P.planb_set_tuning(h, 2, 5, 2, 512, 1)
-    g = P.Graph(h, 4)
-    timed("persistent kernel, graph replay, one batch", lambda: g.launch([(d, o, n)]),
-          "whole keys in the top 5 LDS levels (lds_search 1)")
-    g.close()
+    for tu, note in (((2, 5, 2, 512, 1), "whole keys in the top 5 LDS levels (lds_search 1)"),
+                     ((2, 5, 2, 1024, 2), "the headline shape (key tops)")):
+        P.planb_set_tuning(h, *tu)
+        g = P.Graph(h, 4)
+        timed("persistent kernel, graph replay, one batch", lambda: g.launch([(d, o, n)]), note)
+        g.close()
     return rungs
 
 

@@ -25,16 +25,31 @@ struct BatchRec {  // same layout as planb_batch_t
 };
 static_assert(sizeof(BatchRec) == sizeof(planb_batch_t), "planb_batch_t layout");
 
-template <int B, int KPL, int R, int KB, int BS, bool BIN>
+// Bytes of LDS the staged tree takes: the first t.lds_slots slots, and with
+// TOPS the bottom internal level's key tops after them (B - 1 per node).
+template <int B, int KB, bool TOPS>
+__host__ __device__ inline size_t staged_tree_bytes(const TreeDesc& t)
+{
+    size_t bytes = (size_t)t.lds_slots * KB;
+    if (TOPS && t.depth >= 2) bytes += (size_t)(t.off[t.depth - 1] - t.off[t.depth - 2]) * (B - 1) * 4;
+    return (bytes + 15) / 16 * 16;
+}
+
+// TOPS: the descriptor's lds_levels are depth - 2 and the bottom internal
+// level is staged as key tops (64-bit key slots; see lookup_tops_kernel).
+template <int B, int KPL, int R, int KB, int BS, bool BIN, bool TOPS = false>
 __global__ void __launch_bounds__(BS)
 batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t* __restrict__ count,
                uint32_t max_batches, int index_out)
 {
     using D = Descent<B, KPL, R, KB, BIN>;
     extern __shared__ uint4 lds_raw[];
-    uint32_t* tile_off = reinterpret_cast<uint32_t*>(lds_raw + D::lds_bytes(t) / 16);  // max_batches + 1
-    uint32_t* part = tile_off + max_batches + 1;                                       // BS
-    D::stage(t, lds_raw, threadIdx.x, BS);
+    uint32_t* tile_off = reinterpret_cast<uint32_t*>(lds_raw + staged_tree_bytes<B, KB, TOPS>(t) / 16);  // max_batches + 1
+    uint32_t* part = tile_off + max_batches + 1;                                                        // BS
+    if constexpr (TOPS)
+        D::stage_bottom_tops(t, lds_raw, threadIdx.x, BS);
+    else
+        D::stage(t, lds_raw, threadIdx.x, BS);
 
     const uint32_t nb = min(*count, max_batches);
     const uint32_t per = (nb + BS - 1) / BS;
@@ -68,7 +83,11 @@ batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t*
             if (tile_off[mid] <= tile) lo = mid; else hi = mid;
         }
         const BatchRec br = batches[lo];
-        D::step(t, lds_keys, br.addrs, (uint64_t)(tile - tile_off[lo]) * D::kStep, br.n, br.out, index_out);
+        if constexpr (TOPS)
+            D::template step_hybrid<u64x2, true>(t, lds_raw, br.addrs, (uint64_t)(tile - tile_off[lo]) * D::kStep, br.n,
+                                                 br.out, index_out);
+        else
+            D::step(t, lds_keys, br.addrs, (uint64_t)(tile - tile_off[lo]) * D::kStep, br.n, br.out, index_out);
     }
 }
 
@@ -80,22 +99,67 @@ struct BatchesKernel {
     static Fn get() { return batches_kernel<B, KPL, R, KB, BS, BIN>; }
 };
 
+using BatchesFn = BatchesKernel<8, 1, 1, 8, 512, false>::Fn;
+
 struct BatchesLaunch {
-    BatchesKernel<8, 1, 1, true, 512, false>::Fn fn = nullptr;
+    BatchesFn fn = nullptr;
+    TreeDesc desc{};  // the FIB's, or with the key-tops staging
     unsigned grid = 0;
     size_t lds = 0;
 };
 
+// Key-tops variants: B in {8, 16, 32}, B / KPL in {2, 4}, R in {1, 2, 4}, BS in {512, 1024}.
+template <int B, int KPL>
+BatchesFn pick_tops_r(int R, int bs)
+{
+    auto by_bs = [&](auto r) -> BatchesFn {
+        constexpr int Rc = decltype(r)::value;
+        return bs == 512    ? batches_kernel<B, KPL, Rc, 8, 512, true, true>
+               : bs == 1024 ? batches_kernel<B, KPL, Rc, 8, 1024, true, true>
+                            : nullptr;
+    };
+    return R == 1 ? by_bs(std::integral_constant<int, 1>{}) : R == 2 ? by_bs(std::integral_constant<int, 2>{})
+         : R == 4 ? by_bs(std::integral_constant<int, 4>{}) : nullptr;
+}
+
+BatchesFn pick_batches_tops(int B, int kpl, int R, int bs)
+{
+    if (kpl <= 0 || B % kpl) return nullptr;
+    const int G = B / kpl;
+    if (B == 8) return G == 2 ? pick_tops_r<8, 4>(R, bs) : G == 4 ? pick_tops_r<8, 2>(R, bs) : nullptr;
+    if (B == 16) return G == 2 ? pick_tops_r<16, 8>(R, bs) : G == 4 ? pick_tops_r<16, 4>(R, bs) : nullptr;
+    if (B == 32) return G == 2 ? pick_tops_r<32, 16>(R, bs) : G == 4 ? pick_tops_r<32, 8>(R, bs) : nullptr;
+    return nullptr;
+}
+
 int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
 {
-    const TreeDesc& t = fib->desc;
     const LookupTuning& tu = fib->tune;
-    L->fn = VariantTable<BatchesKernel>::pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
-    if (!L->fn) return fail(PLANB_EINVAL, "no batches kernel for this tuning");
     DevProps p;
     hipError_t e = dev_props(&p);
     if (e != hipSuccess) return fail_hip(e, "device properties");
-    L->lds = (size_t)t.lds_slots * t.key_bytes + ((size_t)max_batches + 1 + tu.block) * 4;
+    const size_t table = ((size_t)max_batches + 1 + tu.block) * 4;  // tile offsets and the scan
+    L->desc = fib->desc;
+    L->fn = nullptr;
+    if (tu.tops) {  // the key-tops staging when it fits beside the batch table, else whole keys
+        TreeDesc t = fib->desc;
+        t.lds_levels = t.depth >= 2 ? t.depth - 2 : 0;
+        t.lds_slots = t.off[t.lds_levels] * t.fanout;
+        size_t tree = (size_t)t.lds_slots * 8;
+        if (t.depth >= 2) tree += (size_t)(t.off[t.depth - 1] - t.off[t.depth - 2]) * (t.fanout - 1) * 4;
+        tree = (tree + 15) / 16 * 16;
+        if (tree + table <= (size_t)p.max_lds) {
+            L->fn = pick_batches_tops((int)t.fanout, tu.kpl, tu.R, tu.block);
+            L->desc = t;
+            L->lds = tree + table;
+        }
+    }
+    const TreeDesc& t = L->desc;
+    if (!L->fn) {
+        L->fn = VariantTable<BatchesKernel>::pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
+        L->lds = ((size_t)t.lds_slots * t.key_bytes + 15) / 16 * 16 + table;
+    }
+    if (!L->fn) return fail(PLANB_EINVAL, "no batches kernel for this tuning");
     if (L->lds > (size_t)p.max_lds)
         return fail(PLANB_ERANGE, "LDS levels plus " + std::to_string(max_batches) +
                                       " batch offsets exceed the workgroup LDS limit; lower lds_levels or max_batches");
@@ -155,7 +219,7 @@ int planb_lookup_batches(const planb_fib_t* fib, const planb_batch_t* batches, c
     if (rc != PLANB_OK) return rc;
     BatchesLaunch L;
     if ((rc = plan_batches(fib, max_batches, &L)) != PLANB_OK) return rc;
-    hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(fib->tune.block), L.lds, static_cast<hipStream_t>(stream), fib->desc,
+    hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(fib->tune.block), L.lds, static_cast<hipStream_t>(stream), L.desc,
                        reinterpret_cast<const BatchRec*>(batches), n_batches, max_batches, 0);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "batches launch");
@@ -189,7 +253,7 @@ planb_graph_t* planb_graph_create(const planb_fib_t* fib, uint32_t max_batches)
         if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) break;
         if ((e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) break;
         (void)hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, g->cap);
-        hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(fib->tune.block), L.lds, g->cap, fib->desc,
+        hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(fib->tune.block), L.lds, g->cap, L.desc,
                            reinterpret_cast<const BatchRec*>(s.dev + 16), reinterpret_cast<const uint32_t*>(s.dev),
                            max_batches, 0);
         hipError_t le = hipGetLastError();

@@ -135,3 +135,44 @@ def test_autotune_keeps_results_exact(P, tmp_path):
     P.planb_lookup(h2, d, len(addrs), out)
     assert np.array_equal(host_u16(out, len(addrs)), want)
     assert json.load(open(cache))
+
+
+def test_batches_and_graph_with_key_tops(P):
+    """A tuning with lds_search 2: the persistent batch kernel stages the bottom
+    internal level as key tops when they fit beside the batch table (else
+    whole keys); device descriptors, graph replays and eager lookups between
+    them all equal the oracle."""
+    import torch
+    fib = fib_of("backbone", 22)
+    trie = oracle_trie("backbone", 22)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
+    P.planb_set_tuning(h, 2, 5, 2, 1024, 2)
+    rng = np.random.default_rng(31)
+    sizes = np.concatenate([[0, 1, 127, 128, 129], S.log_uniform_sizes(rng, 40, 1, 1 << 17)])
+    addrs, offs = _uneven(fib, sizes, 131)
+    want = trie.lookup(addrs)
+    d = to_dev(addrs)
+    out = torch.full((len(addrs),), -1, dtype=torch.int16, device="cuda")
+    desc = torch.from_numpy(np.frombuffer(bytes(P.batch_array(_batches(P, d, out, sizes, offs))),
+                                          dtype=np.uint8).copy()).cuda()
+    cnt = torch.tensor([len(sizes)], dtype=torch.int32, device="cuda")
+    say("key tops: device descriptors")
+    P.planb_lookup_batches(h, desc, cnt, len(sizes))
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    for max_batches in (64, 5000):  # 5000 batch offsets leave no room for the tops: whole keys
+        g = P.Graph(h, max_batches)
+        for rep in range(3):
+            nb = [45, 9, 30][rep]
+            sz = S.log_uniform_sizes(rng, nb, 1, 1 << 16)
+            a, o = _uneven(fib, sz, 200 + rep)
+            w = trie.lookup(a)
+            da = to_dev(a)
+            go = torch.full((len(a),), -1, dtype=torch.int16, device="cuda")
+            say(f"key tops: graph max_batches={max_batches} replay {rep} batches={nb}")
+            g.launch(_batches(P, da, go, sz, o))
+            eager = torch.full((len(a),), -1, dtype=torch.int16, device="cuda")
+            P.planb_lookup(h, da, len(a), eager)
+            torch.cuda.synchronize()
+            assert np.array_equal(host_u16(go, len(a)), w)
+            assert np.array_equal(host_u16(eager, len(a)), w)
+        g.close()
