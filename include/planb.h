@@ -229,15 +229,20 @@ int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
  *                      levels are then shared by fanout/keys_per_lane lanes
  *                      (1, 2 or 4), which take the lookups over by shuffles;
  *                      2 (64-bit key slots; fanout/keys_per_lane 2 or 4): as 1,
- *                      but planb_lookup and planb_lookup_index stage every
- *                      internal level in LDS (ignoring lds_levels): the bottom
- *                      one as the top 32 bits of each key, the levels above it
- *                      whole, so that only the leaf is read from device memory;
- *                      a lookup whose address ties a bottom key's top half
- *                      re-reads that node whole.  Results are unchanged.  The other lookup paths (batches,
- *                      graphs, many FIBs, IPv4) run this tuning as 1 with
+ *                      but planb_lookup and planb_lookup_index (on batches of
+ *                      2^20 addresses or more; smaller ones run as 1) and the
+ *                      persistent batch kernel (when it fits beside the batch
+ *                      table) stage every internal level in LDS, ignoring
+ *                      lds_levels: the bottom one as the top 32 bits of each
+ *                      key, the levels above it whole, so that only the leaf is
+ *                      read from device memory; a lookup whose address ties a
+ *                      bottom key's top half re-reads that node whole.
+ *                      The many-FIB and IPv4 paths run this tuning as 1 with
  *                      lds_levels.  PLANB_ERANGE when those tops exceed a
  *                      workgroup's LDS.
+ * A FIB starts with keys_per_lane = fanout/4 (or planb_params_t's), the
+ * deepest lds_levels within 64 KiB, 2 lookups per group and the fastest
+ * lds_search that applies: 2 with 1024 threads, else 1, else 0 (512 threads).
  */
 typedef struct planb_tuning {
     uint32_t keys_per_lane;

@@ -165,14 +165,22 @@ void build_image(const Intervals& iv, const Layout& lay, int key_bytes, std::vec
 
 int finish_fib(planb_fib_t* f, const planb_params_t& p)
 {
+    // The initial launch shape, the fastest that applies of the measured
+    // ones: the key tops (1024 threads), else the hybrid binary search, else
+    // every lane comparing its keys (512 threads).
     planb_tuning_t tu{};
     tu.keys_per_lane = p.keys_per_lane ? p.keys_per_lane : default_kpl(p.fanout);
     tu.lds_levels = p.lds_levels > 0 ? p.lds_levels : -1;
     tu.lookups_per_group = 2;
-    tu.block_threads = 512;
     int32_t lds_ok = 0;
-    int rc = validate_tuning(f, tu, &f->tune, &lds_ok);
+    int rc = PLANB_EINVAL;
+    for (uint32_t mode : {2u, 1u, 0u}) {
+        tu.lds_search = mode;
+        tu.block_threads = mode == 2 ? 1024 : 512;
+        if ((rc = validate_tuning(f, tu, &f->tune, &lds_ok)) == PLANB_OK) break;
+    }
     if (rc != PLANB_OK) return rc;
+    clear_error();  // a shape that did not apply is no error of the build
     f->lds_levels = lds_ok;
     refresh_desc(f);
     return PLANB_OK;

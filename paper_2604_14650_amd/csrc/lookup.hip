@@ -262,6 +262,8 @@ hipError_t launch_lookup_v4(const TreeDesc& t, const LookupTuning& tu, const uin
     return hipGetLastError();
 }
 
+constexpr uint64_t kTopsMinLookups = 1ull << 20;
+
 hipError_t launch_lookup(const TreeDesc& td, const LookupTuning& tu, const void* addrs, uint64_t n, void* out,
                          bool index_out, hipStream_t stream)
 {
@@ -270,7 +272,10 @@ hipError_t launch_lookup(const TreeDesc& td, const LookupTuning& tu, const void*
     KernelFn fn = nullptr;
     size_t slot_bytes = t.key_bytes;
     size_t extra = 0;
-    if (tu.tops) {
+    // Below about 2^20 lookups the larger LDS staging of the key tops (one
+    // workgroup per CU loading up to 160 KB) costs more than it saves: such
+    // batches take the whole-key hybrid descent of the same tuning.
+    if (tu.tops && n >= kTopsMinLookups) {
         if (t.key_bytes != 8) return hipErrorInvalidValue;
         // exact levels above the bottom internal one, then that level's key tops
         t.lds_levels = t.depth >= 2 ? t.depth - 2 : 0;

@@ -336,11 +336,16 @@ def test_key_tops_in_lds_tiny(P, tiny, fanout, kpl, R):
         out = out_u16(addrs.shape[0])
         P.planb_lookup(h, d, addrs.shape[0], out)
         assert np.array_equal(host_u16(out, addrs.shape[0]), want)
-    n = 1 << 16
+    # 3 fewer addresses: below 2^20 the same tuning runs the whole-key hybrid descent
+    m = addrs.shape[0] - 3
+    out = out_u16(m)
+    P.planb_lookup(h, d, m, out)
+    assert np.array_equal(host_u16(out, m), want[:m])
+    n = addrs.shape[0]
     idx = torch.full((n,), -1, dtype=torch.int32, device="cuda")
-    P.planb_lookup_index(h, to_dev(addrs[:n]), n, idx)
+    P.planb_lookup_index(h, d, n, idx)
     i = idx.cpu().numpy().astype(np.int64)
-    assert np.array_equal(i, np.searchsorted(starts[:, 0], addrs[:n, 0], side="right") - 1)
+    assert np.array_equal(i, np.searchsorted(starts[:, 0], addrs[:, 0], side="right") - 1)
 
 
 @pytest.mark.parametrize("fanout", [8, 16])
@@ -391,6 +396,9 @@ def test_key_tops_in_lds_edges(P, name):
                     extra.add(h2 << 64 | int(rng.integers(0, 2**63)))
     q = S.from_ints(sorted({S.to_int(r) for r in q} | extra)) if extra else q
     want = lpm_bruteforce(p, L, nh, q)
+    # repeated to 2^20 addresses: smaller batches run the whole-key hybrid descent
+    reps = -(-(1 << 20) // q.shape[0])
+    q, want = np.tile(q, (reps, 1)), np.tile(want, reps)
     for fanout in (8, 16, 32):
         h = P.planb_build(p, L, nh, fanout=fanout, key_bits=64)  # automatic would pick 32 for the first two
         for kpl, R in ((fanout // 2, 2), (fanout // 4, 1)):
