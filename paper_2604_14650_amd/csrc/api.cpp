@@ -54,6 +54,7 @@ void refresh_desc(planb_fib_t* f)
     t.lds_slots = (uint32_t)f->lay.prefix_slots(f->lds_levels);
     t.fanout = f->lay.b;
     t.leaf_base = (uint32_t)f->lay.leaf_base();
+    t.last_hop = f->iv.nh.empty() ? 0xFFFFu : f->iv.nh.back();
     for (int l = 0; l < kDevMaxLevels; ++l) {
         t.off[l] = l < (int)f->lay.depth ? (uint32_t)f->lay.offset[l] : 0;
         t.last[l] = l < (int)f->lay.depth ? (uint32_t)(f->lay.nodes[l] - 1) : 0;

@@ -312,7 +312,7 @@ struct Descent {
         // have all of theirs <= x, so that lane is the count of lanes with any,
         // minus one, and its own count picks the hop in its block.  One group
         // sum adds both counts: keys in the low byte, lanes above it.
-        const uint16_t last_hop = t.vals[t.m_minus_1];
+        const uint32_t last_hop = t.last_hop;
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const uint32_t cl = (uint32_t)leaf_lane_count(L[u], j, xh[u], xl[u]);
@@ -353,37 +353,38 @@ struct Descent {
     }
 
     // The bottom internal level from its key tops, one lane per lookup: a
-    // binary search on the tops, where a key whose top half is below x's is
-    // <= x and one above is not.  A tie leaves the key open, so the search
-    // counts it as <= x and notes it; afterwards every lookup that met a tie
-    // recounts its node from the whole keys in device memory (one load round
-    // for the wavefront, taken by the tied lanes only).
+    // binary search counts the tops <= x's top half (exact on the tops).  The
+    // keys it counts whose top equals x's are the end of that prefix, and the
+    // ones among them above x are a suffix of it, so a lane whose last counted
+    // top ties walks back over them, one whole key read from device memory
+    // per step (one step, nearly always).
     static __device__ __forceinline__ void bottom_step(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
                                                        uint32_t* q)
     {
         const uint32_t lvl = bottom_level(t), off = t.off[lvl], lim = t.last[lvl + 1];
-        uint32_t c[R];
-        bool tie[R];
+        const K* gkeys = static_cast<const K*>(t.keys);
+        uint32_t c[R], last[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
             c[r] = 0;
-            tie[r] = false;
+            last[r] = 0;
 #pragma unroll
             for (int step = B / 2; step >= 1; step >>= 1) {
                 const uint32_t v = tops[n0 + c[r] + (uint32_t)(step - 1)];
-                tie[r] |= v == tx;
-                c[r] += v <= tx ? (uint32_t)step : 0u;
+                const bool le = v <= tx;
+                last[r] = le ? v : last[r];  // the top of key c - 1
+                c[r] += le ? (uint32_t)step : 0u;
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (tie[r]) {
-                const K* node = slot_ptr(static_cast<const K*>(t.keys), (off + q[r]) * (uint32_t)B);
-                uint32_t cnt = 0;
-#pragma unroll
-                for (int s = 0; s < B - 1; ++s) cnt += node[s] <= xh[r] ? 1u : 0u;
-                c[r] = cnt;
+            const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
+            if (c[r] > 0 && last[r] == tx) {
+                const uint32_t node = (off + q[r]) * (uint32_t)B;
+                uint32_t k = c[r];
+                while (k > 0 && tops[n0 + k - 1] == tx && *slot_ptr(gkeys, node + k - 1) > xh[r]) --k;
+                c[r] = k;
             }
         }
 #pragma unroll

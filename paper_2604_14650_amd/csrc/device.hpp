@@ -25,6 +25,7 @@ struct TreeDesc {
     uint32_t lds_slots;      // slots in those levels (a prefix of the slot array)
     uint32_t fanout;         // B (checked against the kernel's template)
     uint32_t leaf_base;      // slot of the first leaf
+    uint32_t last_hop;       // next hop of the last interval (vals[m_minus_1])
     uint32_t off[kDevMaxLevels];   // first node of each internal level
     uint32_t last[kDevMaxLevels];  // last allocated node of each level (the leaf level last)
 };
