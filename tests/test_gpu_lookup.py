@@ -419,3 +419,34 @@ def test_key_tops_refused_for_wide_keys(P, tiny):
     with pytest.raises(P.PlanbError) as e:  # one lane per lookup in every level: no such shape
         P.planb_set_tuning(h, 8, -1, 2, 1024, 2)
     assert e.value.code == P.PLANB_EINVAL
+
+
+def test_key_tops_dense_slash32(P):
+    """20,000 /64 rules and 300 /48 rules inside one /32: hundreds of
+    consecutive bottom-level keys share their top 32 bits, so the tie walk of
+    lds_search 2 runs over long runs of equal tops."""
+    rng = np.random.default_rng(41)
+    top = 0x20010DB8 << 96
+    los = rng.choice(1 << 32, size=20000, replace=False).astype(np.int64)
+    rules = {(top | (int(v) << 64), 64): int(rng.integers(0, 60000)) for v in los}
+    for v in rng.choice(1 << 16, size=300, replace=False):
+        rules[(top | (int(v) << 80), 48)] = int(rng.integers(0, 60000))
+    rules[(top, 32)] = 7
+    rules[(0, 0)] = 1
+    keys = sorted(rules)
+    p = S.from_ints([k[0] for k in keys])
+    L = np.array([k[1] for k in keys], np.uint8)
+    nh = np.array([rules[k] for k in keys], np.uint16)
+    from oracle.trie import Trie
+    trie = Trie(p, L, nh)
+    hi = np.concatenate([(top >> 64) + rng.integers(0, 1 << 32, size=(1 << 20) - 4096),
+                         (p[rng.integers(0, len(keys), size=4096), 0]).astype(np.int64)]).astype(np.uint64)
+    q = np.stack([hi, rng.integers(0, 2**63, size=hi.shape[0]).astype(np.uint64)], axis=1)
+    want = trie.lookup(q)
+    h = P.planb_build(p, L, nh, fanout=8)
+    assert P.planb_get_info(h)["key_bits"] == 64
+    say("tops dense /32")
+    P.planb_set_tuning(h, 2, -1, 2, 1024, 2)
+    out = out_u16(q.shape[0])
+    P.planb_lookup(h, to_dev(q), q.shape[0], out)
+    assert np.array_equal(host_u16(out, q.shape[0]), want)
