@@ -357,38 +357,53 @@ struct Descent {
     // keys it counts whose top equals x's are the end of that prefix, and the
     // ones among them above x are a suffix of it, so a lane whose last counted
     // top ties walks back over them, one whole key read from device memory
-    // per step (one step, nearly always).
-    static __device__ __forceinline__ void bottom_step(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
-                                                       uint32_t* q)
+    // per step (one step, nearly always).  bottom_search issues the first of
+    // those reads; bottom_finish, called after the lane hand-off's address
+    // shuffles, uses it, so that its round trip overlaps them.
+    struct Bottom {
+        uint32_t c[R], last[R];
+        uint64_t tk[R];  // the key c - 1, read when its top ties
+    };
+    static __device__ __forceinline__ void bottom_search(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
+                                                         const uint32_t* q, Bottom& bs)
+    {
+        const uint32_t lvl = bottom_level(t), off = t.off[lvl];
+        const K* gkeys = static_cast<const K*>(t.keys);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
+            uint32_t c = 0, last = 0;
+#pragma unroll
+            for (int step = B / 2; step >= 1; step >>= 1) {
+                const uint32_t v = tops[n0 + c + (uint32_t)(step - 1)];
+                const bool le = v <= tx;
+                last = le ? v : last;
+                c += le ? (uint32_t)step : 0u;
+            }
+            bs.c[r] = c;
+            bs.last[r] = last;
+            // every lane loads; the untied ones all read slot 0 (one shared line), so
+            // the load is not in a branch and its wait can follow the shuffles
+            const bool tie = c > 0 && last == tx;
+            bs.tk[r] = *slot_ptr(gkeys, tie ? (off + q[r]) * (uint32_t)B + c - 1 : 0u);
+        }
+    }
+    static __device__ __forceinline__ void bottom_finish(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
+                                                         uint32_t* q, const Bottom& bs)
     {
         const uint32_t lvl = bottom_level(t), off = t.off[lvl], lim = t.last[lvl + 1];
         const K* gkeys = static_cast<const K*>(t.keys);
-        uint32_t c[R], last[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
-            c[r] = 0;
-            last[r] = 0;
-#pragma unroll
-            for (int step = B / 2; step >= 1; step >>= 1) {
-                const uint32_t v = tops[n0 + c[r] + (uint32_t)(step - 1)];
-                const bool le = v <= tx;
-                last[r] = le ? v : last[r];  // the top of key c - 1
-                c[r] += le ? (uint32_t)step : 0u;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
-            if (c[r] > 0 && last[r] == tx) {
+            uint32_t c = bs.c[r];
+            if (c > 0 && bs.last[r] == tx && bs.tk[r] > xh[r]) {
                 const uint32_t node = (off + q[r]) * (uint32_t)B;
-                uint32_t k = c[r];
-                while (k > 0 && tops[n0 + k - 1] == tx && *slot_ptr(gkeys, node + k - 1) > xh[r]) --k;
-                c[r] = k;
+                --c;
+                while (c > 0 && tops[n0 + c - 1] == tx && *slot_ptr(gkeys, node + c - 1) > xh[r]) --c;
             }
+            q[r] = min(q[r] * B + c, lim);
         }
-#pragma unroll
-        for (int r = 0; r < R; ++r) q[r] = min(q[r] * B + c[r], lim);
     }
 
     static __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
@@ -444,9 +459,10 @@ struct Descent {
             for (int r = 0; r < R; ++r)
                 q[r] = min(q[r] * B + lane_bincount<true>(lds_keys, (size_t)(off + q[r]) * B, xh[r], xl[r]), lim);
         }
+        Bottom bs;
         if constexpr (TOPS) {  // lds_levels = depth - 2: the bottom internal level from its tops
             if (t.depth >= 2) {
-                bottom_step(t, bottom_tops(lds, t), xh, q);
+                bottom_search(t, bottom_tops(lds, t), xh, q, bs);
                 lds_internal = t.depth - 1;
             }
         }
@@ -473,8 +489,19 @@ struct Descent {
             const int owner = (u % G) * LPW + grp;
             yh[u] = shfl64(xh[u / G], owner);
             yl[u] = WIDE ? shfl64(xl[u / G], owner) : 0;
-            p[u] = (uint32_t)__shfl((int)q[u / G], owner, 64);
         }
+        if constexpr (TOPS) {  // the tie reads were issued before the shuffles above
+            // Keep the first use of those reads (and so the wait for them)
+            // after the shuffles: the compiler would otherwise hoist the
+            // comparison, and the wait, above them.  The empty asm only marks
+            // the values as changed here; it reads and writes no memory.
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) asm volatile("" : "+v"(bs.tk[r]));
+            if (t.depth >= 2) bottom_finish(t, bottom_tops(lds, t), xh, q, bs);
+        }
+#pragma unroll
+        for (int u = 0; u < T; ++u) p[u] = (uint32_t)__shfl((int)q[u / G], (u % G) * LPW + grp, 64);
         for (uint32_t l = lds_internal; l + 1 < t.depth; ++l) {
             const uint32_t off = t.off[l], lim = t.last[l + 1];
 #pragma unroll
