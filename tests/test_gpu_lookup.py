@@ -450,3 +450,22 @@ def test_key_tops_dense_slash32(P):
     out = out_u16(q.shape[0])
     P.planb_lookup(h, to_dev(q), q.shape[0], out)
     assert np.array_equal(host_u16(out, q.shape[0]), want)
+
+
+def test_key_tops_refused_when_too_large(P):
+    """A 300k-prefix table with 64-bit keys: its bottom internal level's tops
+    exceed a workgroup's LDS, so lds_search 2 is refused with PLANB_ERANGE,
+    the default tuning falls back to lds_search 1, and lookups stay exact."""
+    from oracle.trie import Trie
+    fib = S.make_fib(S.vrf_spec(300000), 91)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
+    assert P.planb_get_info(h)["key_bits"] == 64
+    assert P.planb_get_tuning(h)["lds_search"] == 1
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_set_tuning(h, 2, -1, 2, 1024, 2)
+    assert e.value.code == P.PLANB_ERANGE
+    a = S.mixed_traffic(fib, 1 << 20, 0.5, 123)
+    say("tops refused: default tuning on a 300k table")
+    out = out_u16(a.shape[0])
+    P.planb_lookup(h, to_dev(a), a.shape[0], out)
+    assert np.array_equal(host_u16(out, a.shape[0]), Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(a))
