@@ -463,7 +463,7 @@ def main():
     result = {
         "metric": METRIC, "value": round(glps, 3), "unit": "GLPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "backbone-shaped FIB of 200,000 prefixes; 2^%d destination addresses "
                                "(70%% inside prefixes, 30%% uniform in 2000::/3)" % args.addresses,
