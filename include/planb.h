@@ -135,10 +135,15 @@ int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n,
 int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n,
                        uint32_t* out, void* stream);
 
-/* Releases the handle and its device memory.  It first waits for all work
- * enqueued on the device (hipDeviceSynchronize), so lookups in flight that use
- * the handle finish on the old structure (Section 3, "Dynamic FIB Update":
- * free after in-flight lookups complete).  NULL is ignored. */
+/* Releases the handle (Section 3, "Dynamic FIB Update": the replaced
+ * structure is freed once the lookups in flight on it complete).  Every call
+ * that enqueues work reading a FIB -- the lookup, batch, graph, learned,
+ * model and table-set calls -- records an event after that work on its
+ * stream.  planb_free returns at once: the device memory is freed in stream
+ * order behind those events, on a library stream, so neither the host nor any
+ * other stream waits.  Work captured into a caller's own graph is not
+ * recorded; keep the FIB until that graph's last replay has completed.  The
+ * handle may not be used after the call.  NULL is ignored. */
 void planb_free(planb_fib_t* fib);
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -405,8 +410,10 @@ typedef struct planb_burst {
 
 typedef struct planb_tableset planb_tableset_t;
 planb_tableset_t* planb_tableset_create(uint32_t max_tables);
-/* Points slot at fib (NULL empties it); synchronous.  The caller keeps fib
- * alive while any launch may use the slot. */
+/* Points slot at fib (NULL empties it).  Launches of the set already
+ * enqueued read the descriptors when they run, so the call first waits (on
+ * the host) for those launches to finish, then writes the slot.  The caller
+ * keeps fib alive while the slot names it. */
 int planb_tableset_set(planb_tableset_t* ts, uint32_t slot, const planb_fib_t* fib);
 /* Launch shape of the multi-FIB kernel (keys per lane, lookups per group, block size). */
 int planb_tableset_set_tuning(planb_tableset_t* ts, uint32_t keys_per_lane, uint32_t lookups_per_group,
@@ -435,8 +442,13 @@ void planb_tableset_free(planb_tableset_t* ts);
  * completion event has fired (copying results to the callers' host buffers)
  * and packs queued bursts of any tables into every free launch slot, one
  * stream per slot, so arrivals join the next launch while others run
- * (continuous batching).  planb_server_set_table on a live id swaps in the
- * rebuilt FIB; the old one is freed after the last launch using it.
+ * (continuous batching).  Each launch carries its own copy of the tree and
+ * model descriptors of the tables it serves, so planb_server_set_table on a
+ * live id (which swaps in the rebuilt FIB) and evictions never change what a
+ * launch already enqueued reads; a replaced FIB is freed after the launches
+ * that read it.  A burst whose table cannot be made resident (its rules fail
+ * to build, or it alone exceeds the budget) completes at once with that
+ * status and its output untouched.
  * Single-threaded: call a server's functions from one thread.
  */
 typedef struct planb_server planb_server_t;
@@ -460,7 +472,7 @@ typedef struct planb_completion {
     uint32_t n;
     double submit_us; /* planb_server_now_us() at submit */
     double done_us;   /* ... when poll saw the launch complete */
-    int32_t status;   /* PLANB_OK */
+    int32_t status;   /* PLANB_OK, or the error that kept the burst's table from being served */
     int32_t pad;
 } planb_completion_t;
 

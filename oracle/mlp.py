@@ -10,13 +10,18 @@ paper has no learned component); its definition here is the plain one:
   position   p  = clamp(floor(y * m), 0, m - 1)
 
 Parameters are one flat vector in the order W1 (row-major), b1, W2
-(row-major), b2, w3, b3 (5,313 values).  The GPU keeps W1, W2 and w3 as
-bfloat16 and everything else in float32; it rounds h1 to bfloat16 before the
-second layer and, when training, rounds the back-propagated layer errors to
-bfloat16 before the weight-gradient products.  ``rounding=True`` applies the
-same rounding points here (the arithmetic in between is float64), so the two
-sides differ only by float32 accumulation order and the rare bfloat16 rounding
-decision that this order flips.
+(row-major), b2, w3, b3 (5,313 values).
+
+Rounding rule (part of the model's definition): a tensor is rounded to
+bfloat16 (nearest, ties to even) exactly where it enters a matrix-core product
+as an operand.  Forward: the weights W1, W2, w3 and the layer-2 input h1.
+Backward: the layer errors dz2 and dz1 where they enter the weight-gradient
+products (dz2 also where it is propagated back through W2).  Biases, the
+output layer's gradient, the bias gradients and every accumulation stay in
+float.  ``rounding=True`` applies these points (the arithmetic in between is
+float64); ``rounding=False`` is the exact float64 model.  The rounded path is
+pinned against a construction of the same rule from torch's bfloat16
+conversion and float64 autograd, with planted misplacements that must differ.
 
 Loss: mean squared error between y and a target; training uses the middle of
 the target interval's slot, (i + 1/2) / m, so that floor(y * m) = i.
@@ -93,8 +98,9 @@ def predict_positions(y, m):
     return np.clip(v, 0, m - 1).astype(np.int64)
 
 
-def loss_and_grad(vec, X, t, rounding=True):
-    """Mean squared error of y against targets t and its gradient w.r.t. vec."""
+def loss_and_grad(vec, X, t, rounding=True, parts=False):
+    """Mean squared error of y against targets t and its gradient w.r.t. vec.
+    parts=True also returns the intermediate tensors (for error bounds)."""
     n = X.shape[0]
     y, c = forward(vec, X, rounding)
     p = c["p"]
@@ -113,6 +119,9 @@ def loss_and_grad(vec, X, t, rounding=True):
     dz1q = bf16_round(dz1) if rounding else dz1
     g["b1"] = dz1.sum(axis=0)
     g["W1"] = dz1q.T @ X
+    if parts:
+        return loss, pack(g), {"y": y, "dy": dy, "h1q": c["h1q"], "h2": c["h2"], "dz2": dz2, "dz2q": dz2q,
+                               "dz1": dz1, "dz1q": dz1q}
     return loss, pack(g)
 
 

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libplanb.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["lookup.hip", "learned.hip", "batches.hip", "multi.hip", "build_device.hip"]
-CXX_SOURCES = ["api.cpp", "builder.cpp", "server.cpp", "cpu_btree.cpp"]
+CXX_SOURCES = ["api.cpp", "builder.cpp", "server.cpp", "cpu_btree.cpp", "lifetime.cpp"]
 # host code of the CPU baseline: AVX2 vector compares (any x86-64 server since 2015)
 EXTRA_FLAGS = {"cpu_btree.cpp": ["-mavx2"]}
 

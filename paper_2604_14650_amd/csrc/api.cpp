@@ -287,8 +287,9 @@ planb_fib_t* planb_build_ex(const planb_addr_t* prefixes, const uint8_t* lengths
     }
     const size_t kbytes = image.size();
     const size_t vbytes = ((m + 63) / 64) * 64 * sizeof(uint16_t);
-    if ((e = hipMalloc(&f->d_keys, kbytes)) != hipSuccess || (e = hipMalloc(&f->d_vals, vbytes)) != hipSuccess) {
-        fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    if ((e = fib_alloc(f->device, &f->d_keys, kbytes)) != hipSuccess ||
+        (e = fib_alloc(f->device, reinterpret_cast<void**>(&f->d_vals), vbytes)) != hipSuccess) {
+        fail(PLANB_ENOMEM, std::string("device allocation: ") + hipGetErrorString(e));
         planb_free(f);
         return nullptr;
     }
@@ -317,10 +318,8 @@ planb_fib_t* planb_build(const planb_addr_t* prefixes, const uint8_t* lengths, c
 void planb_free(planb_fib_t* fib)
 {
     if (!fib) return;
-    (void)hipDeviceSynchronize();
     release_learned(fib);
-    if (fib->d_keys) (void)hipFree(fib->d_keys);
-    if (fib->d_vals) (void)hipFree(fib->d_vals);
+    free_after(fib->uses, fib->device, {fib->d_keys, fib->d_vals});
     delete fib;
 }
 
@@ -341,6 +340,7 @@ int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, ui
     int rc = check_lookup_args(fib, addrs, n, out, 2);
     if (rc != PLANB_OK || n == 0) return rc;
     hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, false, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
 
@@ -358,6 +358,7 @@ int planb_lookup_v4(const planb_fib_t* fib, const uint32_t* addrs, size_t n, uin
     int rc = check_current_device(fib);
     if (rc != PLANB_OK) return rc;
     hipError_t e = launch_lookup_v4(fib->desc, fib->tune, addrs, n, out, false, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "IPv4 lookup launch");
 }
 
@@ -366,6 +367,7 @@ int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t
     int rc = check_lookup_args(fib, addrs, n, out, 4);
     if (rc != PLANB_OK || n == 0) return rc;
     hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, true, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
 
@@ -374,6 +376,7 @@ int planb_lookup_bsearch(const planb_fib_t* fib, const planb_addr_t* addrs, size
     int rc = check_lookup_args(fib, addrs, n, out, 2);
     if (rc != PLANB_OK || n == 0) return rc;
     hipError_t e = launch_bsearch(fib->desc, addrs, n, out, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "binary-search launch");
 }
 

@@ -3,7 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/planb.h"
 #include "builder.hpp"
@@ -12,7 +16,36 @@
 
 namespace planb {
 struct LearnedModel;  // learned position model state (learned.hip)
-}
+
+// An event recorded after the latest work on one stream that reads an object.
+struct UseEvent {
+    hipEvent_t ev = nullptr;
+    ~UseEvent();
+};
+using UseRef = std::shared_ptr<UseEvent>;
+
+// Per object (a FIB, a table set): one event per stream that has enqueued
+// work reading it, re-recorded on each use (lifetime.cpp).
+struct UseLog {
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, UseRef>> last;
+};
+
+// Records, on `stream`, the end of the work just enqueued there for `log`'s
+// object.  Nothing is recorded while the stream is being captured into a
+// graph (such work is the graph owner's to order).  Returns the event, or
+// null when none was recorded.
+UseRef note_use(UseLog& log, hipStream_t stream);
+// Makes `ev` (recorded by another object's note_use) the latest use on stream.
+void note_shared_use(UseLog& log, hipStream_t stream, const UseRef& ev);
+// Device memory owned by a FIB or its model (stream-ordered allocator).
+hipError_t fib_alloc(int device, void** p, size_t bytes);
+// Frees ptrs (from fib_alloc) once every use recorded in `log` so far has
+// completed; returns at once and blocks no stream.
+void free_after(UseLog& log, int device, const std::vector<void*>& ptrs);
+// Releases bookkeeping of frees that have run.
+void reap_frees();
+}  // namespace planb
 
 struct planb_fib {
     planb::Intervals iv;   // host copy of the elementary intervals
@@ -26,6 +59,7 @@ struct planb_fib {
     int32_t lds_levels = 0;
     planb::TreeDesc desc{};
     planb::LearnedModel* learned = nullptr;
+    mutable planb::UseLog uses;  // streams whose enqueued work reads this FIB
 };
 
 namespace planb {

@@ -222,6 +222,7 @@ int planb_lookup_batches(const planb_fib_t* fib, const planb_batch_t* batches, c
     hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(fib->tune.block), L.lds, static_cast<hipStream_t>(stream), L.desc,
                        reinterpret_cast<const BatchRec*>(batches), n_batches, max_batches, 0);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "batches launch");
 }
 
@@ -295,6 +296,7 @@ int planb_graph_launch(planb_graph_t* g, const planb_batch_t* batches, uint32_t 
     if ((e = hipEventRecord(s.done, static_cast<hipStream_t>(stream))) != hipSuccess)
         return fail_hip(e, "hipEventRecord");
     s.used = true;
+    note_use(g->fib->uses, static_cast<hipStream_t>(stream));
     return PLANB_OK;
 }
 

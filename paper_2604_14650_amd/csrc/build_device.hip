@@ -509,8 +509,9 @@ extern "C" planb_fib_t* planb_build_device(const planb_addr_t* prefixes, const u
     if (rc != 0) return bail(rc == -5 ? PLANB_ERANGE : PLANB_EINVAL, err);
     const Layout& lay = f->lay;
     const size_t kbytes = lay.total_slots() * kb, vbytes = ((m + 63) / 64) * 64 * sizeof(uint16_t);
-    if ((e = hipMalloc(&f->d_keys, kbytes)) != hipSuccess || (e = hipMalloc(&f->d_vals, vbytes)) != hipSuccess)
-        return bail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    if ((e = fib_alloc(f->device, &f->d_keys, kbytes)) != hipSuccess ||
+        (e = fib_alloc(f->device, reinterpret_cast<void**>(&f->d_vals), vbytes)) != hipSuccess)
+        return bail(PLANB_ENOMEM, std::string("device allocation: ") + hipGetErrorString(e));
     f->key_bytes = kbytes;
     f->value_bytes = vbytes;
     uint8_t* img = static_cast<uint8_t*>(f->d_keys);

@@ -610,12 +610,13 @@ int ensure_model(planb_fib_t* f, uint32_t segments)
     f->learned = L;
     L->segments = segments;
     hipError_t e;
-    if ((e = hipMalloc(&L->w, kParams * 4)) != hipSuccess || (e = hipMalloc(&L->m1, kParams * 4)) != hipSuccess ||
-        (e = hipMalloc(&L->m2, kParams * 4)) != hipSuccess || (e = hipMalloc(&L->wb, kParams * 2)) != hipSuccess ||
-        (e = hipMalloc(&L->eps, (size_t)segments * 4)) != hipSuccess ||
-        (e = hipMalloc(&L->partials, (size_t)L->max_parts * kParams * 4)) != hipSuccess) {
+    auto get = [&](auto** p, size_t bytes) { return fib_alloc(f->device, reinterpret_cast<void**>(p), bytes); };
+    if ((e = get(&L->w, kParams * 4)) != hipSuccess || (e = get(&L->m1, kParams * 4)) != hipSuccess ||
+        (e = get(&L->m2, kParams * 4)) != hipSuccess || (e = get(&L->wb, kParams * 2)) != hipSuccess ||
+        (e = get(&L->eps, (size_t)segments * 4)) != hipSuccess ||
+        (e = get(&L->partials, (size_t)L->max_parts * kParams * 4)) != hipSuccess) {
         release_learned(f);
-        return fail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        return fail(PLANB_ENOMEM, std::string("device allocation: ") + hipGetErrorString(e));
     }
     return PLANB_OK;
 }
@@ -751,8 +752,9 @@ void release_learned(planb_fib_t* f)
 {
     LearnedModel* L = f->learned;
     if (!L) return;
-    for (void* p : {(void*)L->w, (void*)L->m1, (void*)L->m2, (void*)L->wb, (void*)L->eps, (void*)L->partials})
-        if (p) (void)hipFree(p);
+    // lookups already enqueued may still read the model: freed after them
+    free_after(f->uses, f->device,
+               {(void*)L->w, (void*)L->m1, (void*)L->m2, (void*)L->wb, (void*)L->eps, (void*)L->partials});
     delete L;
     f->learned = nullptr;
 }
@@ -852,6 +854,7 @@ int planb_model_predict(const planb_fib_t* fib, const planb_addr_t* addrs, size_
                        static_cast<hipStream_t>(stream), model_desc(fib->learned),
                        reinterpret_cast<const u64x2*>(addrs), (uint64_t)n, y);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "predict launch");
 }
 
@@ -866,7 +869,9 @@ int planb_model_grad(planb_fib_t* fib, const planb_addr_t* samples, const float*
     TrainArgs T{reinterpret_cast<const u64x2*>(samples), targets, nullptr, 0, (uint32_t)n, nullptr};
     uint32_t parts = 0;
     if ((rc = launch_grad(fib->learned, T, &parts, static_cast<hipStream_t>(stream))) != PLANB_OK) return rc;
-    return launch_adam(fib->learned, parts, grad, false, 0.f, static_cast<hipStream_t>(stream));
+    rc = launch_adam(fib->learned, parts, grad, false, 0.f, static_cast<hipStream_t>(stream));
+    if (rc == PLANB_OK) note_use(fib->uses, static_cast<hipStream_t>(stream));
+    return rc;
 }
 
 int planb_model_adam(planb_fib_t* fib, const float* grad, float lr, void* stream)
@@ -878,7 +883,9 @@ int planb_model_adam(planb_fib_t* fib, const float* grad, float lr, void* stream
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(fib->learned->partials, grad, kParams * 4, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return fail_hip(e, "copying the gradient");
-    return launch_adam(fib->learned, 1, nullptr, true, lr, st);
+    const int rc2 = launch_adam(fib->learned, 1, nullptr, true, lr, st);
+    if (rc2 == PLANB_OK) note_use(fib->uses, st);
+    return rc2;
 }
 
 int planb_model_build_eps(planb_fib_t* fib, void* stream)
@@ -1049,6 +1056,7 @@ int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size
     uint64_t nn = n;
     void* args[] = {args_t, &M, &a, &nn, &out, &fallback_count};
     e = hipLaunchKernel(fn, dim3(grid), dim3(kLearnBlock), args, 0, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "learned lookup launch");
 }
 

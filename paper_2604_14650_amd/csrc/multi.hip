@@ -80,7 +80,22 @@ struct planb_tableset {
     int key_bytes = 0;
     int device = 0;
     LookupTuning tune;               // launch shape of the multi-FIB kernel
+    UseLog uses;                     // streams with launches of this set
 };
+
+namespace {
+
+// One event for the launch, shared by the set and by every FIB it names, so
+// that a FIB freed later waits for this launch too.
+void note_set_use(const planb_tableset_t* ts_c, hipStream_t stream)
+{
+    auto* ts = const_cast<planb_tableset_t*>(ts_c);
+    UseRef ev = note_use(ts->uses, stream);
+    for (const planb_fib_t* f : ts->fibs)
+        if (f) note_shared_use(f->uses, stream, ev);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -103,14 +118,15 @@ planb_tableset_t* planb_tableset_create(uint32_t max_tables)
     ts->tune.R = 2;
     ts->tune.block = 512;
     hipError_t e = hipGetDevice(&ts->device);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ts->dev), sizeof(TreeDesc) * max_tables);
+    if (e == hipSuccess)
+        e = fib_alloc(ts->device, reinterpret_cast<void**>(&ts->dev), sizeof(TreeDesc) * max_tables);
     if (e == hipSuccess) e = hipMemset(ts->dev, 0, sizeof(TreeDesc) * max_tables);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ts->dev_models), sizeof(ModelDesc) * max_tables);
+    if (e == hipSuccess)
+        e = fib_alloc(ts->device, reinterpret_cast<void**>(&ts->dev_models), sizeof(ModelDesc) * max_tables);
     if (e == hipSuccess) e = hipMemset(ts->dev_models, 0, sizeof(ModelDesc) * max_tables);
     if (e != hipSuccess) {
         fail_hip(e, "creating a table set");
-        if (ts->dev) (void)hipFree(ts->dev);
-        if (ts->dev_models) (void)hipFree(ts->dev_models);
+        free_after(ts->uses, ts->device, {ts->dev, ts->dev_models});
         delete ts;
         return nullptr;
     }
@@ -120,9 +136,7 @@ planb_tableset_t* planb_tableset_create(uint32_t max_tables)
 void planb_tableset_free(planb_tableset_t* ts)
 {
     if (!ts) return;
-    (void)hipDeviceSynchronize();
-    if (ts->dev) (void)hipFree(ts->dev);
-    if (ts->dev_models) (void)hipFree(ts->dev_models);
+    free_after(ts->uses, ts->device, {ts->dev, ts->dev_models});
     delete ts;
 }
 
@@ -147,7 +161,13 @@ int planb_tableset_set(planb_tableset_t* ts, uint32_t slot, const planb_fib_t* f
         d.lds_slots = 0;
     }
     const ModelDesc md = ready_model_desc(fib);
-    hipError_t e = hipMemcpy(ts->dev + slot, &d, sizeof(TreeDesc), hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    {  // launches of the set already enqueued read the descriptors when they run
+        std::lock_guard<std::mutex> lk(ts->uses.mu);
+        for (auto& u : ts->uses.last)
+            if (e == hipSuccess && u.second && u.second->ev) e = hipEventSynchronize(u.second->ev);
+    }
+    if (e == hipSuccess) e = hipMemcpy(ts->dev + slot, &d, sizeof(TreeDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ts->dev_models + slot, &md, sizeof(ModelDesc), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail_hip(e, "writing a table descriptor");
     ts->host[slot] = d;
@@ -182,6 +202,7 @@ int planb_lookup_multi(const planb_tableset_t* ts, const planb_burst_t* bursts, 
     if (rc != PLANB_OK) return rc;
     hipError_t e = launch_multi(L, ts->dev, ts->max_tables, reinterpret_cast<const BurstRec*>(bursts), n_bursts,
                                 max_bursts, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_set_use(ts, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "multi-FIB launch");
 }
 
@@ -199,6 +220,7 @@ int planb_lookup_multi_learned(const planb_tableset_t* ts, const planb_burst_t* 
     hipError_t e = launch_multi_learned(L, ts->dev, ts->dev_models, ts->max_tables,
                                         reinterpret_cast<const BurstRec*>(bursts), n_bursts, max_bursts,
                                         fallback_count, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) note_set_use(ts, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "learned multi-FIB launch");
 }
 

@@ -16,12 +16,15 @@
 //    least recently used idle tables while the budget would be exceeded;
 //  * set_table() on a live id builds the new FIB and swaps it in; the old one
 //    is freed when the last launch that used it has completed.
+// Every launch carries its own copy of the tree (and model) descriptors of
+// the tables it serves, written on its stream with its bursts, so a swap or
+// an eviction never changes what a launch already enqueued reads; the FIBs
+// themselves are freed after the launches recorded on them (planb_free).
 #include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -37,13 +40,6 @@ double now_us()
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-void free_fib_nosync(planb_fib_t* f)
-{
-    release_learned(f);
-    if (f->d_keys) (void)hipFree(f->d_keys);
-    if (f->d_vals) (void)hipFree(f->d_vals);
-    delete f;
-}
 
 struct Pending {
     int64_t tag;
@@ -65,45 +61,65 @@ struct Table {
     size_t bytes = 0;
     double last_use = 0;
     int inflight = 0;            // launches in flight that use `fib`
+    uint64_t gen = 0;            // bumped whenever `fib` is replaced or evicted
+};
+
+// Descriptor area of one launch (host pinned and device copies alike):
+// [count u32, pad to 16][BurstRec x max_bursts][TreeDesc x T][ModelDesc x T],
+// T = tables one launch may serve; a burst's `table` is its table's index
+// among the launch's T descriptors.
+struct DescLayout {
+    size_t bursts = 16, trees = 0, models = 0, bytes = 0;
+    uint32_t max_tables = 0;
+    DescLayout() = default;
+    DescLayout(uint32_t max_bursts, uint32_t T) : max_tables(T)
+    {
+        auto up = [](size_t x) { return (x + 15) / 16 * 16; };
+        trees = up(bursts + (size_t)max_bursts * sizeof(BurstRec));
+        models = up(trees + (size_t)T * sizeof(TreeDesc));
+        bytes = up(models + (size_t)T * sizeof(ModelDesc));
+    }
 };
 
 struct Slot {
     hipStream_t st = nullptr;
-    hipEvent_t done = nullptr;
+    UseRef done;                      // recorded after each launch's results are copied back
     planb_addr_t* h_in = nullptr;
     uint16_t* h_out = nullptr;
-    unsigned char* h_desc = nullptr;  // [count u32, pad][BurstRec x max_bursts]
+    unsigned char* h_desc = nullptr;  // DescLayout
     planb_addr_t* d_in = nullptr;
     uint16_t* d_out = nullptr;
     unsigned char* d_desc = nullptr;
     bool busy = false;
     std::vector<Pending> bursts;
-    std::vector<planb_fib_t*> fibs;  // FIB used by each table of the launch (for deferred frees)
-    std::vector<uint32_t> tables;
+    std::vector<uint32_t> tables;    // tables of the launch
+    std::vector<uint64_t> gens;      // their generation when the launch was filled
 };
 
 }  // namespace
 
 struct planb_server {
     planb_server_cfg_t cfg{};
-    planb_tableset_t* ts = nullptr;
     MultiLaunch launch;
+    DescLayout lay;
     std::vector<Table> tables;
+    std::vector<uint32_t> local;  // table id -> index among the filling launch's tables (or kNone)
     std::deque<Pending> queue;
     std::vector<Slot> slots;
     std::deque<planb_completion_t> done;
-    std::unordered_map<planb_fib_t*, int> retired;  // replaced FIBs -> launches still using them
     uint64_t used_bytes = 0;
     planb_server_stats_t stats{};
 };
 
 namespace {
 
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
 void server_release(planb_server_t* s)
 {
     for (auto& sl : s->slots) {
         if (sl.st) (void)hipStreamSynchronize(sl.st);
-        if (sl.done) (void)hipEventDestroy(sl.done);
+        sl.done.reset();
         if (sl.st) (void)hipStreamDestroy(sl.st);
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         if (sl.h_out) (void)hipHostFree(sl.h_out);
@@ -113,9 +129,7 @@ void server_release(planb_server_t* s)
         if (sl.d_desc) (void)hipFree(sl.d_desc);
     }
     for (auto& t : s->tables)
-        if (t.fib) free_fib_nosync(t.fib);
-    for (auto& r : s->retired) free_fib_nosync(r.first);
-    if (s->ts) planb_tableset_free(s->ts);
+        if (t.fib) planb_free(t.fib);
     delete s;
 }
 
@@ -154,11 +168,10 @@ int admit(planb_server_t* s, uint32_t id, bool* ok)
                 return PLANB_OK;
             }
             Table& v = s->tables[victim];
-            int rc = planb_tableset_set(s->ts, (uint32_t)victim, nullptr);
-            if (rc != PLANB_OK) return rc;
-            free_fib_nosync(v.fib);
+            planb_free(v.fib);  // idle: no launch of this server reads it
             s->used_bytes -= v.bytes;
             v.fib = nullptr;
+            ++v.gen;
             v.bytes = 0;
             ++s->stats.evictions;
         }
@@ -170,12 +183,7 @@ int admit(planb_server_t* s, uint32_t id, bool* ok)
     if (!f) return planb_last_status() ? planb_last_status() : PLANB_EDEVICE;
     int rc = PLANB_OK;
     if (s->cfg.learned && (rc = planb_train(f, nullptr, nullptr, nullptr)) != PLANB_OK) {
-        free_fib_nosync(f);
-        return rc;
-    }
-    rc = planb_tableset_set(s->ts, id, f);
-    if (rc != PLANB_OK) {
-        free_fib_nosync(f);
+        planb_free(f);
         return rc;
     }
     t.fib = f;
@@ -201,20 +209,11 @@ void finish_slot(planb_server_t* s, Slot& sl)
     }
     for (size_t k = 0; k < sl.tables.size(); ++k) {
         Table& tb = s->tables[sl.tables[k]];
-        planb_fib_t* f = sl.fibs[k];
-        if (tb.fib == f) {
-            --tb.inflight;
-        } else {  // replaced while in flight
-            auto it = s->retired.find(f);
-            if (it != s->retired.end() && --it->second == 0) {
-                free_fib_nosync(f);
-                s->retired.erase(it);
-            }
-        }
+        if (tb.gen == sl.gens[k]) --tb.inflight;  // else replaced meanwhile (and freed after this launch)
     }
     sl.bursts.clear();
     sl.tables.clear();
-    sl.fibs.clear();
+    sl.gens.clear();
     sl.busy = false;
 }
 
@@ -253,67 +252,115 @@ void run_copies(const std::vector<CopyJob>& jobs, size_t total)
     for (auto& t : th) t.join();
 }
 
+void complete_with_error(planb_server_t* s, const Pending& p, int status)
+{
+    planb_completion_t c{};
+    c.tag = p.tag;
+    c.table = p.table;
+    c.n = p.n;
+    c.submit_us = p.submit_us;
+    c.done_us = now_us();
+    c.status = status;
+    s->done.push_back(c);
+}
+
+// Packs queued bursts into one launch on the slot's stream.  A burst whose
+// table cannot be made resident (its rules fail to build, or it alone exceeds
+// the budget) completes at once with that error.  Nothing is committed to the
+// slot before the launch is enqueued: if enqueueing fails the bursts go back
+// to the front of the queue, in order, and the error is returned.
 int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
 {
     *launched = false;
-    const uint32_t maxb = s->cfg.max_bursts, maxl = s->cfg.max_lookups;
+    const uint32_t maxb = s->cfg.max_bursts, maxl = s->cfg.max_lookups, maxt = s->lay.max_tables;
     uint32_t nb = 0, na = 0;
-    BurstRec* desc = reinterpret_cast<BurstRec*>(sl.h_desc + 16);
+    BurstRec* desc = reinterpret_cast<BurstRec*>(sl.h_desc + s->lay.bursts);
     std::vector<char> blocked(s->tables.size(), 0);
     std::vector<CopyJob> copies;
+    std::vector<Pending> taken;
+    std::vector<uint32_t> tabs;
+    std::vector<uint64_t> gens;
+    std::vector<planb_fib_t*> fibs;
+    auto rollback = [&](int rc) {
+        for (auto it = taken.rbegin(); it != taken.rend(); ++it) s->queue.push_front(std::move(*it));
+        for (uint32_t id : tabs) {
+            --s->tables[id].inflight;
+            s->local[id] = kNone;
+        }
+        return rc;
+    };
     for (auto it = s->queue.begin(); it != s->queue.end() && nb < maxb;) {
         Pending& p = *it;
-        if (na + p.n > maxl) {
-            if (na == 0) return fail(PLANB_ERANGE, "burst larger than max_lookups");
-            break;
-        }
+        if (na + p.n > maxl) break;  // submit bounds n by max_lookups, so it fits an empty launch
         if (blocked[p.table]) {
             ++it;
             continue;
         }
+        if (s->local[p.table] == kNone && tabs.size() == maxt) break;
         bool ok = true;
         int rc = admit(s, p.table, &ok);
-        if (rc != PLANB_OK) return rc;
+        if (rc != PLANB_OK) {
+            complete_with_error(s, p, rc);
+            it = s->queue.erase(it);
+            continue;
+        }
         if (!ok) {  // keep it queued until memory frees up
             blocked[p.table] = 1;
             ++it;
             continue;
         }
         Table& t = s->tables[p.table];
+        if (s->local[p.table] == kNone) {
+            s->local[p.table] = (uint32_t)tabs.size();
+            tabs.push_back(p.table);
+            gens.push_back(t.gen);
+            fibs.push_back(t.fib);
+            ++t.inflight;  // no eviction of this table while the launch is built or runs
+        }
         copies.push_back(CopyJob{sl.h_in + na, p.addrs, (size_t)p.n * sizeof(planb_addr_t)});
-        desc[nb] = BurstRec{p.table, p.n, reinterpret_cast<const u64x2*>(sl.d_in + na), sl.d_out + na};
+        desc[nb] = BurstRec{s->local[p.table], p.n, reinterpret_cast<const u64x2*>(sl.d_in + na), sl.d_out + na};
         p.offset = na;
         na += p.n;
         ++nb;
-        if (std::find(sl.tables.begin(), sl.tables.end(), p.table) == sl.tables.end()) {
-            sl.tables.push_back(p.table);
-            sl.fibs.push_back(t.fib);
-            ++t.inflight;
-        }
         t.last_use = now_us();
-        sl.bursts.push_back(std::move(p));
+        taken.push_back(std::move(p));
         it = s->queue.erase(it);
     }
-    if (nb == 0) return PLANB_OK;
-    run_copies(copies, (size_t)na * sizeof(planb_addr_t));
-    if (s->launch.fn == nullptr) {  // first launch: the table set now knows fanout and key width
-        int rc = s->cfg.learned ? tableset_plan_learned(s->ts, maxb, &s->launch) : tableset_plan(s->ts, maxb, &s->launch);
-        if (rc != PLANB_OK) return rc;
+    if (nb == 0) return rollback(PLANB_OK);
+    // this launch's own copy of its tables' descriptors
+    TreeDesc* trees = reinterpret_cast<TreeDesc*>(sl.h_desc + s->lay.trees);
+    ModelDesc* models = reinterpret_cast<ModelDesc*>(sl.h_desc + s->lay.models);
+    for (size_t k = 0; k < tabs.size(); ++k) {
+        trees[k] = fibs[k]->desc;
+        trees[k].lds_levels = 0;  // the multi-FIB kernels stage no tree levels
+        trees[k].lds_slots = 0;
+        models[k] = ready_model_desc(fibs[k]);
     }
-    const BurstRec* d_bursts = reinterpret_cast<const BurstRec*>(sl.d_desc + 16);
-    const uint32_t* d_count = reinterpret_cast<const uint32_t*>(sl.d_desc);
+    run_copies(copies, (size_t)na * sizeof(planb_addr_t));
     std::memcpy(sl.h_desc, &nb, sizeof(uint32_t));
+    const BurstRec* d_bursts = reinterpret_cast<const BurstRec*>(sl.d_desc + s->lay.bursts);
+    const TreeDesc* d_trees = reinterpret_cast<const TreeDesc*>(sl.d_desc + s->lay.trees);
+    const ModelDesc* d_models = reinterpret_cast<const ModelDesc*>(sl.d_desc + s->lay.models);
+    const uint32_t* d_count = reinterpret_cast<const uint32_t*>(sl.d_desc);
+    const uint32_t nt = (uint32_t)tabs.size();
     hipError_t e;
     if ((e = hipMemcpyAsync(sl.d_in, sl.h_in, (size_t)na * 16, hipMemcpyHostToDevice, sl.st)) != hipSuccess ||
-        (e = hipMemcpyAsync(sl.d_desc, sl.h_desc, 16 + (size_t)nb * sizeof(BurstRec), hipMemcpyHostToDevice, sl.st)) !=
-            hipSuccess ||
-        (e = s->cfg.learned ? launch_multi_learned(s->launch, tableset_device(s->ts), tableset_models(s->ts),
-                                                   tableset_capacity(s->ts), d_bursts, d_count, maxb, nullptr, sl.st)
-                            : launch_multi(s->launch, tableset_device(s->ts), tableset_capacity(s->ts), d_bursts,
-                                           d_count, maxb, sl.st)) != hipSuccess ||
+        (e = hipMemcpyAsync(sl.d_desc, sl.h_desc, s->lay.bytes, hipMemcpyHostToDevice, sl.st)) != hipSuccess ||
+        (e = s->cfg.learned ? launch_multi_learned(s->launch, d_trees, d_models, nt, d_bursts, d_count, maxb, nullptr,
+                                                   sl.st)
+                            : launch_multi(s->launch, d_trees, nt, d_bursts, d_count, maxb, sl.st)) != hipSuccess ||
         (e = hipMemcpyAsync(sl.h_out, sl.d_out, (size_t)na * 2, hipMemcpyDeviceToHost, sl.st)) != hipSuccess ||
-        (e = hipEventRecord(sl.done, sl.st)) != hipSuccess)
-        return fail_hip(e, "server launch");
+        (e = hipEventRecord(sl.done->ev, sl.st)) != hipSuccess) {
+        // work already enqueued on the stream may still read the staging buffers:
+        // wait for it before they can be refilled
+        (void)hipStreamSynchronize(sl.st);
+        return rollback(fail_hip(e, "server launch"));
+    }
+    for (planb_fib_t* f : fibs) note_shared_use(f->uses, sl.st, sl.done);  // frees wait for this launch
+    for (uint32_t id : tabs) s->local[id] = kNone;
+    sl.bursts = std::move(taken);
+    sl.tables = std::move(tabs);
+    sl.gens = std::move(gens);
     sl.busy = true;
     ++s->stats.launches;
     s->stats.bursts += nb;
@@ -355,19 +402,25 @@ planb_server_t* planb_server_create(const planb_server_cfg_t* cfg_in)
     }
     s->cfg = cfg;
     s->tables.resize(cfg.max_tables);
-    s->ts = planb_tableset_create(cfg.max_tables);
-    if (!s->ts) {
+    s->local.assign(cfg.max_tables, kNone);
+    s->lay = DescLayout(cfg.max_bursts, std::min(cfg.max_bursts, cfg.max_tables));
+    LookupTuning tu;
+    tu.kpl = cfg.fanout >= 16 ? 4 : 2;
+    tu.R = 2;
+    tu.block = 512;
+    const int kb = (int)cfg.key_bits / 8;
+    if ((cfg.learned ? plan_multi_learned((int)cfg.fanout, kb, cfg.max_bursts, &s->launch)
+                     : plan_multi((int)cfg.fanout, kb, tu, cfg.max_bursts, &s->launch)) != PLANB_OK) {
         server_release(s);
         return nullptr;
     }
-    // fix the table set's shape before planning the launch
-    planb_tableset_set_tuning(s->ts, cfg.fanout >= 16 ? 4 : 2, 2, 512);
     s->slots.resize(cfg.streams);
-    const size_t dbytes = 16 + (size_t)cfg.max_bursts * sizeof(BurstRec);
+    const size_t dbytes = s->lay.bytes;
     hipError_t e = hipSuccess;
     for (auto& sl : s->slots) {
+        sl.done = std::make_shared<UseEvent>();
         if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.done->ev, hipEventDisableTiming)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_in), (size_t)cfg.max_lookups * 16, 0)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_out), (size_t)cfg.max_lookups * 2, 0)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_desc), dbytes, 0)) != hipSuccess ||
@@ -399,17 +452,13 @@ int planb_server_set_table(planb_server_t* s, uint32_t id, const planb_addr_t* p
     long long m = planb_build_intervals(prefixes, lengths, next_hops, n, 0, nullptr, nullptr, 0);
     if (m < 0) return (int)m;
     Table& t = s->tables[id];
-    if (t.fib) {  // rebuild-and-swap: retire the live structure
-        int rc = planb_tableset_set(s->ts, id, nullptr);
-        if (rc != PLANB_OK) return rc;
+    if (t.fib) {  // rebuild-and-swap: retire the live structure, freed after the launches that read it
         s->used_bytes -= t.bytes;
-        if (t.inflight > 0)
-            s->retired[t.fib] = t.inflight;
-        else
-            free_fib_nosync(t.fib);
+        planb_free(t.fib);
         t.fib = nullptr;
         t.bytes = 0;
         t.inflight = 0;
+        ++t.gen;
     }
     t.registered = true;
     t.m = (uint64_t)m;
@@ -443,7 +492,7 @@ int planb_server_poll(planb_server_t* s, planb_completion_t* out, uint32_t cap, 
     for (;;) {
         for (auto& sl : s->slots) {
             if (!sl.busy) continue;
-            hipError_t q = hipEventQuery(sl.done);
+            hipError_t q = hipEventQuery(sl.done->ev);
             if (q == hipSuccess) {
                 finish_slot(s, sl);
             } else if (q != hipErrorNotReady) {

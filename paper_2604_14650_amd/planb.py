@@ -275,19 +275,53 @@ def _dev_ptr(t, what):
     return int(t)
 
 
+def _records(t) -> int | None:
+    """Records a tensor holds (None for a raw pointer)."""
+    if not hasattr(t, "data_ptr"):
+        return None
+    return t.shape[0] if t.dim() > 0 else 0
+
+
+def _check_io(addrs, out, n, rec_bytes: int, out_bytes: int, what: str = "out"):
+    """When tensors are passed, n must fit both of them and their element
+    layout must be the one the C call reads and writes; raw pointers are the
+    caller's responsibility."""
+    if n is None:
+        if not hasattr(addrs, "data_ptr"):
+            raise ValueError("n is required when addrs is a raw pointer")
+        n = addrs.shape[0]
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    if hasattr(addrs, "data_ptr"):
+        if rec_bytes == 16:
+            if addrs.dim() != 2 or addrs.shape[1] != 2 or addrs.element_size() != 8:
+                raise ValueError(f"addrs must be an (n, 2) tensor of 64-bit words, got {tuple(addrs.shape)} "
+                                 f"of {addrs.dtype}")
+        elif addrs.dim() != 1 or addrs.element_size() != rec_bytes:
+            raise ValueError(f"addrs must be a 1-D tensor of {rec_bytes}-byte addresses")
+        if n > addrs.shape[0]:
+            raise ValueError(f"n = {n} exceeds the {addrs.shape[0]} address records passed")
+    if out is None:
+        raise ValueError(f"{what} is required")
+    if hasattr(out, "data_ptr"):
+        if out.element_size() != out_bytes:
+            raise ValueError(f"{what} must hold {out_bytes}-byte elements, got {out.dtype}")
+        if n > out.numel():
+            raise ValueError(f"n = {n} exceeds the {out.numel()} elements of {what}")
+    return n
+
+
 def planb_lookup(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
     """addrs: device tensor (n, 2) int64 (the {hi, lo} records); out: device
     tensor (n,) int16/uint16 receiving next hops.  Asynchronous on ``stream``."""
-    if n is None:
-        n = addrs.shape[0]
+    n = _check_io(addrs, out, n, 16, 2)
     _check(_lib.planb_lookup(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), _stream_handle(stream)))
     return out
 
 
 def planb_lookup_index(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
     """Like planb_lookup, but out (n,) int32 receives interval indices."""
-    if n is None:
-        n = addrs.shape[0]
+    n = _check_io(addrs, out, n, 16, 4)
     _check(_lib.planb_lookup_index(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"),
                                    _stream_handle(stream)))
     return out
@@ -295,16 +329,14 @@ def planb_lookup_index(fib: Fib, addrs, n: int | None = None, out=None, stream=N
 
 def planb_lookup_v4(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
     """addrs: device tensor (n,) int32 of IPv4 addresses; the FIB must hold 32-bit keys."""
-    if n is None:
-        n = addrs.shape[0]
+    n = _check_io(addrs, out, n, 4, 2)
     _check(_lib.planb_lookup_v4(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), _stream_handle(stream)))
     return out
 
 
 def planb_lookup_bsearch(fib: Fib, addrs, n: int | None = None, out=None, stream=None):
     """Binary search over the sorted interval starts (ablation baseline); same results as planb_lookup."""
-    if n is None:
-        n = addrs.shape[0]
+    n = _check_io(addrs, out, n, 16, 2)
     _check(_lib.planb_lookup_bsearch(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"),
                                      _stream_handle(stream)))
     return out
@@ -496,8 +528,7 @@ def planb_train(fib: Fib, epochs: int = 0, batch: int = 0, lr: float = 0.0, segm
 
 
 def planb_lookup_learned(fib: Fib, addrs, n: int | None = None, out=None, fallback_count=None, stream=None):
-    if n is None:
-        n = addrs.shape[0]
+    n = _check_io(addrs, out, n, 16, 2)
     fb = _dev_ptr(fallback_count, "fallback_count") if fallback_count is not None else None
     _check(_lib.planb_lookup_learned(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), fb,
                                      _stream_handle(stream)))
@@ -522,15 +553,15 @@ def planb_model_get_params(fib: Fib) -> np.ndarray:
 
 
 def planb_model_predict(fib: Fib, addrs, n=None, y=None, stream=None):
-    if n is None:
-        n = addrs.shape[0]
+    n = _check_io(addrs, y, n, 16, 4, "y")
     _check(_lib.planb_model_predict(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(y, "y"), _stream_handle(stream)))
     return y
 
 
 def planb_model_grad(fib: Fib, samples, targets, n=None, grad=None, stream=None):
-    if n is None:
-        n = samples.shape[0]
+    n = _check_io(samples, targets, n, 16, 4, "targets")
+    if hasattr(grad, "data_ptr") and (grad.element_size() != 4 or grad.numel() < planb_model_num_params()):
+        raise ValueError("grad must hold planb_model_num_params() float32 values")
     _check(_lib.planb_model_grad(fib, _dev_ptr(samples, "samples"), _dev_ptr(targets, "targets"), n,
                                  _dev_ptr(grad, "grad"), _stream_handle(stream)))
     return grad
@@ -641,7 +672,7 @@ class Server:
         for i in range(k):
             c = self._comp[i]
             self._keep.pop(c.tag, None)
-            res.append((c.tag, c.table, c.n, c.submit_us, c.done_us))
+            res.append((c.tag, c.table, c.n, c.submit_us, c.done_us, c.status))
         return res
 
     def admit(self, table_id: int):

@@ -28,7 +28,7 @@ def replay(server: "P.Server", arrivals_s, tables, addrs, outs, timeout_s: float
         while nxt < n and sched[nxt] <= now:
             server.submit(int(tables[nxt]), addrs[nxt], outs[nxt], nxt)
             nxt += 1
-        for tag, _, _, _, done_us in server.poll(block=(nxt == n)):
+        for tag, _, _, _, done_us, _ in server.poll(block=(nxt == n)):
             lat[tag] = done_us - sched[tag]
             done += 1
         if now - t0 > timeout_s * 1e6:

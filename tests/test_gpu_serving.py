@@ -175,13 +175,33 @@ def test_server_tight_budget_admission_and_eviction(P, vrfs):
 
 
 def test_server_rejects_a_table_larger_than_the_budget(P, vrfs):
-    tabs, _ = vrfs
-    srv = P.Server(max_tables=2, streams=1, fanout=16, key_bits=64, memory_budget=4096)
-    srv.set_table(0, tabs[-1].prefixes, tabs[-1].lengths, tabs[-1].next_hops)
-    srv.submit(0, S.mixed_traffic(tabs[-1], 10, 0.5, 1), np.zeros(10, np.uint16), 0)
-    with pytest.raises(P.PlanbError) as e:
-        srv.poll(block=True)
-    assert e.value.code == P.PLANB_ERANGE
+    """A burst whose table alone exceeds the budget completes with
+    PLANB_ERANGE and an untouched output; bursts of a table that fits are
+    served beside it, and the server keeps serving after the error."""
+    tabs, tries = vrfs
+    small = P.planb_build(tabs[0].prefixes, tabs[0].lengths, tabs[0].next_hops, fanout=16, key_bits=64)
+    budget = P.planb_get_info(small)["key_bytes"] + P.planb_get_info(small)["value_bytes"] + 4096
+    small.close()
+    srv = P.Server(max_tables=2, streams=1, fanout=16, key_bits=64, memory_budget=budget)
+    srv.set_table(0, tabs[-1].prefixes, tabs[-1].lengths, tabs[-1].next_hops)  # too large for the budget
+    srv.set_table(1, tabs[0].prefixes, tabs[0].lengths, tabs[0].next_hops)
+    big_out = np.full(10, 7, np.uint16)
+    srv.submit(0, S.mixed_traffic(tabs[-1], 10, 0.5, 1), big_out, 0)
+    a1 = S.mixed_traffic(tabs[0], 500, 0.5, 2)
+    o1 = np.zeros(len(a1), np.uint16)
+    srv.submit(1, a1, o1, 1)
+    got = {}
+    while len(got) < 2:
+        for c in srv.poll(block=True):
+            got[c[0]] = c
+    assert got[0][5] == P.PLANB_ERANGE and (big_out == 7).all()
+    assert got[1][5] == P.PLANB_OK and np.array_equal(o1, tries[0].lookup(a1))
+    a2 = S.mixed_traffic(tabs[0], 300, 0.5, 3)  # polling again after the error
+    o2 = np.zeros(len(a2), np.uint16)
+    srv.submit(1, a2, o2, 2)
+    c = srv.poll(block=True)
+    assert [x[0] for x in c] == [2] and c[0][5] == P.PLANB_OK
+    assert np.array_equal(o2, tries[0].lookup(a2))
     srv.close()
 
 
@@ -205,6 +225,36 @@ def test_server_rebuild_and_swap(P, vrfs):
             got[c[0]] = c
     assert np.array_equal(o1, t_old.lookup(a1))
     assert np.array_equal(o2, t_new.lookup(a2))
+    srv.close()
+
+
+def test_server_swap_while_launches_are_queued(P, vrfs):
+    """A swap lands while launches of the old table are still enqueued
+    behind a large copy and kernel on the other slot stream; every burst
+    equals the oracle of the rules it was submitted under."""
+    tabs, tries = vrfs
+    old, new = tabs[5], tabs[0]  # the rebuilt rule set is small, so the swap itself is quick
+    srv = P.Server(max_tables=1, streams=2, max_bursts=16, max_lookups=1 << 20, fanout=16, key_bits=64)
+    srv.set_table(0, old.prefixes, old.lengths, old.next_hops)
+    srv.admit(0)
+    before = [S.mixed_traffic(old, 1 << 20, 0.5, 21), S.mixed_traffic(old, 2000, 0.5, 22)]
+    outs = [np.zeros(len(a), np.uint16) for a in before]
+    got = {}
+    for k, a in enumerate(before):
+        srv.submit(0, a, outs[k], k)
+        for c in srv.poll():  # each poll fills a free slot: both launches are now enqueued
+            got[c[0]] = c
+    srv.set_table(0, new.prefixes, new.lengths, new.next_hops)
+    after = S.mixed_traffic(new, 3000, 0.5, 23)
+    o_after = np.zeros(len(after), np.uint16)
+    srv.submit(0, after, o_after, 2)
+    while len(got) < 3:
+        for c in srv.poll(block=True):
+            got[c[0]] = c
+    assert all(c[5] == P.PLANB_OK for c in got.values())
+    for k, a in enumerate(before):
+        assert np.array_equal(outs[k], tries[5].lookup(a)), k
+    assert np.array_equal(o_after, tries[0].lookup(after))
     srv.close()
 
 

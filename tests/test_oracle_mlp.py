@@ -132,3 +132,171 @@ def test_planted_gradient_mistake_is_caught():
     v, yt = torch_forward(vec, X)
     torch.mean((yt - torch.tensor(t)) ** 2).backward()
     assert not np.allclose(_mutant_no_relu_mask(vec, X, t), v.grad.numpy(), rtol=1e-6, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# The bfloat16 rounding path, pinned against an independent construction.
+#
+# The model's rounding rule, stated once: a tensor is rounded to bfloat16
+# exactly where it enters a matrix-core product as an operand -- the weights
+# W1, W2 and w3 (stored bf16), the layer-2 input h1 in the forward pass, and,
+# in the backward pass, the layer errors dz2 and dz1 that enter the
+# weight-gradient products (dz2 also enters the back-propagation product
+# dz2 . W2).  Bias gradients, the output layer's gradient and every
+# accumulation stay in float.
+#
+# Below, that rule is written with torch's own bfloat16 conversion and torch
+# float64 autograd: QF rounds in the forward pass and is transparent to the
+# gradient (weights, h1); QB is the identity forward and rounds the error that
+# flows back through it (placed on a layer's matrix product, before its bias
+# is added, so the bias gradient sees the unrounded error).  Autograd then
+# derives every gradient from the chain rule, with no hand-written backward.
+# ---------------------------------------------------------------------------
+
+
+def _bf16_t(x):
+    return x.to(torch.bfloat16).to(torch.float64)
+
+
+class _QF(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        return _bf16_t(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _QB(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return _bf16_t(g)
+
+
+RULE = dict(w_round=True, h1_round=True, h2_round=False, dz2_round=True, dz1_round=True,
+            bias_sees_rounded=False, w3_round=True)
+
+
+def torch_rounded_loss_and_grad(vec, X, t, **over):
+    """Loss, gradient (flat, oracle order) and y of the rounded model built
+    from the rule above; keyword overrides plant one misplaced rounding."""
+    r = dict(RULE, **over)
+    ident = lambda z: z  # noqa: E731
+    qf_w = _QF.apply if r["w_round"] else ident
+    qb1 = _QB.apply if r["dz1_round"] else ident
+    qb2 = _QB.apply if r["dz2_round"] else ident
+    v = torch.tensor(vec, dtype=torch.float64, requires_grad=True)
+    o, P = 0, {}
+    for name, shape in mlp.SHAPES:
+        k = int(np.prod(shape))
+        P[name] = v[o:o + k].reshape(shape)
+        o += k
+    Xt = torch.tensor(X, dtype=torch.float64)
+    W1, W2 = qf_w(P["W1"]), qf_w(P["W2"])
+    w3 = _QF.apply(P["w3"]) if r["w3_round"] else P["w3"]
+    if r["bias_sees_rounded"]:
+        z1 = qb1(Xt @ W1.T + P["b1"])
+    else:
+        z1 = qb1(Xt @ W1.T) + P["b1"]
+    h1 = torch.relu(z1)
+    h1q = _QF.apply(h1) if r["h1_round"] else h1
+    if r["bias_sees_rounded"]:
+        z2 = qb2(h1q @ W2.T + P["b2"])
+    else:
+        z2 = qb2(h1q @ W2.T) + P["b2"]
+    h2 = torch.relu(z2)
+    if r["h2_round"]:
+        h2 = _QF.apply(h2)
+    y = h2 @ w3 + P["b3"][0]
+    loss = torch.mean((y - torch.tensor(t, dtype=torch.float64)) ** 2)
+    loss.backward()
+    return loss.item(), v.grad.numpy().copy(), y.detach().numpy()
+
+
+def _rounding_case(seed, n=256):
+    vec = rand_params(seed)
+    X = mlp.features(S.uniform_2000_3(np.random.default_rng(seed + 1), n))
+    t = np.random.default_rng(seed + 2).random(n)
+    return vec, X, t
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_rounded_path_matches_independent_construction(seed):
+    vec, X, t = _rounding_case(seed)
+    loss_t, g_t, y_t = torch_rounded_loss_and_grad(vec, X, t)
+    y_o, _ = mlp.forward(vec, X, rounding=True)
+    loss_o, g_o = mlp.loss_and_grad(vec, X, t, rounding=True)
+    # same rounding decisions on both sides; only float64 summation order differs
+    assert np.allclose(y_o, y_t, rtol=1e-12, atol=1e-14)
+    assert abs(loss_o - loss_t) <= 1e-12 * max(1.0, abs(loss_t))
+    scale = np.abs(g_t).max()
+    assert np.allclose(g_o, g_t, rtol=1e-9, atol=1e-12 * scale)
+
+
+# Each planted mistake moves one rounding point; the oracle must differ from
+# it.  (Rounding dz1 before or after the ReLU mask is not among them: the mask
+# multiplies by 0 or 1, so the two orders give the same values.)
+MUTANTS = {
+    "h2 rounded": dict(h2_round=True),
+    "h1 not rounded": dict(h1_round=False),
+    "dz2 not rounded": dict(dz2_round=False),
+    "dz1 not rounded": dict(dz1_round=False),
+    "bias gradients from rounded errors": dict(bias_sees_rounded=True),
+    "w3 kept in float": dict(w3_round=False),
+    "W1/W2 kept in float": dict(w_round=False),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_misplaced_rounding_is_caught(name):
+    vec, X, t = _rounding_case(31)
+    _, g_o = mlp.loss_and_grad(vec, X, t, rounding=True)
+    y_o, _ = mlp.forward(vec, X, rounding=True)
+    _, g_m, y_m = torch_rounded_loss_and_grad(vec, X, t, **MUTANTS[name])
+    scale = np.abs(g_o).max()
+    same_grad = np.allclose(g_o, g_m, rtol=1e-6, atol=1e-9 * scale)
+    same_y = np.allclose(y_o, y_m, rtol=1e-9, atol=1e-12)
+    assert not (same_grad and same_y), name
+
+
+@pytest.mark.parametrize("n", [4096, 4096 + 9, 1033])
+def test_exact_case_is_exact_in_float32(n):
+    """The GPU gradient test's inputs (tests/mlp_exact.py): evaluated in
+    float32, in two different summation orders, every decision-feeding
+    quantity equals the float64 oracle's exactly, so a float32 kernel takes
+    the oracle's rounding and ReLU decisions."""
+    from mlp_exact import exact_case
+    vec, addrs, t = exact_case(40 + n % 7, n)
+    X = mlp.features(addrs)
+    _, _, q = mlp.loss_and_grad(vec, X, t.astype(np.float64), parts=True)
+    p = mlp.model_weights(vec)
+    f32 = {k: v.astype(np.float32) for k, v in p.items()}
+    for rev in (False, True):
+        order = slice(None, None, -1) if rev else slice(None)
+
+        def mm(a, b):  # float32 products summed one term at a time, in this order
+            acc = np.zeros((a.shape[0], b.shape[1]), np.float32)
+            for k in range(a.shape[1])[order]:
+                acc += a[:, k:k + 1].astype(np.float32) * b[k:k + 1, :].astype(np.float32)
+            return acc
+
+        z1 = mm(X.astype(np.float32), f32["W1"].T) + f32["b1"]
+        h1q = mlp.bf16_round(np.maximum(z1, 0)).astype(np.float32)
+        assert np.array_equal(h1q, q["h1q"])
+        z2 = mm(h1q, f32["W2"].T) + f32["b2"]
+        h2 = np.maximum(z2, 0)
+        assert np.array_equal(h2, q["h2"])
+        y = mm(h2, f32["w3"][:, None])[:, 0] + f32["b3"][0]
+        assert np.array_equal(y, q["y"])
+        dy = (y - t) * np.float32(2.0 / n)
+        dz2 = np.where(h2 > 0, dy[:, None] * f32["w3"][None, :], np.float32(0))
+        dz2q = mlp.bf16_round(dz2).astype(np.float32)
+        assert np.array_equal(dz2q, q["dz2q"])
+        dh1 = mm(dz2q, f32["W2"])
+        dz1 = np.where(q["h1q"] > 0, dh1, np.float32(0))
+        assert np.array_equal(mlp.bf16_round(dz1), q["dz1q"])
