@@ -13,8 +13,9 @@
  *    of the current HIP device (hipMalloc, or a torch CUDA tensor).
  *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *    Lookup calls only enqueue work: results are valid after the stream is
- *    synchronised.  They never allocate or synchronise, so they can be
- *    captured into a HIP graph.
+ *    synchronised.  They never synchronise, and none allocates except
+ *    planb_lookup_learned, which takes its fallback queue from the
+ *    stream-ordered pool.
  *  - Functions returning int give PLANB_OK (0) or a negative planb_status;
  *    functions returning a pointer give NULL on failure.  On failure
  *    planb_last_error() returns a message for the calling thread.
@@ -365,11 +366,21 @@ typedef struct planb_train_report {
  * table.  Synchronises `stream`.  report may be NULL. */
 int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg, void* stream, planb_train_report_t* report);
 
-/* Exact lookup through the model (see above); fallback_count (device uint32,
- * may be NULL) is incremented by the number of addresses that fell back to the
- * tree -- the caller zeroes it.  PLANB_EINVAL if the FIB has no trained model. */
+/* Exact lookup through the model (see above).  The lookups whose window check
+ * fails are appended to a fallback queue in scratch device memory (a counter
+ * and one 4-byte entry per lookup: 256 + 4n bytes, allocated with
+ * hipMallocAsync on `stream` and freed with hipFreeAsync behind the work, so
+ * the host never waits); a second kernel then runs the tree descent for the
+ * queued lookups.  fallback_count (device uint32, may be NULL) is incremented
+ * by the number of lookups that fell back -- the caller zeroes it.
+ *   addrs  device, n records, 16-byte aligned;  out: device, n uint16
+ *   n      0 is a no-op; must be < 2^32
+ * Returns PLANB_OK, PLANB_EINVAL (no trained model, NULL or misaligned
+ * pointer), PLANB_ERANGE, PLANB_ENOMEM (the queue could not be allocated),
+ * PLANB_EDEVICE. */
 int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
                          uint32_t* fallback_count, void* stream);
+
 
 /* Model access (tests, checkpoints).  The flat parameter vector holds W1
  * (64 x 16, row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1):

@@ -14,7 +14,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
+#include <string>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -174,10 +176,20 @@ constexpr int kLearnBlock = 256;
 // batch of n (4 MFMA tiles of 16), then one lane per address for the window
 // search, verification and fallback.  R holds the model's weight operands and
 // sb1/sb2/sw3 its biases and output weights as float.
-template <int B, int KB>
+// Lookups whose window check fails: with QUEUE they are appended to a queue
+// in scratch memory and searched afterwards by fallback_kernel, so that a
+// wavefront never waits for one lane's whole-tree descent; without it (the
+// multi-FIB kernel) the failing lanes descend the tree in place.
+struct FallbackQueue {
+    uint32_t* count;  // entries appended (zeroed before the lookup)
+    uint32_t* idx;    // address index of each entry; cap entries
+    uint32_t cap;     // >= the lookups of the launch
+};
+
+template <int B, int KB, bool QUEUE>
 __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const MlpRegs& R, const float* sb1,
                                     const float* sb2, const float* sw3, float b3, const u64x2* addrs, uint64_t base,
-                                    uint64_t n, uint16_t* out, uint32_t* fallbacks)
+                                    uint64_t n, uint16_t* out, uint32_t* fallbacks, const FallbackQueue& fq)
 {
     using KF = KeyFmt<KB>;
     const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
@@ -219,11 +231,25 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     }
     const uint64_t i = base + l;
     const bool need = !ok && i < n;
-    if (need) j = descend_lane<B, KB>(t, xhi, xlo);
-    if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
-    if (fallbacks) {
+    if constexpr (QUEUE) {
+        // one atomic per wavefront reserves the queue entries of its failing lanes
         const uint64_t mask = __ballot(need);
-        if (l == 0 && mask) atomicAdd(fallbacks, (uint32_t)__popcll(mask));
+        if (mask) {
+            const int first_lane = __builtin_ctzll(mask);
+            uint32_t first = 0;
+            if (l == first_lane) first = atomicAdd(fq.count, (uint32_t)__popcll(mask));
+            first = (uint32_t)__builtin_amdgcn_readlane((int)first, first_lane);
+            const uint32_t slot = first + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
+            if (need && slot < fq.cap) fq.idx[slot] = (uint32_t)i;  // cap >= n: always taken
+        }
+        if (ok && i < n) __builtin_nontemporal_store(t.vals[j], out + i);
+    } else {
+        if (need) j = descend_lane<B, KB>(t, xhi, xlo);
+        if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
+        if (fallbacks) {
+            const uint64_t mask = __ballot(need);
+            if (l == 0 && mask) atomicAdd(fallbacks, (uint32_t)__popcll(mask));
+        }
     }
 }
 
@@ -231,7 +257,7 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
 template <int B, int KB>
 __global__ void __launch_bounds__(kLearnBlock)
 learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out,
-               uint32_t* __restrict__ fallbacks)
+               FallbackQueue fq)
 {
     __shared__ float sb1[kH], sb2[kH], sw3[kH];
     stage_small(M, sb1, sb2, sw3);
@@ -242,7 +268,29 @@ learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_
     const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
     for (uint64_t base = wave * 64; base < n; base += nwaves * 64)
-        learned_step<B, KB>(t, M, R, sb1, sb2, sw3, b3, addrs, base, n, out, fallbacks);
+        learned_step<B, KB, true>(t, M, R, sb1, sb2, sw3, b3, addrs, base, n, out, nullptr, fq);
+}
+
+// Clears the fallback queue before a learned lookup (a kernel, not a memset,
+// so that the sequence can be captured into a graph).
+__global__ void queue_reset_kernel(uint32_t* count)
+{
+    if (threadIdx.x == 0) *count = 0;
+}
+
+// The tree descent for the queued lookups; adds their number to fallbacks.
+template <int B, int KB>
+__global__ void __launch_bounds__(kLearnBlock)
+fallback_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint16_t* __restrict__ out, FallbackQueue fq,
+                uint32_t* __restrict__ fallbacks)
+{
+    const uint32_t c = min(*fq.count, fq.cap);
+    if (fallbacks && c && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(fallbacks, c);
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x) {
+        const uint32_t i = fq.idx[k];
+        const u64x2 a = __builtin_nontemporal_load(addrs + i);
+        __builtin_nontemporal_store(t.vals[descend_lane<B, KB>(t, a.x, a.y)], out + i);
+    }
 }
 
 // Learned lookups of bursts that each name a table: tiles of 64 addresses
@@ -296,7 +344,7 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             loaded = br.table;
         }
-        learned_step<B, KB>(t, M, R, sb1, sb2, sw3, b3, addrs, base, br.n, out, fallbacks);
+        learned_step<B, KB, false>(t, M, R, sb1, sb2, sw3, b3, addrs, base, br.n, out, fallbacks, FallbackQueue{});
         __builtin_amdgcn_wave_barrier();  // the next tile may restage the vectors
     }
 }
@@ -570,24 +618,31 @@ struct LearnedModel {
 
 namespace {
 
-template <int B, int KB>
-struct LearnedKernel {
-    static void* get() { return reinterpret_cast<void*>(learned_kernel<B, KB>); }
+// The two kernels of a learned lookup for one (fanout, key width).
+struct LearnedFns {
+    void* lookup = nullptr;
+    void* fallback = nullptr;
 };
 
-template <int B>
-void* learned_by_kb(int kb)
+template <int B, int KB>
+LearnedFns learned_fns()
 {
-    return kb == 4 ? LearnedKernel<B, 4>::get() : kb == 8 ? LearnedKernel<B, 8>::get() : LearnedKernel<B, 16>::get();
+    return {reinterpret_cast<void*>(learned_kernel<B, KB>), reinterpret_cast<void*>(fallback_kernel<B, KB>)};
 }
 
-void* pick_learned(int B, int kb)
+template <int B>
+LearnedFns learned_by_kb(int kb)
+{
+    return kb == 4 ? learned_fns<B, 4>() : kb == 8 ? learned_fns<B, 8>() : learned_fns<B, 16>();
+}
+
+LearnedFns pick_learned(int B, int kb)
 {
     switch (B) {
     case 8: return learned_by_kb<8>(kb);
     case 16: return learned_by_kb<16>(kb);
     case 32: return learned_by_kb<32>(kb);
-    default: return nullptr;
+    default: return {};
     }
 }
 
@@ -817,6 +872,59 @@ hipError_t launch_multi_learned(const MultiLaunch& L, const TreeDesc* tables, co
     return hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, L.lds, stream);
 }
 
+// ---------------------------------------------------------------- learned lookup launch
+constexpr size_t kQueueHeaderBytes = 256;  // the counter, then the entries (256-byte aligned)
+
+namespace {
+
+int learned_check(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, const uint16_t* out,
+                  const uint32_t* fallback_count)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    if (!fib->learned || !fib->learned->has_eps) return fail(PLANB_EINVAL, "the FIB has no trained model");
+    if (n == 0) return PLANB_OK;
+    if (n >= (1ull << 32)) return fail(PLANB_ERANGE, "batch too large (n must be < 2^32)");
+    if (!addrs || !out) return fail(PLANB_EINVAL, "NULL device pointer");
+    if (reinterpret_cast<uintptr_t>(addrs) % 16 || reinterpret_cast<uintptr_t>(out) % 2 ||
+        reinterpret_cast<uintptr_t>(fallback_count) % 4)
+        return fail(PLANB_EINVAL, "misaligned pointer");
+    return check_current_device(fib);
+}
+
+// Reset the queue, run the learned lookup, then the tree descent for the
+// queued lookups; fq.cap >= n.
+int launch_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
+                   uint32_t* fallback_count, FallbackQueue fq, hipStream_t st)
+{
+    const LearnedFns fns = pick_learned((int)fib->desc.fanout, (int)fib->desc.key_bytes);
+    if (!fns.lookup) return fail(PLANB_EINVAL, "no learned kernel for this fanout");
+    DevProps p;
+    hipError_t e = dev_props(&p);
+    if (e != hipSuccess) return fail_hip(e, "device properties");
+    int nb = 1;
+    if ((e = occupancy(fns.lookup, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
+    const uint64_t want = (n + (kLearnBlock / 64) * 64 - 1) / ((kLearnBlock / 64) * 64);
+    const unsigned grid = (unsigned)std::min<uint64_t>(want, (uint64_t)p.cus * nb);
+    TreeDesc t = fib->desc;
+    ModelDesc M = model_desc(fib->learned);
+    const u64x2* a = reinterpret_cast<const u64x2*>(addrs);
+    uint64_t nn = n;
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, fq.count);
+    void* args[] = {&t, &M, &a, &nn, &out, &fq};
+    if ((e = hipLaunchKernel(fns.lookup, dim3(grid), dim3(kLearnBlock), args, 0, st)) != hipSuccess)
+        return fail_hip(e, "learned lookup launch");
+    // the queue's length is known only on the device: a fixed grid walks it
+    const unsigned fgrid = (unsigned)std::min<uint64_t>((n + kLearnBlock - 1) / kLearnBlock, (uint64_t)p.cus * 2);
+    void* fargs[] = {&t, &a, &out, &fq, &fallback_count};
+    if ((e = hipLaunchKernel(fns.fallback, dim3(fgrid), dim3(kLearnBlock), fargs, 0, st)) != hipSuccess)
+        return fail_hip(e, "fallback launch");
+    if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "learned lookup launch");
+    note_use(fib->uses, st);
+    return PLANB_OK;
+}
+
+}  // namespace
+
 }  // namespace planb
 
 using namespace planb;
@@ -1029,35 +1137,24 @@ int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg_in, void* stream,
 int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
                          uint32_t* fallback_count, void* stream)
 {
-    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
-    if (!fib->learned || !fib->learned->has_eps) return fail(PLANB_EINVAL, "the FIB has no trained model");
-    if (n == 0) return PLANB_OK;
-    if (n >= (1ull << 40)) return fail(PLANB_ERANGE, "batch too large (n must be < 2^40)");
-    if (!addrs || !out) return fail(PLANB_EINVAL, "NULL device pointer");
-    if (reinterpret_cast<uintptr_t>(addrs) % 16 || reinterpret_cast<uintptr_t>(out) % 2 ||
-        reinterpret_cast<uintptr_t>(fallback_count) % 4)
-        return fail(PLANB_EINVAL, "misaligned pointer");
-    int rc = check_current_device(fib);
-    if (rc != PLANB_OK) return rc;
-    void* fn = pick_learned((int)fib->desc.fanout, (int)fib->desc.key_bytes);
-    if (!fn) return fail(PLANB_EINVAL, "no learned kernel for this fanout");
-    DevProps p;
-    hipError_t e = dev_props(&p);
-    if (e != hipSuccess) return fail_hip(e, "device properties");
-    int nb = 1;
-    if ((e = occupancy(fn, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
-    const uint64_t want = (n + (kLearnBlock / 64) * 64 - 1) / ((kLearnBlock / 64) * 64);
-    const uint64_t cap = (uint64_t)p.cus * nb;
-    const unsigned grid = (unsigned)std::min(want, cap);
-    TreeDesc t = fib->desc;
-    void* args_t = &t;
-    ModelDesc M = model_desc(fib->learned);
-    const u64x2* a = reinterpret_cast<const u64x2*>(addrs);
-    uint64_t nn = n;
-    void* args[] = {args_t, &M, &a, &nn, &out, &fallback_count};
-    e = hipLaunchKernel(fn, dim3(grid), dim3(kLearnBlock), args, 0, static_cast<hipStream_t>(stream));
-    if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? PLANB_OK : fail_hip(e, "learned lookup launch");
+    int rc = learned_check(fib, addrs, n, out, fallback_count);
+    if (rc != PLANB_OK || n == 0) return rc;
+    // the fallback queue: a counter and one entry per lookup, from the
+    // stream-ordered pool (allocated and freed in stream order: no host wait)
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void* scratch = nullptr;
+    const size_t bytes = kQueueHeaderBytes + (size_t)n * 4;
+    hipError_t e = hipMallocAsync(&scratch, bytes, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PLANB_ENOMEM, std::string("fallback queue (hipMallocAsync): ") + hipGetErrorString(e));
+    }
+    FallbackQueue fq{static_cast<uint32_t*>(scratch),
+                     reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) + kQueueHeaderBytes), (uint32_t)n};
+    rc = launch_learned(fib, addrs, n, out, fallback_count, fq, st);
+    e = hipFreeAsync(scratch, st);
+    if (rc == PLANB_OK && e != hipSuccess) rc = fail_hip(e, "freeing the fallback queue");
+    return rc;
 }
 
 }  // extern "C"
