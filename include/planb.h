@@ -15,7 +15,7 @@
  *    Lookup calls only enqueue work: results are valid after the stream is
  *    synchronised.  They never synchronise, and none allocates except
  *    planb_lookup_learned, which takes its fallback queue from the
- *    stream-ordered pool.
+ *    stream-ordered pool (planb_lookup_learned_noalloc allocates nothing).
  *  - Functions returning int give PLANB_OK (0) or a negative planb_status;
  *    functions returning a pointer give NULL on failure.  On failure
  *    planb_last_error() returns a message for the calling thread.
@@ -381,6 +381,20 @@ int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg, void* stream, pl
 int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
                          uint32_t* fallback_count, void* stream);
 
+/* planb_lookup_learned for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors, but the fallback queue is a
+ * fixed device array of the library (16 MiB + 256 bytes on each GPU it runs
+ * on, held until the process ends) instead of an allocation, so the call
+ * makes no hipMalloc/hipMallocAsync/hipFree and no allocating library call.
+ *   n  at most 4,194,304 (2^22) lookups per call; more gives PLANB_ERANGE.
+ * Every call on one GPU shares that array, which keeps the last call's
+ * contents (a kernel clears its counter at the start of each call): calls
+ * that overlap on one GPU -- on different streams, or from different host
+ * threads without ordering -- race and may return wrong next hops.  Order
+ * them on one stream. */
+int planb_lookup_learned_noalloc(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
+                                 uint32_t* fallback_count, void* stream);
 
 /* Model access (tests, checkpoints).  The flat parameter vector holds W1
  * (64 x 16, row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1):

@@ -875,7 +875,35 @@ hipError_t launch_multi_learned(const MultiLaunch& L, const TreeDesc* tables, co
 // ---------------------------------------------------------------- learned lookup launch
 constexpr size_t kQueueHeaderBytes = 256;  // the counter, then the entries (256-byte aligned)
 
+// The fallback queue of planb_lookup_learned_noalloc: a fixed device array
+// (per GPU, for the life of the process) instead of an allocation.  Host code
+// never passes `scratch` itself to a kernel: each device's address of it comes
+// from hipGetSymbolAddress (static_queue).
+constexpr size_t kStaticQueueEntries = size_t(1) << 22;  // 16 MiB of entries
+static __device__ __align__(256) uint32_t scratch[kQueueHeaderBytes / 4 + kStaticQueueEntries];
+
 namespace {
+
+std::mutex g_static_mu;
+std::vector<uint32_t*> g_static_ptr;  // by device ordinal; null until looked up
+
+// Address of `scratch` on `device` (the current device), looked up once per device.
+int static_queue(int device, uint32_t** out)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if ((int)g_static_ptr.size() <= device) g_static_ptr.resize(device + 1, nullptr);
+    if (!g_static_ptr[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(PLANB_EDEVICE, std::string("looking up the static fallback queue: ") + hipGetErrorString(e));
+        }
+        g_static_ptr[device] = static_cast<uint32_t*>(ptr);
+    }
+    *out = g_static_ptr[device];
+    return PLANB_OK;
+}
 
 int learned_check(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, const uint16_t* out,
                   const uint32_t* fallback_count)
@@ -1155,6 +1183,21 @@ int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size
     e = hipFreeAsync(scratch, st);
     if (rc == PLANB_OK && e != hipSuccess) rc = fail_hip(e, "freeing the fallback queue");
     return rc;
+}
+
+int planb_lookup_learned_noalloc(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
+                                 uint32_t* fallback_count, void* stream)
+{
+    int rc = learned_check(fib, addrs, n, out, fallback_count);
+    if (rc != PLANB_OK || n == 0) return rc;
+    if (n > kStaticQueueEntries)
+        return fail(PLANB_ERANGE, "planb_lookup_learned_noalloc takes at most " + std::to_string(kStaticQueueEntries) +
+                                      " lookups per call (its fallback queue is a fixed device array); got " +
+                                      std::to_string(n));
+    uint32_t* base = nullptr;
+    if ((rc = static_queue(fib->device, &base)) != PLANB_OK) return rc;
+    FallbackQueue fq{base, base + kQueueHeaderBytes / 4, (uint32_t)n};
+    return launch_learned(fib, addrs, n, out, fallback_count, fq, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

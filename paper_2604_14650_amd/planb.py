@@ -139,6 +139,7 @@ _sig("planb_graph_free", None, _vp)
 _sig("planb_autotune", ctypes.c_int, _vp, _vp, _sz, ctypes.c_uint32, _vp, ctypes.POINTER(planb_autotune_result_t))
 _sig("planb_train", ctypes.c_int, _vp, ctypes.POINTER(planb_train_cfg_t), _vp, ctypes.POINTER(planb_train_report_t))
 _sig("planb_lookup_learned", ctypes.c_int, _vp, _vp, _sz, _vp, _vp, _vp)
+_sig("planb_lookup_learned_noalloc", ctypes.c_int, _vp, _vp, _sz, _vp, _vp, _vp)
 _sig("planb_model_num_params", ctypes.c_int)
 _sig("planb_model_set_params", ctypes.c_int, _vp, _vp, ctypes.c_uint32)
 _sig("planb_model_get_params", ctypes.c_int, _vp, _vp)
@@ -532,6 +533,14 @@ def planb_lookup_learned(fib: Fib, addrs, n: int | None = None, out=None, fallba
     fb = _dev_ptr(fallback_count, "fallback_count") if fallback_count is not None else None
     _check(_lib.planb_lookup_learned(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), fb,
                                      _stream_handle(stream)))
+    return out
+
+
+def planb_lookup_learned_noalloc(fib: Fib, addrs, n: int | None = None, out=None, fallback_count=None, stream=None):
+    n = _check_io(addrs, out, n, 16, 2)
+    fb = _dev_ptr(fallback_count, "fallback_count") if fallback_count is not None else None
+    _check(_lib.planb_lookup_learned_noalloc(fib, _dev_ptr(addrs, "addrs"), n, _dev_ptr(out, "out"), fb,
+                                             _stream_handle(stream)))
     return out
 
 
