@@ -12,6 +12,10 @@ Legs (all on the same FIB and address batch unless stated):
              fallback rate and its speedup over the plain lookup
   batches    uneven batches (log-uniform 64..2^22) replayed one at a time:
              per-batch latency p50/p99 for plain launches and graph replays
+  uneven     the 1M-prefix FIB with /128 host routes (128-bit keys): 512
+             Zipf batches of 64..2^22, autotuned per size bucket; eager,
+             persistent and graph throughput, one-at-a-time latency, and
+             0 mismatches against the oracle over every batch
   serving    16 VRF-style tables (50k..500k prefixes) behind the serving
              runtime, Poisson bursts of 32..4096 at 25/50/80 % of capacity
   cpu        the binary-trie oracle over the whole batch on the host cores
@@ -57,6 +61,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-batches", action="store_true")
+    ap.add_argument("--skip-uneven", action="store_true", help="skip the 1M-prefix uneven-batch leg")
     ap.add_argument("--skip-ablation", action="store_true")
     ap.add_argument("--skip-rebuild", action="store_true")
     ap.add_argument("--skip-ipv4", action="store_true")
@@ -207,6 +212,111 @@ def batches_leg(P, h, d, n, out, seed=1044, count=96):
                      "glps": round(float(sizes.sum() / (v.sum() / 1e6) / 1e9), 3)}
     res["batches"] = int(count)
     res["sizes"] = "log-uniform 64..4194304"
+    return res
+
+
+def uneven_leg(P, log_fn, n_batches=512, seed=1033, buckets=(256, 4096, 1 << 16, 1 << 20, 1 << 22)):
+    """Uneven batches on the 1M-prefix FIB with 5 % /128 host routes (so 128-bit
+    keys): 512 batches, sizes log-uniform over 64..2^22, Zipf(1.1) destinations.
+    Launch shapes are autotuned per batch-size bucket (fanout by the summed
+    bucket times).  Timed: every batch as its own planb_lookup back to back,
+    all of them in one persistent launch, and in one graph replay; then each
+    batch alone (enqueue to completion, host clock) as a plain launch and as a
+    graph replay of its bucket's shape, and empty graph replays (the replay's
+    own cost).  Every mode's output is compared with the trie oracle over all
+    batches."""
+    import torch
+    import planb_synth as S
+    from oracle.trie import Trie, default_threads
+    from paper_2604_14650_amd import autotune
+    t0 = time.time()
+    fib = S.make_fib(S.LARGE, 33)
+    sizes, addrs = S.uneven_batches(fib, n_batches, 64, 1 << 22, seed)
+    total = int(sizes.sum())
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    log_fn(f"uneven: {len(fib)} prefixes, {n_batches} batches, {total} lookups ({time.time() - t0:.1f} s)")
+    t0 = time.time()
+    want = Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(addrs, default_threads())
+    log_fn(f"uneven: oracle over every batch ({time.time() - t0:.1f} s)")
+    d = upload(addrs)
+    del addrs
+    out = torch.empty(total, dtype=torch.int16, device="cuda")
+    h, rec = autotune.tune_sizes(fib.prefixes, fib.lengths, fib.next_hops, d, list(buckets), cache_path=None, reps=3,
+                                 log=log_fn)
+    info = P.planb_get_info(h)
+    table = P.planb_get_size_tunings(h)
+    mism = {}
+
+    def check(name):
+        torch.cuda.synchronize()
+        mism[name] = int((out.cpu().numpy().view(np.uint16) != want).sum())
+        out.fill_(-1)
+
+    def every_batch():
+        for i in range(n_batches):
+            P.planb_lookup(h, d[offs[i]:], int(sizes[i]), out[offs[i]:])
+
+    res = {"prefixes": len(fib), "intervals": info["intervals"], "key_bits": info["key_bits"], "depth": info["depth"],
+           "fanout": rec["fanout"], "batches": n_batches, "lookups": total,
+           "sizes": "log-uniform 64..4194304", "autotuned_buckets": rec["buckets"],
+           "fanout_sweep": rec["fanout_sweep"]}
+    ts = time_steps(every_batch, 5, 1)
+    res["eager_glps"] = round(total / (sum(ts) / len(ts)) / 1e9, 3)
+    check("eager")
+    desc = torch.from_numpy(np.frombuffer(bytes(P.batch_array(
+        [(d[offs[i]:], out[offs[i]:], int(sizes[i])) for i in range(n_batches)])), dtype=np.uint8).copy()).cuda()
+    cnt = torch.tensor([n_batches], dtype=torch.int32, device="cuda")
+    P.planb_set_tuning(h, **table[-1][1])  # the largest bucket's shape for launches over every batch
+    ts = time_steps(lambda: P.planb_lookup_batches(h, desc, cnt, n_batches), 5, 1)
+    res["persistent_glps"] = round(total / (sum(ts) / len(ts)) / 1e9, 3)
+    check("persistent")
+    g = P.Graph(h, n_batches)
+    every = [(d[offs[i]:], out[offs[i]:], int(sizes[i])) for i in range(n_batches)]
+    ts = time_steps(lambda: g.launch(every), 5, 1)
+    res["graph_glps"] = round(total / (sum(ts) / len(ts)) / 1e9, 3)
+    check("graph")
+    g.close()
+    # one batch at a time: plain launch (its bucket's shape) and a replay of a graph of its bucket's shape
+    graphs = []
+    for lo, tu in table:
+        P.planb_set_tuning(h, **tu)
+        graphs.append((lo, P.Graph(h, 1)))
+    stream = torch.cuda.current_stream()
+    lat = {"plain": [], "graph": []}
+    for i in range(n_batches):
+        a, o, m = d[offs[i]:], out[offs[i]:], int(sizes[i])
+        gi = max(k for k, (lo, _) in enumerate(graphs) if lo <= m)
+        for mode in ("plain", "graph", "plain", "graph"):  # the first of each is a warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if mode == "plain":
+                P.planb_lookup(h, a, m, o)
+            else:
+                graphs[gi][1].launch([(a, o, m)])
+            stream.synchronize()
+            lat[mode].append((time.perf_counter() - t1) * 1e6)
+    check("one_at_a_time")
+    empty = []
+    for _ in range(200):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        graphs[0][1].launch([])
+        stream.synchronize()
+        empty.append((time.perf_counter() - t1) * 1e6)
+    for _, g in graphs:
+        g.close()
+    bucket_of = np.searchsorted([lo for lo, _ in table], sizes, side="right") - 1
+    for mode, v in lat.items():
+        v = np.array(v[1::2])
+        r = {"p50_us": round(float(np.percentile(v, 50)), 2), "p99_us": round(float(np.percentile(v, 99)), 2),
+             "glps": round(float(total / (v.sum() / 1e6) / 1e9), 3)}
+        r["p50_us_by_bucket"] = {str(table[k][0]): round(float(np.percentile(v[bucket_of == k], 50)), 2)
+                                 for k in range(len(table)) if np.any(bucket_of == k)}
+        res[mode] = r
+    res["empty_graph_replay_p50_us"] = round(float(np.percentile(empty, 50)), 2)
+    res["mismatches_vs_oracle"] = mism
+    del d, desc
+    torch.cuda.empty_cache()
     return res
 
 
@@ -390,27 +500,59 @@ def rebuild_leg(P, reps=3):
     return res
 
 
-def cpu_btree_leg(fib, addrs, got):
-    """CPU linearized B+-tree baseline (the same image the GPU descends, searched
-    by the paper's batched branch-free CPU descent) on the host cores: the whole
-    batch on every core used, and one core on a 2^24-address sample."""
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": usable}
+
+
+def cpu_btree_leg(fib, addrs, got, warmup=3, reps=20, single_sample=1 << 24):
+    """The method on the host cores in the paper's own CPU design
+    (planb_cpu_tree_*: fanout 9, 8 keys per 64-byte node, vector compare +
+    popcount, batched and fully unrolled descent): 64-bit keys (the paper's
+    width, exact on this FIB) and 128-bit keys, over the whole batch on every
+    usable core and on one core over a 2^24-address sample; 3 warm-ups and 20
+    timed repetitions each, as in the paper's measurements.  Results are
+    compared with the GPU's."""
     from paper_2604_14650_amd import planb as P
-    from oracle.trie import default_threads
-    thr = default_threads()
-    tree = P.CpuTree(fib.prefixes, fib.lengths, fib.next_hops, fanout=16)
-    tree.lookup(addrs[:1 << 20], thr)  # warm-up
-    t0 = time.perf_counter()
-    res = tree.lookup(addrs, thr)
-    dt = time.perf_counter() - t0
-    one = addrs[:1 << 24]
-    t1 = time.perf_counter()
-    tree.lookup(one, 1)
-    dt1 = time.perf_counter() - t1
-    return {"value": round(addrs.shape[0] / dt / 1e9, 4), "unit": "GLPS", "cores": thr,
-            "kind": "linearized B+-tree (planb_cpu_lookup, fanout 16, 64-bit keys)",
-            "sample": f"the whole batch ({addrs.shape[0]} addresses), {thr} threads, {dt:.2f} s",
-            "single_core_mlps": round(one.shape[0] / dt1 / 1e6, 1),
-            "mismatches_vs_gpu": int((res != got).sum())}
+    cpu = host_cpu()
+    thr = cpu["nproc"]
+    res = {"kind": "linearized B+-tree in the paper's CPU design (planb_cpu_tree_*: fanout 9, 8 keys per node, "
+                   "vector compare + popcount, batched, unrolled)", "cpu": cpu["model"], "nproc": thr,
+           "warmup": warmup, "reps": reps}
+    out = np.empty(addrs.shape[0], dtype=np.uint16)
+    for kb in (64, 128):
+        tree = P.PaperCpuTree(fib.prefixes, fib.lengths, fib.next_hops, key_bits=kb)
+        r = {"isa": tree.isa, "depth": tree.depth}
+        for label, a, threads in (("all_cores", addrs, thr), ("one_core", addrs[:single_sample], 1)):
+            o = out[:a.shape[0]]
+            for _ in range(warmup):
+                tree.lookup(a, threads, out=o)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                tree.lookup(a, threads, out=o)
+            dt = (time.perf_counter() - t0) / reps
+            r[label] = {"glps": round(a.shape[0] / dt / 1e9, 4), "threads": threads, "addresses": int(a.shape[0]),
+                        "mismatches_vs_gpu": int((o != got[:a.shape[0]]).sum())}
+        tree.close()
+        res[f"keys_{kb}"] = r
+        log(f"cpu paper-design B+-tree, {kb}-bit keys: {r}")
+    res["value"] = res["keys_64"]["all_cores"]["glps"]
+    res["unit"] = "GLPS"
+    res["cores"] = thr
+    res["single_core_mlps"] = round(res["keys_64"]["one_core"]["glps"] * 1e3, 1)
+    return res
 
 
 def main():
@@ -494,10 +636,15 @@ def main():
             result["rebuild"] = rebuild_leg(P)
         if not args.skip_batches:
             result["batch_latency"] = batches_leg(P, h, d, n, out)
-            result["p99_batch_latency_us"] = result["batch_latency"]["graph"]["p99_us"]
             log(f"batches: {result['batch_latency']}")
         del d  # the IPv6 batch is no longer needed on the device
         torch.cuda.empty_cache()
+        if not args.skip_uneven:
+            result["uneven_batches"] = uneven_leg(P, log)
+            # batch latency as a user would submit: one plain launch per batch, enqueue to completion
+            result["p99_batch_latency_us"] = result["uneven_batches"]["plain"]["p99_us"]
+            result["p50_batch_latency_us"] = result["uneven_batches"]["plain"]["p50_us"]
+            log(f"uneven batches: {result['uneven_batches']}")
         if not args.skip_ipv4:
             result["ipv4"] = ipv4_leg(P, n, max(3, args.steps // 2))
             log(f"ipv4: {result['ipv4']}")

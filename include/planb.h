@@ -329,6 +329,31 @@ int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint3
                    planb_autotune_result_t* result);
 
 /*
+ * Launch shapes by call size (uneven batches, the paper's Section 3
+ * "Batching": a shape that suits 2^28 lookups is not the one for 64).
+ * planb_set_size_tunings installs count entries with strictly ascending
+ * min_lookups; planb_lookup and planb_lookup_index then run a call of n
+ * lookups with the tuning of the last entry whose min_lookups <= n, and with
+ * the FIB's own tuning (planb_set_tuning) below the first.  count = 0 clears
+ * the table.  Each tuning is checked as by planb_set_tuning (PLANB_EINVAL,
+ * PLANB_ERANGE; the table is unchanged on error).  Not synchronised with
+ * lookups running on other host threads.  planb_get_size_tunings copies up
+ * to cap entries (either array may be NULL) and returns the entry count.
+ *
+ * planb_autotune_sizes runs the autotuner (as planb_autotune, also trying
+ * shallower LDS staging below 2^16 lookups) on the first sizes[k] addresses
+ * of the device sample for each of count strictly ascending sizes (each in
+ * 1..n), reports bucket k's winner in results[k], and installs them as size
+ * tunings: bucket k serves calls from ceil(sqrt(sizes[k-1] * sizes[k]))
+ * lookups up (bucket 0 from 1).  The FIB's own tuning is left as it was.
+ */
+int planb_set_size_tunings(planb_fib_t* fib, const uint64_t* min_lookups, const planb_tuning_t* tunings,
+                           uint32_t count);
+int planb_get_size_tunings(const planb_fib_t* fib, uint64_t* min_lookups, planb_tuning_t* tunings, uint32_t cap);
+int planb_autotune_sizes(planb_fib_t* fib, const planb_addr_t* sample, size_t n, const uint64_t* sizes, uint32_t count,
+                         uint32_t reps, void* stream, planb_autotune_result_t* results);
+
+/*
  * Learned position model (an addition to the paper's method).  A
  * 16 -> 64 -> 64 -> 1 ReLU MLP reads the 16 address bytes (most significant
  * first) as byte/256 and predicts y ~ (interval index + 1/2) / m; W1, W2 and
@@ -590,6 +615,32 @@ long long planb_build_image(const planb_addr_t* starts, const uint16_t* next_hop
  */
 int planb_cpu_lookup(const void* image, const planb_info_t* info, const planb_addr_t* addrs, size_t n,
                      uint16_t* out, int threads);
+
+/*
+ * planb_cpu_tree_* -- host-core baseline in the paper's own CPU design
+ * (Section 3: "Parameter Tuning" b = 9, so 8 keys per 64-byte node;
+ * "Separation of Keys and Values"; Algorithm 1 and Listing 1's count of keys
+ * <= x per node by one vector compare and a popcount, "Vectorization and SIMD
+ * Acceleration"; "Batching"; "Branch-Free Traversal and Loop Unrolling").
+ * planb_cpu_tree_build lays out a fanout-9 linearized B+-tree over m sorted
+ * interval starts (host; starts[0] must be 0, strictly increasing) and keeps
+ * a copy of their next hops; key_bits is 64 (the paper's width: only exact,
+ * and only accepted, when every start's low word is zero) or 128 (a node's 8
+ * high words, then its 8 low words).  NULL on bad input or allocation failure.
+ * planb_cpu_tree_lookup searches n host addresses into n host next hops with
+ * `threads` threads (<= 0: every hardware thread), AVX-512 compares when the
+ * host has them, else AVX2 (planb_cpu_tree_isa says which: "avx512" or
+ * "avx2"); PLANB_OK or PLANB_EINVAL.  Host only: for measurements beside the
+ * GPU kernels; no GPU entry point calls it.
+ */
+typedef struct planb_cpu_tree planb_cpu_tree_t;
+planb_cpu_tree_t* planb_cpu_tree_build(const planb_addr_t* starts, const uint16_t* next_hops, size_t m,
+                                       uint32_t key_bits);
+int planb_cpu_tree_lookup(const planb_cpu_tree_t* tree, const planb_addr_t* addrs, size_t n, uint16_t* out,
+                          int threads);
+const char* planb_cpu_tree_isa(const planb_cpu_tree_t* tree);
+int planb_cpu_tree_depth(const planb_cpu_tree_t* tree);
+void planb_cpu_tree_free(planb_cpu_tree_t* tree);
 
 #ifdef __cplusplus
 }

@@ -2,8 +2,11 @@
 
 For each fanout it builds the FIB and lets the native planb_autotune time
 every compiled-in launch shape on a device-resident sample; the fastest
-(fanout, tuning) wins.  Results are cached in a JSON file keyed by a hash of
-the FIB, the key width requested and the sample's size bucket (log2), so a
+(fanout, tuning) wins.  ``tune_sizes`` does the same per batch-size bucket
+(native planb_autotune_sizes): the fanout with the least summed time over the
+buckets' sizes wins, and its per-bucket launch shapes are installed on the
+handle.  Results are cached in a JSON file keyed by a hash of the FIB, the key
+width requested and the sample's size bucket (log2) or the bucket sizes, so a
 rerun on the same FIB skips the trials.
 """
 from __future__ import annotations
@@ -78,6 +81,48 @@ def tune(prefixes, lengths, next_hops, sample, n: int | None = None, fanouts=(8,
                                         "lds_search")},
            "glps": round(r["glps"], 3), "fanout_glps": trials, "sample": n,
            "seconds": round(time.time() - t0, 2)}
+    if cache_path:
+        cache = _load(cache_path)
+        cache[key] = rec
+        _save(cache_path, cache)
+    return h, dict(rec, cached=False)
+
+
+def tune_sizes(prefixes, lengths, next_hops, sample, sizes, fanouts=(8, 16, 32), key_bits: int = 0,
+               cache_path: str | None = DEFAULT_CACHE, reps: int = 3, log=None):
+    """Per batch-size bucket launch shapes.  Returns (fib handle whose size
+    tunings are installed, record dict with the fanout and per-bucket picks)."""
+    sizes = [int(x) for x in sizes]
+    key = f"{fib_fingerprint(prefixes, lengths, next_hops)}:k{key_bits}:sizes{','.join(map(str, sizes))}:" \
+          f"f{','.join(map(str, fanouts))}"
+    cache = _load(cache_path) if cache_path else {}
+    rec = cache.get(key)
+    if rec:
+        h = P.planb_build(prefixes, lengths, next_hops, fanout=rec["fanout"], key_bits=key_bits)
+        P.planb_set_size_tunings(h, [(e["min_lookups"], e["tuning"]) for e in rec["buckets"]])
+        return h, dict(rec, cached=True)
+    best = None
+    sweep = {}
+    t0 = time.time()
+    for b in fanouts:
+        h = P.planb_build(prefixes, lengths, next_hops, fanout=b, key_bits=key_bits)
+        res = P.planb_autotune_sizes(h, sample, sizes, reps)
+        total_ms = sum(r["ms_per_call"] for r in res)
+        sweep[str(b)] = {"total_ms": round(total_ms, 4), "glps": [round(r["glps"], 3) for r in res]}
+        if log:
+            log(f"autotune sizes fanout {b}: {sweep[str(b)]}")
+        if best is None or total_ms < best[1]:
+            if best is not None:
+                best[0].close()
+            best = (h, total_ms, b, res)
+        else:
+            h.close()
+    h, total_ms, b, res = best
+    table = P.planb_get_size_tunings(h)
+    rec = {"fanout": b, "key_bits": P.planb_get_info(h)["key_bits"],
+           "buckets": [{"size": sizes[i], "min_lookups": table[i][0], "tuning": table[i][1],
+                        "glps": round(res[i]["glps"], 3)} for i in range(len(sizes))],
+           "fanout_sweep": sweep, "seconds": round(time.time() - t0, 2)}
     if cache_path:
         cache = _load(cache_path)
         cache[key] = rec

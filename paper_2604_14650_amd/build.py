@@ -19,6 +19,9 @@ OBJDIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["lookup.hip", "learned.hip", "batches.hip", "multi.hip", "build_device.hip"]
 CXX_SOURCES = ["api.cpp", "builder.cpp", "server.cpp", "cpu_btree.cpp", "lifetime.cpp"]
+# plain host C++ that uses no HIP at all (x86 vector intrinsics chosen at run time): the host compiler
+HOST_SOURCES = ["cpu_paper_tree.cpp"]
+CXX = os.environ.get("CXX", "g++")
 # host code of the CPU baseline: AVX2 vector compares (any x86-64 server since 2015)
 EXTRA_FLAGS = {"cpu_btree.cpp": ["-mavx2"]}
 
@@ -32,6 +35,8 @@ def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, src + ".o")
     if src.endswith(".hip"):
         cmd = [HIPCC, *HIP_ONLY, *COMMON, "-c", path, "-o", obj]
+    elif src in HOST_SOURCES:
+        cmd = [CXX, *COMMON, "-c", path, "-o", obj]
     else:  # host C++ that calls the HIP runtime: compiled as host-only HIP code
         cmd = [HIPCC, *COMMON, *EXTRA_FLAGS.get(src, []), "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,7 +48,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     """Compile every source (always) and link libplanb.so; returns its path."""
     os.makedirs(OBJDIR, exist_ok=True)
-    sources = [s for s in HIP_SOURCES + CXX_SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    sources = [s for s in HIP_SOURCES + CXX_SOURCES + HOST_SOURCES if os.path.exists(os.path.join(CSRC, s))]
     jobs = min(len(sources), max(1, min(8, os.cpu_count() or 1)))
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, sources))

@@ -42,22 +42,40 @@ int deepest_lds_levels(const Layout& lay, size_t key_bytes, size_t budget)
     return L;
 }
 
-void refresh_desc(planb_fib_t* f)
+TreeDesc make_desc(const planb_fib_t* f, int32_t lds_levels)
 {
-    TreeDesc& t = f->desc;
+    TreeDesc t{};
     t.keys = f->d_keys;
     t.key_bytes = f->key_bytes_per_slot;
     t.vals = f->d_vals;
     t.m_minus_1 = f->iv.starts.size() - 1;
     t.depth = f->lay.depth;
-    t.lds_levels = (uint32_t)f->lds_levels;
-    t.lds_slots = (uint32_t)f->lay.prefix_slots(f->lds_levels);
+    t.lds_levels = (uint32_t)lds_levels;
+    t.lds_slots = (uint32_t)f->lay.prefix_slots(lds_levels);
     t.fanout = f->lay.b;
     t.leaf_base = (uint32_t)f->lay.leaf_base();
     t.last_hop = f->iv.nh.empty() ? 0xFFFFu : f->iv.nh.back();
     for (int l = 0; l < kDevMaxLevels; ++l) {
         t.off[l] = l < (int)f->lay.depth ? (uint32_t)f->lay.offset[l] : 0;
         t.last[l] = l < (int)f->lay.depth ? (uint32_t)(f->lay.nodes[l] - 1) : 0;
+    }
+    return t;
+}
+
+void refresh_desc(planb_fib_t* f)
+{
+    f->desc = make_desc(f, f->lds_levels);
+    for (auto& s : f->size_tunings) s.desc = make_desc(f, s.lds_levels);
+}
+
+void shape_for(const planb_fib_t* f, uint64_t n, const LookupTuning** tu, const TreeDesc** desc)
+{
+    *tu = &f->tune;
+    *desc = &f->desc;
+    for (const auto& s : f->size_tunings) {
+        if (s.min_lookups > n) break;
+        *tu = &s.tune;
+        *desc = &s.desc;
     }
 }
 
@@ -339,7 +357,10 @@ int planb_lookup(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, ui
 {
     int rc = check_lookup_args(fib, addrs, n, out, 2);
     if (rc != PLANB_OK || n == 0) return rc;
-    hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, false, static_cast<hipStream_t>(stream));
+    const LookupTuning* tu;
+    const TreeDesc* desc;
+    shape_for(fib, n, &tu, &desc);
+    hipError_t e = launch_lookup(*desc, *tu, addrs, n, out, false, static_cast<hipStream_t>(stream));
     if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
@@ -366,7 +387,10 @@ int planb_lookup_index(const planb_fib_t* fib, const planb_addr_t* addrs, size_t
 {
     int rc = check_lookup_args(fib, addrs, n, out, 4);
     if (rc != PLANB_OK || n == 0) return rc;
-    hipError_t e = launch_lookup(fib->desc, fib->tune, addrs, n, out, true, static_cast<hipStream_t>(stream));
+    const LookupTuning* tu;
+    const TreeDesc* desc;
+    shape_for(fib, n, &tu, &desc);
+    hipError_t e = launch_lookup(*desc, *tu, addrs, n, out, true, static_cast<hipStream_t>(stream));
     if (e == hipSuccess) note_use(fib->uses, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PLANB_OK : fail_hip(e, "lookup launch");
 }
@@ -521,6 +545,39 @@ int planb_set_tuning(planb_fib_t* fib, const planb_tuning_t* tuning)
     fib->lds_levels = lds;
     refresh_desc(fib);
     return PLANB_OK;
+}
+
+int planb_set_size_tunings(planb_fib_t* fib, const uint64_t* min_lookups, const planb_tuning_t* tunings,
+                           uint32_t count)
+{
+    if (!fib || (count && (!min_lookups || !tunings))) return fail(PLANB_EINVAL, "NULL argument");
+    std::vector<planb_fib_t::SizeTuning> v;
+    for (uint32_t k = 0; k < count; ++k) {
+        if (k && min_lookups[k] <= min_lookups[k - 1])
+            return fail(PLANB_EINVAL, "min_lookups must be strictly ascending");
+        planb_fib_t::SizeTuning s{};
+        s.min_lookups = min_lookups[k];
+        int rc = validate_tuning(fib, tunings[k], &s.tune, &s.lds_levels);
+        if (rc != PLANB_OK) return rc;
+        s.desc = make_desc(fib, s.lds_levels);
+        v.push_back(s);
+    }
+    fib->size_tunings.swap(v);
+    return PLANB_OK;
+}
+
+int planb_get_size_tunings(const planb_fib_t* fib, uint64_t* min_lookups, planb_tuning_t* tunings, uint32_t cap)
+{
+    if (!fib) return fail(PLANB_EINVAL, "NULL fib");
+    const uint32_t n = (uint32_t)fib->size_tunings.size();
+    for (uint32_t k = 0; k < n && k < cap; ++k) {
+        const auto& s = fib->size_tunings[k];
+        if (min_lookups) min_lookups[k] = s.min_lookups;
+        if (tunings)
+            tunings[k] = planb_tuning_t{(uint32_t)s.tune.kpl, s.lds_levels, (uint32_t)s.tune.R, (uint32_t)s.tune.block,
+                                        s.tune.tops ? 2u : s.tune.bin ? 1u : 0u};
+    }
+    return (int)n;
 }
 
 int planb_get_tuning(const planb_fib_t* fib, planb_tuning_t* tuning)

@@ -60,6 +60,15 @@ struct planb_fib {
     planb::TreeDesc desc{};
     planb::LearnedModel* learned = nullptr;
     mutable planb::UseLog uses;  // streams whose enqueued work reads this FIB
+    // Launch shapes by call size (planb_set_size_tunings): a call of n lookups
+    // uses the last entry with min_lookups <= n, else tune / desc above.
+    struct SizeTuning {
+        uint64_t min_lookups;
+        planb::LookupTuning tune;
+        int32_t lds_levels;
+        planb::TreeDesc desc;
+    };
+    std::vector<SizeTuning> size_tunings;  // ascending min_lookups
 };
 
 namespace planb {
@@ -70,6 +79,12 @@ int fail(int code, const std::string& msg);
 int fail_hip(hipError_t e, const char* what);
 int check_current_device(const planb_fib_t* fib);
 void refresh_desc(planb_fib_t* f);
+// The tree descriptor of f with its top lds_levels levels staged in LDS.
+TreeDesc make_desc(const planb_fib_t* f, int32_t lds_levels);
+// Checks a public tuning against f (sets the error); out / lds_out receive it.
+int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning* out, int32_t* lds_out);
+// Launch shape and descriptor for a call of n lookups.
+void shape_for(const planb_fib_t* f, uint64_t n, const LookupTuning** tu, const TreeDesc** desc);
 void release_learned(planb_fib_t* f);  // frees the learned model, if any
 // Default launch shape (params' keys per lane / LDS levels, if set) and descriptor.
 int finish_fib(planb_fib_t* f, const planb_params_t& p);

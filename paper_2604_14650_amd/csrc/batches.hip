@@ -10,6 +10,7 @@
 // counters, atomics or memsets and can be captured into a graph once and
 // replayed with new batch descriptors.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -46,10 +47,6 @@ batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t*
     extern __shared__ uint4 lds_raw[];
     uint32_t* tile_off = reinterpret_cast<uint32_t*>(lds_raw + staged_tree_bytes<B, KB, TOPS>(t) / 16);  // max_batches + 1
     uint32_t* part = tile_off + max_batches + 1;                                                        // BS
-    if constexpr (TOPS)
-        D::stage_bottom_tops(t, lds_raw, threadIdx.x, BS);
-    else
-        D::stage(t, lds_raw, threadIdx.x, BS);
 
     const uint32_t nb = min(*count, max_batches);
     const uint32_t per = (nb + BS - 1) / BS;
@@ -73,8 +70,18 @@ batches_kernel(TreeDesc t, const BatchRec* __restrict__ batches, const uint32_t*
     if (threadIdx.x == BS - 1) tile_off[nb] = part[BS - 1];
     __syncthreads();
 
-    const auto* lds_keys = reinterpret_cast<const typename D::K*>(lds_raw);
+    // The grid is sized for the device (and fixed inside a graph); a
+    // workgroup that gets no tile of this launch skips the LDS staging, which
+    // would otherwise dominate launches of a few small batches.
     const uint32_t total = tile_off[nb];
+    if (blockIdx.x * (uint32_t)(BS / 64) >= total) return;
+    if constexpr (TOPS)
+        D::stage_bottom_tops(t, lds_raw, threadIdx.x, BS);
+    else
+        D::stage(t, lds_raw, threadIdx.x, BS);
+    __syncthreads();
+
+    const auto* lds_keys = reinterpret_cast<const typename D::K*>(lds_raw);
     const uint32_t nwaves = gridDim.x * (BS / 64);
     for (uint32_t tile = blockIdx.x * (BS / 64) + (threadIdx.x >> 6); tile < total; tile += nwaves) {
         uint32_t lo = 0, hi = nb;  // tile_off[lo] <= tile < tile_off[hi]
@@ -167,6 +174,74 @@ int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
     if ((e = occupancy(reinterpret_cast<const void*>(L->fn), tu.block, L->lds, &nb)) != hipSuccess)
         return fail_hip(e, "occupancy");
     L->grid = (unsigned)(p.cus * nb);
+    return PLANB_OK;
+}
+
+// Times every compiled-in tuning of the FIB's fanout and key width on the
+// first n sample addresses (one warm-up and reps timed calls each) and applies
+// the fastest.  Small calls (below 2^16 lookups) also try shallower LDS
+// staging, which costs them more than it saves.
+int autotune_core(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint32_t reps, hipStream_t st,
+                  planb_autotune_result_t* res)
+{
+    if (reps == 0) reps = 3;
+    const int max_lds = max_lds_bytes();
+    const uint32_t b = fib->lay.b;
+    int deepest = 0;
+    while (deepest < (int)fib->lay.depth &&
+           fib->lay.prefix_slots(deepest + 1) * (size_t)fib->key_bytes_per_slot <= (size_t)max_lds)
+        ++deepest;
+    const int shallowest = n < (1u << 16) ? 0 : std::max(0, deepest - 2);
+    std::vector<planb_tuning_t> cands;
+    for (uint32_t kpl = 1; kpl <= b && kpl <= 16; kpl *= 2) {
+        if (b / kpl > 32) continue;
+        for (uint32_t bin = 0; bin <= ((kpl == b || b / kpl == 2 || b / kpl == 4) ? 1u : 0u); ++bin)
+            for (uint32_t R : {1u, 2u, 4u})
+                for (uint32_t bs : {512u, 1024u})
+                    for (int lds = shallowest; lds <= deepest; ++lds)
+                        cands.push_back(planb_tuning_t{kpl, lds, R, bs, bin});
+        // the bottom internal level as key tops (64-bit key slots; skipped by
+        // planb_set_tuning when the levels do not fit a workgroup's LDS)
+        if (fib->key_bytes_per_slot == 8 && (b / kpl == 2 || b / kpl == 4))
+            for (uint32_t R : {1u, 2u, 4u})
+                for (uint32_t bs : {512u, 1024u}) cands.push_back(planb_tuning_t{kpl, deepest, R, bs, 2u});
+    }
+    uint16_t* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&out), n * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    planb_tuning_t saved{};
+    planb_get_tuning(fib, &saved);
+    planb_tuning_t best = saved;
+    float best_ms = -1.f;
+    uint32_t tried = 0;
+    for (size_t c = 0; e == hipSuccess && c < cands.size(); ++c) {
+        if (planb_set_tuning(fib, &cands[c]) != PLANB_OK) continue;
+        if (planb_lookup(fib, sample, n, out, st) != PLANB_OK) continue;  // warm-up
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (uint32_t r = 0; r < reps; ++r) planb_lookup(fib, sample, n, out, st);
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        ms /= (float)reps;
+        ++tried;
+        if (best_ms < 0.f || ms < best_ms) {
+            best_ms = ms;
+            best = cands[c];
+        }
+    }
+    if (out) (void)hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    planb_set_tuning(fib, &best);
+    clear_error();
+    if (e != hipSuccess) return fail_hip(e, "autotune timing");
+    if (best_ms < 0.f) return fail(PLANB_EDEVICE, "no candidate tuning could be timed");
+    res->tuning = best;
+    res->ms_per_call = best_ms;
+    res->glps = (float)((double)n / (best_ms * 1e-3) / 1e9);
+    res->candidates = tried;
     return PLANB_OK;
 }
 
@@ -313,64 +388,39 @@ int planb_autotune(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint3
         return fail(PLANB_EINVAL, "need a non-empty, 16-byte aligned device sample");
     int rc = check_current_device(fib);
     if (rc != PLANB_OK) return rc;
-    if (reps == 0) reps = 3;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int max_lds = max_lds_bytes();
-    const uint32_t b = fib->lay.b;
-    int deepest = 0;
-    while (deepest < (int)fib->lay.depth &&
-           fib->lay.prefix_slots(deepest + 1) * (size_t)fib->key_bytes_per_slot <= (size_t)max_lds)
-        ++deepest;
-    std::vector<planb_tuning_t> cands;
-    for (uint32_t kpl = 1; kpl <= b && kpl <= 16; kpl *= 2) {
-        if (b / kpl > 32) continue;
-        for (uint32_t bin = 0; bin <= ((kpl == b || b / kpl == 2 || b / kpl == 4) ? 1u : 0u); ++bin)
-            for (uint32_t R : {1u, 2u, 4u})
-                for (uint32_t bs : {512u, 1024u})
-                    for (int lds = std::max(0, deepest - 2); lds <= deepest; ++lds)
-                        cands.push_back(planb_tuning_t{kpl, lds, R, bs, bin});
-        // the bottom internal level as key tops (64-bit key slots; skipped by
-        // planb_set_tuning when the levels do not fit a workgroup's LDS)
-        if (fib->key_bytes_per_slot == 8 && (b / kpl == 2 || b / kpl == 4))
-            for (uint32_t R : {1u, 2u, 4u})
-                for (uint32_t bs : {512u, 1024u}) cands.push_back(planb_tuning_t{kpl, deepest, R, bs, 2u});
+    return autotune_core(fib, sample, n, reps, static_cast<hipStream_t>(stream), res);
+}
+
+int planb_autotune_sizes(planb_fib_t* fib, const planb_addr_t* sample, size_t n, const uint64_t* sizes, uint32_t count,
+                         uint32_t reps, void* stream, planb_autotune_result_t* results)
+{
+    if (!fib || !sizes || !results || count == 0) return fail(PLANB_EINVAL, "NULL argument or no sizes");
+    if (!sample || reinterpret_cast<uintptr_t>(sample) % 16) return fail(PLANB_EINVAL, "need a 16-byte aligned device sample");
+    for (uint32_t k = 0; k < count; ++k) {
+        if (sizes[k] == 0 || sizes[k] > n) return fail(PLANB_EINVAL, "every size must be in 1..n (the sample's length)");
+        if (k && sizes[k] <= sizes[k - 1]) return fail(PLANB_EINVAL, "sizes must be strictly ascending");
     }
-    uint16_t* out = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&out), n * sizeof(uint16_t));
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = check_current_device(fib);
+    if (rc != PLANB_OK) return rc;
     planb_tuning_t saved{};
     planb_get_tuning(fib, &saved);
-    planb_tuning_t best = saved;
-    float best_ms = -1.f;
-    uint32_t tried = 0;
-    for (size_t c = 0; e == hipSuccess && c < cands.size(); ++c) {
-        if (planb_set_tuning(fib, &cands[c]) != PLANB_OK) continue;
-        if (planb_lookup(fib, sample, n, out, stream) != PLANB_OK) continue;  // warm-up
-        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-        for (uint32_t r = 0; r < reps; ++r) planb_lookup(fib, sample, n, out, stream);
-        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        ms /= (float)reps;
-        ++tried;
-        if (best_ms < 0.f || ms < best_ms) {
-            best_ms = ms;
-            best = cands[c];
-        }
+    std::vector<planb_fib_t::SizeTuning> keep;
+    keep.swap(fib->size_tunings);  // time every candidate as the FIB's own tuning
+    std::vector<uint64_t> lo(count);
+    std::vector<planb_tuning_t> tu(count);
+    for (uint32_t k = 0; k < count && rc == PLANB_OK; ++k) {
+        rc = autotune_core(fib, sample, sizes[k], reps, static_cast<hipStream_t>(stream), &results[k]);
+        tu[k] = results[k].tuning;
+        // bucket k serves calls from the geometric midpoint below its size
+        lo[k] = k == 0 ? 1 : (uint64_t)std::ceil(std::sqrt((double)sizes[k - 1] * (double)sizes[k]));
+        if (k && lo[k] <= lo[k - 1]) lo[k] = lo[k - 1] + 1;
     }
-    if (out) (void)hipFree(out);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    planb_set_tuning(fib, &best);
-    if (e != hipSuccess) return fail_hip(e, "autotune timing");
-    if (best_ms < 0.f) return fail(PLANB_EDEVICE, "no candidate tuning could be timed");
-    res->tuning = best;
-    res->ms_per_call = best_ms;
-    res->glps = (float)((double)n / (best_ms * 1e-3) / 1e9);
-    res->candidates = tried;
-    return PLANB_OK;
+    planb_set_tuning(fib, &saved);
+    if (rc != PLANB_OK) {
+        fib->size_tunings.swap(keep);
+        return rc;
+    }
+    return planb_set_size_tunings(fib, lo.data(), tu.data(), count);
 }
 
 }  // extern "C"

@@ -137,6 +137,10 @@ _sig("planb_graph_create", _vp, _vp, ctypes.c_uint32)
 _sig("planb_graph_launch", ctypes.c_int, _vp, _vp, ctypes.c_uint32, _vp)
 _sig("planb_graph_free", None, _vp)
 _sig("planb_autotune", ctypes.c_int, _vp, _vp, _sz, ctypes.c_uint32, _vp, ctypes.POINTER(planb_autotune_result_t))
+_sig("planb_set_size_tunings", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32)
+_sig("planb_get_size_tunings", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32)
+_sig("planb_autotune_sizes", ctypes.c_int, _vp, _vp, _sz, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp,
+     _vp)
 _sig("planb_train", ctypes.c_int, _vp, ctypes.POINTER(planb_train_cfg_t), _vp, ctypes.POINTER(planb_train_report_t))
 _sig("planb_lookup_learned", ctypes.c_int, _vp, _vp, _sz, _vp, _vp, _vp)
 _sig("planb_lookup_learned_noalloc", ctypes.c_int, _vp, _vp, _sz, _vp, _vp, _vp)
@@ -377,11 +381,49 @@ def planb_set_tuning(fib: Fib, keys_per_lane: int, lds_levels: int = -1, lookups
     _check(_lib.planb_set_tuning(fib, ctypes.byref(t)))
 
 
+def _tuning_dict(t) -> dict:
+    return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels,
+            "lookups_per_group": t.lookups_per_group, "block_threads": t.block_threads, "lds_search": t.lds_search}
+
+
+def _tuning_struct(d: dict):
+    return planb_tuning_t(d["keys_per_lane"], d["lds_levels"], d["lookups_per_group"], d["block_threads"],
+                          d.get("lds_search", 0))
+
+
 def planb_get_tuning(fib: Fib) -> dict:
     t = planb_tuning_t()
     _check(_lib.planb_get_tuning(fib, ctypes.byref(t)))
-    return {"keys_per_lane": t.keys_per_lane, "lds_levels": t.lds_levels,
-            "lookups_per_group": t.lookups_per_group, "block_threads": t.block_threads, "lds_search": t.lds_search}
+    return _tuning_dict(t)
+
+
+def planb_set_size_tunings(fib: Fib, entries):
+    """entries: [(min_lookups, tuning dict), ...] with ascending min_lookups ([] clears)."""
+    k = len(entries)
+    lo = (ctypes.c_uint64 * max(k, 1))(*[int(e[0]) for e in entries])
+    tu = (planb_tuning_t * max(k, 1))(*[_tuning_struct(e[1]) for e in entries])
+    _check(_lib.planb_set_size_tunings(fib, lo, tu, k))
+
+
+def planb_get_size_tunings(fib: Fib) -> list:
+    k = _lib.planb_get_size_tunings(fib, None, None, 0)
+    if k < 0:
+        _check(k)
+    lo = (ctypes.c_uint64 * max(k, 1))()
+    tu = (planb_tuning_t * max(k, 1))()
+    _check(min(0, _lib.planb_get_size_tunings(fib, lo, tu, k)))
+    return [(int(lo[i]), _tuning_dict(tu[i])) for i in range(k)]
+
+
+def planb_autotune_sizes(fib: Fib, sample, sizes, reps: int = 3, stream=None) -> list:
+    """Autotunes each size on the sample's first addresses and installs the winners as size tunings."""
+    k = len(sizes)
+    sz = (ctypes.c_uint64 * max(k, 1))(*[int(x) for x in sizes])
+    res = (planb_autotune_result_t * max(k, 1))()
+    _check(_lib.planb_autotune_sizes(fib, _dev_ptr(sample, "sample"), int(sample.shape[0]), sz, k, reps,
+                                     _stream_handle(stream), res))
+    return [dict(_tuning_dict(r.tuning), size=int(sizes[i]), ms_per_call=r.ms_per_call, glps=r.glps,
+                 candidates=r.candidates) for i, r in enumerate(res[:k])]
 
 
 def planb_layout(m: int, fanout: int, slots: int, trimmed: bool = True) -> dict:
@@ -453,6 +495,44 @@ class CpuTree:
         _check(_lib.planb_cpu_lookup(self.image.ctypes.data, ctypes.byref(self.info), a.ctypes.data, a.shape[0],
                                      out.ctypes.data, threads))
         return out
+
+
+_sig("planb_cpu_tree_build", _vp, _vp, _vp, _sz, ctypes.c_uint32)
+_sig("planb_cpu_tree_lookup", ctypes.c_int, _vp, _vp, _sz, _vp, ctypes.c_int)
+_sig("planb_cpu_tree_isa", ctypes.c_char_p, _vp)
+_sig("planb_cpu_tree_depth", ctypes.c_int, _vp)
+_sig("planb_cpu_tree_free", None, _vp)
+
+
+class PaperCpuTree:
+    """Host-core baseline in the paper's CPU design (fanout 9, 8 keys per node,
+    vector compare + popcount, batched, unrolled): planb_cpu_tree_*."""
+
+    def __init__(self, prefixes, lengths, next_hops, key_bits: int = 64):
+        starts, nh = planb_build_intervals(prefixes, lengths, next_hops)
+        s = np.ascontiguousarray(starts, dtype=np.uint64)
+        h = np.ascontiguousarray(nh, dtype=np.uint16)
+        self.ptr = _lib.planb_cpu_tree_build(s.ctypes.data, h.ctypes.data, s.shape[0], key_bits)
+        if not self.ptr:
+            raise PlanbError(PLANB_EINVAL, f"planb_cpu_tree_build failed (key_bits {key_bits})")
+        self.key_bits = key_bits
+        self.isa = _lib.planb_cpu_tree_isa(self.ptr).decode()
+        self.depth = int(_lib.planb_cpu_tree_depth(self.ptr))
+
+    def lookup(self, addrs, threads: int = 0, out=None) -> np.ndarray:
+        a = _host(addrs, np.uint64, (2,))
+        if out is None:
+            out = np.empty(a.shape[0], dtype=np.uint16)
+        _check(_lib.planb_cpu_tree_lookup(self.ptr, a.ctypes.data, a.shape[0], out.ctypes.data, threads))
+        return out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            _lib.planb_cpu_tree_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        self.close()
 
 
 def batch_array(batches):

@@ -38,6 +38,7 @@ Table 1 and its synthetic FIBs / traces in the evaluation section):
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -301,17 +302,30 @@ def backbone_traffic(fib: Fib, n: int = 1 << 28, seed: int = 1022, out=None) -> 
     return mixed_traffic(fib, n, 0.7, seed, out=out)
 
 
-def zipf_traffic(fib: Fib, n: int, seed: int, s: float = 1.1) -> np.ndarray:
+def zipf_traffic(fib: Fib, n: int, seed: int, s: float = 1.1, chunk: int = 1 << 21) -> np.ndarray:
     """Destinations Zipf(s) over a random ranking of the prefixes (bounded
-    inverse-CDF over the N ranks), each with a uniform random suffix."""
+    inverse-CDF over the N ranks), each with a uniform random suffix.  Chunks
+    of ``chunk`` addresses draw from their own seeded streams (seed, chunk
+    number) on a pool of host threads, so the result does not depend on the
+    thread count."""
+    from concurrent.futures import ThreadPoolExecutor
     rng = np.random.Generator(np.random.PCG64(seed))
     N = len(fib)
     rank_to_prefix = rng.permutation(N)
     w = np.arange(1, N + 1, dtype=np.float64) ** (-s)
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
-    r = np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), N - 1)
-    return inside_prefixes(rng, fib, rank_to_prefix[r])
+    out = np.empty((n, 2), dtype=U64)
+
+    def one(k):
+        lo, hi = k * chunk, min(n, (k + 1) * chunk)
+        g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, k + 1])))
+        r = np.minimum(np.searchsorted(cdf, g.random(hi - lo), side="right"), N - 1)
+        out[lo:hi] = inside_prefixes(g, fib, rank_to_prefix[r])
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(one, range((n + chunk - 1) // chunk)))
+    return out
 
 
 def ipv4_traffic(fib: Fib, n: int, inside_share: float, seed: int, chunk: int = 1 << 23) -> np.ndarray:

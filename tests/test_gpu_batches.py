@@ -176,3 +176,72 @@ def test_batches_and_graph_with_key_tops(P):
             assert np.array_equal(host_u16(go, len(a)), w)
             assert np.array_equal(host_u16(eager, len(a)), w)
         g.close()
+
+
+def test_uneven_batches_up_to_4m_on_the_large_fib(P):
+    """The 1M-prefix FIB with /128 host routes (128-bit keys) and Zipf(1.1)
+    batches of 64 .. 2^22 addresses, with launch shapes autotuned per batch-size
+    bucket: planb_lookup per batch (each taking its bucket's shape), one
+    persistent launch over every batch, and graph replays (every batch in one
+    replay, and batches one at a time through a graph of the smallest bucket's
+    shape) all equal the oracle."""
+    import torch
+    from paper_2604_14650_amd import autotune
+    fib = fib_of("large", 33)
+    rng = np.random.default_rng(41)
+    sizes = np.concatenate([[64, 65, 4097, (1 << 20) + 3, 1 << 22], S.log_uniform_sizes(rng, 27, 64, 1 << 22)])
+    addrs, offs = _uneven(fib, sizes, 1033)
+    want = oracle_trie("large", 33).lookup(addrs)
+    d = to_dev(addrs)
+    buckets = [256, 4096, 1 << 16, 1 << 20, 1 << 22]
+    say(f"large FIB: {len(sizes)} batches, {len(addrs)} lookups; autotuning {buckets}")
+    h, rec = autotune.tune_sizes(fib.prefixes, fib.lengths, fib.next_hops, d, buckets, fanouts=(16,),
+                                 cache_path=None, reps=1)
+    assert P.planb_get_info(h)["key_bits"] == 128
+    table = P.planb_get_size_tunings(h)
+    assert [e[0] for e in table] == [e["min_lookups"] for e in rec["buckets"]] and table[0][0] == 1
+    out = torch.full((len(addrs),), -1, dtype=torch.int16, device="cuda")
+    say("per-batch planb_lookup with the bucket shapes")
+    for i, m in enumerate(sizes):
+        P.planb_lookup(h, d[offs[i]:], int(m), out[offs[i]:])
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    say("one persistent launch over every batch")
+    out.fill_(-1)
+    desc = torch.from_numpy(np.frombuffer(bytes(P.batch_array(_batches(P, d, out, sizes, offs))),
+                                          dtype=np.uint8).copy()).cuda()
+    cnt = torch.tensor([len(sizes)], dtype=torch.int32, device="cuda")
+    P.planb_lookup_batches(h, desc, cnt, len(sizes))
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    say("every batch in one graph replay")
+    g = P.Graph(h, 64)
+    out.fill_(-1)
+    g.launch(_batches(P, d, out, sizes, offs))
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    g.close()
+    P.planb_set_tuning(h, **table[0][1])
+    g = P.Graph(h, 4)
+    out.fill_(-1)
+    for i in range(len(sizes)):
+        say(f"single-batch graph replay {i}, {int(sizes[i])} lookups")
+        g.launch([(d[offs[i]:], out[offs[i]:], int(sizes[i]))])
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u16(out, len(addrs)), want)
+    g.close()
+    P.planb_set_size_tunings(h, [])
+    assert P.planb_get_size_tunings(h) == []
+
+
+def test_size_tunings_are_checked(P):
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=16)
+    good = P.planb_get_tuning(h)
+    with pytest.raises(P.PlanbError) as e:
+        P.planb_set_size_tunings(h, [(100, good), (100, good)])
+    assert e.value.code == P.PLANB_EINVAL
+    bad = dict(good, keys_per_lane=3)
+    with pytest.raises(P.PlanbError):
+        P.planb_set_size_tunings(h, [(1, good), (1000, bad)])
+    assert P.planb_get_size_tunings(h) == []  # unchanged on error
+    P.planb_set_size_tunings(h, [(1, good), (1000, dict(good, lookups_per_group=1))])
+    assert [e[0] for e in P.planb_get_size_tunings(h)] == [1, 1000]

@@ -426,3 +426,41 @@ def test_cpu_btree_baseline_matches_oracle(b, key_bits):
     want = Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(addrs)
     for threads in (1, 3):
         assert np.array_equal(tree.lookup(addrs, threads), want)
+
+
+@pytest.mark.parametrize("kind", ["vrf", "large_slice", "tiny"])
+@pytest.mark.parametrize("key_bits", [64, 128])
+def test_paper_cpu_tree_matches_oracle(kind, key_bits):
+    """The paper-design CPU baseline (fanout 9, 8 keys per node, vector
+    compare + popcount) returns the oracle's next hops, with 64-bit keys where
+    every start's low word is zero and with 128-bit keys; /128 host routes
+    need (and get) 128-bit keys."""
+    from oracle.trie import Trie
+    if kind == "vrf":
+        fib = S.make_fib(S.vrf_spec(5000), 71)
+    elif kind == "tiny":
+        fib = S.make_fib(S.TINY, 11)
+    else:  # a slice of the 1M-prefix recipe: /128 host routes included
+        big = S.make_fib(S.LARGE, 33)
+        keep = np.arange(0, len(big), 97)
+        fib = S.Fib(big.prefixes[keep], big.lengths[keep], big.next_hops[keep])
+    rng = np.random.default_rng(5)
+    addrs = S.mixed_traffic(fib, 30000, 0.6, 9)
+    starts, _ = P.planb_build_intervals(fib.prefixes, fib.lengths, fib.next_hops)
+    around = starts[rng.integers(0, len(starts), 2000)]
+    below = around.copy()  # each start - 1 (128-bit)
+    borrow = below[:, 1] == 0
+    below[:, 1] -= np.uint64(1)
+    below[:, 0] -= borrow.astype(np.uint64)
+    addrs = np.concatenate([addrs, around, below, S.from_ints([0, 1, (1 << 128) - 1, (1 << 128) - 2])])
+    want = Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(addrs)
+    lo_zero = bool(np.all(starts[:, 1] == 0))
+    if key_bits == 64 and not lo_zero:
+        with pytest.raises(P.PlanbError):
+            P.PaperCpuTree(fib.prefixes, fib.lengths, fib.next_hops, key_bits=64)
+        return
+    tree = P.PaperCpuTree(fib.prefixes, fib.lengths, fib.next_hops, key_bits=key_bits)
+    assert tree.isa in ("avx512", "avx2")
+    assert 8 * 9 ** (tree.depth - 1) >= len(starts) and (tree.depth == 1 or 8 * 9 ** (tree.depth - 2) < len(starts))
+    for threads in (1, 3):
+        assert np.array_equal(tree.lookup(addrs, threads), want)
