@@ -362,14 +362,20 @@ int planb_autotune_sizes(planb_fib_t* fib, const planb_addr_t* sample, size_t n,
  * error table splits [0, m) into equal segments by p and stores, per segment,
  * the largest |p - i| over the first and last address of every interval and
  * two addresses drawn uniformly inside it (4m seeded points, evaluated by the
- * same inference kernel); training uses the same kind of points.  A learned
- * lookup searches [p - w, p + w] of the leaf keys with w = eps + eps/2 + 16,
- * accepts the result only if key[lo] <= x and (hi = m - 1 or key[hi + 1] > x),
- * and otherwise runs the tree descent, so results are always those of
- * planb_lookup.
+ * same inference kernel); training uses the same kind of points.
+ * Trees with 64-bit key slots whose leaf tops fit a workgroup's LDS (the top
+ * 32 bits of every leaf's first key, 4 bytes per leaf, built once with the
+ * model, plus the error table): the window [p - w, p + w], w = 2 eps + 16,
+ * becomes a range of leaves; a binary search over their tops finds the leaf,
+ * verified on the tops (the range's first leaf starts at or below x's top
+ * half, the leaf after it above), ties settled with whole keys; lane groups
+ * then read that one leaf.  Other trees: the window w = eps + eps/2 + 16 of
+ * leaf keys is searched and accepted only if key[lo] <= x and (hi = m - 1 or
+ * key[hi + 1] > x).  A lookup that fails its check runs the tree descent, so
+ * results are always those of planb_lookup.
  */
 typedef struct planb_train_cfg {
-    uint32_t epochs;   /* passes over the 4m sample points (0 -> about 3000 steps in all) */
+    uint32_t epochs;   /* passes over the 4m sample points (0 -> about 30,000 steps in all, 8..400 passes) */
     uint32_t batch;    /* points per Adam step, a multiple of 16 (0 -> 4m/32, within 64..4096) */
     float lr;          /* peak Adam step size, cosine-decayed (0 -> 3e-3) */
     uint32_t segments; /* error-table segments (0 -> 4096); capped at m/64 */
@@ -476,7 +482,7 @@ int planb_lookup_multi(const planb_tableset_t* ts, const planb_burst_t* bursts, 
  * it again after training), the tree descent for the others; results are
  * those of planb_lookup_multi.  fallback_count (device u32, may be NULL) is
  * increased by the number of learned lookups that fell back to the tree.
- * Descriptors as for planb_lookup_multi; LDS: 4 * (max_bursts + 257) + 3072
+ * Descriptors as for planb_lookup_multi; LDS: 4 * (max_bursts + 257)
  * bytes must fit a workgroup. */
 int planb_lookup_multi_learned(const planb_tableset_t* ts, const planb_burst_t* bursts, const uint32_t* n_bursts,
                                uint32_t max_bursts, uint32_t* fallback_count, void* stream);
@@ -511,7 +517,7 @@ typedef struct planb_server_cfg {
     uint32_t fanout;        /* fanout of every table (0 -> 16) */
     uint32_t key_bits;      /* 32, 64 or 128 for every table (0 -> 128) */
     uint64_t memory_budget; /* device bytes for resident trees (0 = unlimited) */
-    uint32_t learned;       /* 1: train a learned model for every table when it is admitted and
+    uint32_t learned;       /* 1: train a learned model (a short run: 8 passes) for every table when it is admitted and
                                serve bursts with planb_lookup_multi_learned (0: planb_lookup_multi) */
     uint32_t reserved;      /* 0 */
 } planb_server_cfg_t;

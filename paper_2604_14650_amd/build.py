@@ -23,7 +23,10 @@ CXX_SOURCES = ["api.cpp", "builder.cpp", "server.cpp", "cpu_btree.cpp", "lifetim
 HOST_SOURCES = ["cpu_paper_tree.cpp"]
 CXX = os.environ.get("CXX", "g++")
 # host code of the CPU baseline: AVX2 vector compares (any x86-64 server since 2015)
-EXTRA_FLAGS = {"cpu_btree.cpp": ["-mavx2"]}
+EXTRA_FLAGS = {"cpu_btree.cpp": ["-mavx2"],
+               # matrix-core results straight into VGPRs (no accumulation-register
+               # copies before the vector instructions that read them)
+               "learned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
@@ -34,7 +37,7 @@ def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, src + ".o")
     if src.endswith(".hip"):
-        cmd = [HIPCC, *HIP_ONLY, *COMMON, "-c", path, "-o", obj]
+        cmd = [HIPCC, *HIP_ONLY, *COMMON, *EXTRA_FLAGS.get(src, []), "-c", path, "-o", obj]
     elif src in HOST_SOURCES:
         cmd = [CXX, *COMMON, "-c", path, "-o", obj]
     else:  # host C++ that calls the HIP runtime: compiled as host-only HIP code

@@ -90,12 +90,13 @@ int validate_tuning(const planb_fib_t* f, const planb_tuning_t& tu, LookupTuning
                                       ", lookups_per_group " + std::to_string(R) + ", block_threads " +
                                       std::to_string(bs) + " for fanout " + std::to_string(b));
     if (tops) {
-        if (f->key_bytes_per_slot != 8 || kpl == b || !lookup_tops_variant_exists((int)b, (int)kpl, (int)R, (int)bs))
-            return fail(PLANB_EINVAL, "lds_search 2 needs 64-bit key slots and fanout / keys_per_lane of 2 or 4");
+        const uint32_t kb = f->key_bytes_per_slot;
+        if ((kb != 8 && kb != 16) || kpl == b || !lookup_tops_variant_exists((int)b, (int)kpl, (int)R, (int)kb, (int)bs))
+            return fail(PLANB_EINVAL, "lds_search 2 needs 64- or 128-bit key slots and fanout / keys_per_lane of 2 or 4");
         // exact levels above the bottom internal one, then that level's key tops (b - 1 per node)
         const uint32_t D = f->lay.depth;
         const size_t tb = D < 2 ? 0
-                                : f->lay.prefix_slots(D - 2) * (size_t)8 +
+                                : f->lay.prefix_slots(D - 2) * (size_t)kb +
                                       (size_t)f->lay.nodes[D - 2] * (b - 1) * 4;
         if (tb > (size_t)max_lds_bytes())
             return fail(PLANB_ERANGE, "the internal levels with the bottom one as key tops need " + std::to_string(tb) +

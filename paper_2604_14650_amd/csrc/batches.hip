@@ -115,28 +115,34 @@ struct BatchesLaunch {
     size_t lds = 0;
 };
 
-// Key-tops variants: B in {8, 16, 32}, B / KPL in {2, 4}, R in {1, 2, 4}, BS in {512, 1024}.
-template <int B, int KPL>
+// Key-tops variants: B in {8, 16, 32}, B / KPL in {2, 4}, R in {1, 2, 4}, KB in {8, 16}, BS in {512, 1024}.
+template <int B, int KPL, int KB>
 BatchesFn pick_tops_r(int R, int bs)
 {
     auto by_bs = [&](auto r) -> BatchesFn {
         constexpr int Rc = decltype(r)::value;
-        return bs == 512    ? batches_kernel<B, KPL, Rc, 8, 512, true, true>
-               : bs == 1024 ? batches_kernel<B, KPL, Rc, 8, 1024, true, true>
+        return bs == 512    ? batches_kernel<B, KPL, Rc, KB, 512, true, true>
+               : bs == 1024 ? batches_kernel<B, KPL, Rc, KB, 1024, true, true>
                             : nullptr;
     };
     return R == 1 ? by_bs(std::integral_constant<int, 1>{}) : R == 2 ? by_bs(std::integral_constant<int, 2>{})
          : R == 4 ? by_bs(std::integral_constant<int, 4>{}) : nullptr;
 }
 
-BatchesFn pick_batches_tops(int B, int kpl, int R, int bs)
+template <int KB>
+BatchesFn pick_batches_tops_kb(int B, int kpl, int R, int bs)
 {
     if (kpl <= 0 || B % kpl) return nullptr;
     const int G = B / kpl;
-    if (B == 8) return G == 2 ? pick_tops_r<8, 4>(R, bs) : G == 4 ? pick_tops_r<8, 2>(R, bs) : nullptr;
-    if (B == 16) return G == 2 ? pick_tops_r<16, 8>(R, bs) : G == 4 ? pick_tops_r<16, 4>(R, bs) : nullptr;
-    if (B == 32) return G == 2 ? pick_tops_r<32, 16>(R, bs) : G == 4 ? pick_tops_r<32, 8>(R, bs) : nullptr;
+    if (B == 8) return G == 2 ? pick_tops_r<8, 4, KB>(R, bs) : G == 4 ? pick_tops_r<8, 2, KB>(R, bs) : nullptr;
+    if (B == 16) return G == 2 ? pick_tops_r<16, 8, KB>(R, bs) : G == 4 ? pick_tops_r<16, 4, KB>(R, bs) : nullptr;
+    if (B == 32) return G == 2 ? pick_tops_r<32, 16, KB>(R, bs) : G == 4 ? pick_tops_r<32, 8, KB>(R, bs) : nullptr;
     return nullptr;
+}
+
+BatchesFn pick_batches_tops(int B, int kpl, int R, int kb, int bs)
+{
+    return kb == 8 ? pick_batches_tops_kb<8>(B, kpl, R, bs) : kb == 16 ? pick_batches_tops_kb<16>(B, kpl, R, bs) : nullptr;
 }
 
 int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
@@ -152,11 +158,11 @@ int plan_batches(const planb_fib_t* fib, uint32_t max_batches, BatchesLaunch* L)
         TreeDesc t = fib->desc;
         t.lds_levels = t.depth >= 2 ? t.depth - 2 : 0;
         t.lds_slots = t.off[t.lds_levels] * t.fanout;
-        size_t tree = (size_t)t.lds_slots * 8;
+        size_t tree = (size_t)t.lds_slots * t.key_bytes;
         if (t.depth >= 2) tree += (size_t)(t.off[t.depth - 1] - t.off[t.depth - 2]) * (t.fanout - 1) * 4;
         tree = (tree + 15) / 16 * 16;
         if (tree + table <= (size_t)p.max_lds) {
-            L->fn = pick_batches_tops((int)t.fanout, tu.kpl, tu.R, tu.block);
+            L->fn = pick_batches_tops((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block);
             L->desc = t;
             L->lds = tree + table;
         }
@@ -200,9 +206,9 @@ int autotune_core(planb_fib_t* fib, const planb_addr_t* sample, size_t n, uint32
                 for (uint32_t bs : {512u, 1024u})
                     for (int lds = shallowest; lds <= deepest; ++lds)
                         cands.push_back(planb_tuning_t{kpl, lds, R, bs, bin});
-        // the bottom internal level as key tops (64-bit key slots; skipped by
-        // planb_set_tuning when the levels do not fit a workgroup's LDS)
-        if (fib->key_bytes_per_slot == 8 && (b / kpl == 2 || b / kpl == 4))
+        // the bottom internal level as key tops (64- and 128-bit key slots; skipped
+        // by planb_set_tuning when the levels do not fit a workgroup's LDS)
+        if ((fib->key_bytes_per_slot == 8 || fib->key_bytes_per_slot == 16) && (b / kpl == 2 || b / kpl == 4))
             for (uint32_t R : {1u, 2u, 4u})
                 for (uint32_t bs : {512u, 1024u}) cands.push_back(planb_tuning_t{kpl, deepest, R, bs, 2u});
     }

@@ -55,16 +55,17 @@ struct Descent {
     }
     static __device__ void stage_bottom_tops(const TreeDesc& t, uint4* lds_raw, int tid, int nthreads)
     {
-        static_assert(KB == 8, "key tops are defined for 64-bit key slots");
+        static_assert(KB == 8 || KB == 16, "key tops are defined for 64- and 128-bit key slots");
+        constexpr uint32_t W = KB / 4;  // 32-bit words per slot; word 1 is the top of the high word
         stage(t, lds_raw, tid, nthreads);
         if (t.depth < 2) return;
         const uint32_t lvl = bottom_level(t);
         const uint32_t keys = (t.off[lvl + 1] - t.off[lvl]) * (uint32_t)(B - 1);
-        const uint32_t* src = static_cast<const uint32_t*>(t.keys);  // the high word of key i is word 2i + 1
+        const uint32_t* src = static_cast<const uint32_t*>(t.keys);
         uint32_t* tops = bottom_tops(lds_raw, t);
         for (uint32_t i = tid; i < keys; i += nthreads) {
             const uint32_t node = i / (uint32_t)(B - 1), s = i - node * (uint32_t)(B - 1);
-            tops[i] = src[2 * ((t.off[lvl] + node) * (uint32_t)B + s) + 1];
+            tops[i] = src[(size_t)W * ((t.off[lvl] + node) * (uint32_t)B + s) + 1];
         }
     }
 
@@ -362,8 +363,10 @@ struct Descent {
     // shuffles, uses it, so that its round trip overlaps them.
     struct Bottom {
         uint32_t c[R], last[R];
-        uint64_t tk[R];  // the key c - 1, read when its top ties
+        K tk[R];  // the key c - 1, read when its top ties
     };
+    // key > x for a whole key read from device memory
+    static __device__ __forceinline__ bool key_gt(const K& k, uint64_t xh, uint64_t xl) { return !KF::le(k, xh, xl); }
     static __device__ __forceinline__ void bottom_search(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
                                                          const uint32_t* q, Bottom& bs)
     {
@@ -385,11 +388,11 @@ struct Descent {
             // every lane loads; the untied ones all read slot 0 (one shared line), so
             // the load is not in a branch and its wait can follow the shuffles
             const bool tie = c > 0 && last == tx;
-            bs.tk[r] = *slot_ptr(gkeys, tie ? (off + q[r]) * (uint32_t)B + c - 1 : 0u);
+            bs.tk[r] = *slot_ptr(gkeys, tie ? (SlotIdx)(off + q[r]) * (SlotIdx)B + c - 1 : (SlotIdx)0);
         }
     }
     static __device__ __forceinline__ void bottom_finish(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
-                                                         uint32_t* q, const Bottom& bs)
+                                                         const uint64_t* xl, uint32_t* q, const Bottom& bs)
     {
         const uint32_t lvl = bottom_level(t), off = t.off[lvl], lim = t.last[lvl + 1];
         const K* gkeys = static_cast<const K*>(t.keys);
@@ -397,10 +400,10 @@ struct Descent {
         for (int r = 0; r < R; ++r) {
             const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
             uint32_t c = bs.c[r];
-            if (c > 0 && bs.last[r] == tx && bs.tk[r] > xh[r]) {
-                const uint32_t node = (off + q[r]) * (uint32_t)B;
+            if (c > 0 && bs.last[r] == tx && key_gt(bs.tk[r], xh[r], xl[r])) {
+                const SlotIdx node = (SlotIdx)(off + q[r]) * (SlotIdx)B;
                 --c;
-                while (c > 0 && tops[n0 + c - 1] == tx && *slot_ptr(gkeys, node + c - 1) > xh[r]) --c;
+                while (c > 0 && tops[n0 + c - 1] == tx && key_gt(*slot_ptr(gkeys, node + c - 1), xh[r], xl[r])) --c;
             }
             q[r] = min(q[r] * B + c, lim);
         }
@@ -497,8 +500,11 @@ struct Descent {
             // the values as changed here; it reads and writes no memory.
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int r = 0; r < R; ++r) asm volatile("" : "+v"(bs.tk[r]));
-            if (t.depth >= 2) bottom_finish(t, bottom_tops(lds, t), xh, q, bs);
+            for (int r = 0; r < R; ++r) {
+                if constexpr (WIDE) asm volatile("" : "+v"(bs.tk[r].x), "+v"(bs.tk[r].y), "+v"(bs.tk[r].z), "+v"(bs.tk[r].w));
+                else asm volatile("" : "+v"(bs.tk[r]));
+            }
+            if (t.depth >= 2) bottom_finish(t, bottom_tops(lds, t), xh, xl, q, bs);
         }
 #pragma unroll
         for (int u = 0; u < T; ++u) p[u] = (uint32_t)__shfl((int)q[u / G], (u % G) * LPW + grp, 64);

@@ -127,6 +127,131 @@ __device__ inline float mlp_forward(const MlpRegs& R, const float* sb1, const fl
     return part + b3;
 }
 
+// ---- inference forward pass (the lookups, the error table and
+// planb_model_predict all use this one; training uses mlp_forward above).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Weight operands of mlp_infer (40 VGPRs).  Layer 1 takes the address bytes
+// as integers (0..255, exact in bf16) against W1 / 256: scaling by a power of
+// two is exact, so every product equals W1 * byte/256.  Layer 2 runs as two
+// v_mfma_f32_16x16x32_bf16 per row block: in chunk q of the 64 hidden units,
+// lane group g's slots 0..3 and 4..7 hold units 32q + 4g + j and
+// 32q + 16 + 4g + j, which are exactly its layer-1 C registers of row blocks
+// 2q and 2q + 1; W2 is loaded in the same unit order, so the contraction is
+// the same sum and nothing moves between the layers.
+struct InferRegs {
+    s4 w1[4];     // (W1 / 256)[16mb + l%16][4g + i]
+    bf8 w2[4][2];  // W2[16mb + l%16][unit(q, g, j)]
+};
+
+__device__ inline __bf16 bf_bits(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+// The per-row constants of mlp_infer held in registers (40 VGPRs): this
+// lane's rows 16mb + 4g + i of b1 and b2 (the accumulators start from them)
+// and of w3 (bf16, two per register).  Reading them from LDS for every tile
+// made LDS bandwidth the limit of the whole forward pass.
+struct InferConsts {
+    f4 b1[4], b2[4];
+    uint32_t w3[8];  // w3[16mb + 4g + 2k], w3[16mb + 4g + 2k + 1] as bf16 bits, low half first
+};
+
+__device__ inline void load_consts(const ModelDesc& M, InferConsts& C)
+{
+    const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            C.b1[mb][i] = M.w[ob1 + 16 * mb + 4 * g + i];
+            C.b2[mb][i] = M.w[ob2 + 16 * mb + 4 * g + i];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            C.w3[2 * mb + k] = (uint32_t)M.wb[ow3 + 16 * mb + 4 * g + 2 * k] |
+                               ((uint32_t)M.wb[ow3 + 16 * mb + 4 * g + 2 * k + 1] << 16);
+    }
+}
+
+__device__ inline void load_infer(const uint16_t* wb, InferRegs& R)
+{
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const __bf16 w = (__bf16)(bf2f(wb[oW1 + (16 * mb + c) * kF + 4 * g + i]) * (1.0f / 256.0f));
+            R.w1[mb][i] = (short)__builtin_bit_cast(uint16_t, w);
+        }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int unit = 32 * q + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+                R.w2[mb][q][j] = bf_bits(wb[oW2 + (16 * mb + c) * kH + unit]);
+            }
+}
+
+// ReLU on the bit pattern: one integer max.  A float whose sign bit is set
+// (negative, or -0) is a negative integer, and non-negative floats order as
+// their bit patterns do.
+__device__ inline float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// y for the wavefront's 16 columns (address of column l%16 in every lane of
+// that column).  Same arithmetic definition as mlp_forward: h1 rounded to bf16
+// (round to nearest even, here by the hardware conversion), fp32 accumulation
+// (the accumulators start from the biases).
+__device__ inline float mlp_infer(const InferRegs& R, const InferConsts& C, float b3, uint64_t xhi, uint64_t xlo)
+{
+    const int g = (threadIdx.x & 63) >> 4;
+    // bytes 4g .. 4g + 3 of the address, most significant first, as bf16 integers
+    const uint32_t w = (uint32_t)((g < 2 ? xhi : xlo) >> ((g & 1) ? 0 : 32));
+    s4 xb;
+    xb[0] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)(w >> 24));
+    xb[1] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)((w >> 16) & 0xFFu));
+    xb[2] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)((w >> 8) & 0xFFu));
+    xb[3] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)(w & 0xFFu));
+    // h1 = bf16(ReLU(z)) = ReLU(bf16(z)) (rounding keeps the sign), so round two
+    // values at a time and take the ReLU of the packed pair with one 16-bit max
+    uint32_t hp[2][4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        const f4 z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[mb], xb, C.b1[mb], 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+            typedef float fl2 __attribute__((ext_vector_type(2)));
+            typedef short sh2 __attribute__((ext_vector_type(2)));
+            const bf2 pr = __builtin_convertvector(fl2{z[2 * k], z[2 * k + 1]}, bf2);
+            const sh2 v = __builtin_elementwise_max(__builtin_bit_cast(sh2, pr), sh2{0, 0});
+            hp[mb >> 1][2 * (mb & 1) + k] = __builtin_bit_cast(uint32_t, v);
+        }
+    }
+    bf8 h[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        h[q] = __builtin_bit_cast(bf8, u4{hp[q][0], hp[q][1], hp[q][2], hp[q][3]});
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        f4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[mb][0], h[0], C.b2[mb], 0, 0, 0);
+        z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[mb][1], h[1], z, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t pair = C.w3[2 * mb + i / 2];
+            const float w3 = __uint_as_float((i & 1) ? (pair & 0xFFFF0000u) : (pair << 16));
+            acc[i] = fmaf(w3, relu_bits(z[i]), acc[i]);
+        }
+    }
+    float part = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    return part + b3;
+}
+
 // Stage biases and w3 (as float) in LDS.
 __device__ inline void stage_small(const ModelDesc& M, float* sb1, float* sb2, float* sw3)
 {
@@ -174,8 +299,8 @@ constexpr int kLearnBlock = 256;
 
 // One wavefront step of the learned lookup: addresses [base, base + 64) of a
 // batch of n (4 MFMA tiles of 16), then one lane per address for the window
-// search, verification and fallback.  R holds the model's weight operands and
-// sb1/sb2/sw3 its biases and output weights as float.
+// search, verification and fallback.  R and C hold the model's weight
+// operands and per-row constants.
 // Lookups whose window check fails: with QUEUE they are appended to a queue
 // in scratch memory and searched afterwards by fallback_kernel, so that a
 // wavefront never waits for one lane's whole-tree descent; without it (the
@@ -187,9 +312,9 @@ struct FallbackQueue {
 };
 
 template <int B, int KB, bool QUEUE>
-__device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const MlpRegs& R, const float* sb1,
-                                    const float* sb2, const float* sw3, float b3, const u64x2* addrs, uint64_t base,
-                                    uint64_t n, uint16_t* out, uint32_t* fallbacks, const FallbackQueue& fq)
+__device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const InferRegs& R, const InferConsts& C,
+                                    float b3, const u64x2* addrs, uint64_t base, uint64_t n, uint16_t* out,
+                                    uint32_t* fallbacks, const FallbackQueue& fq)
 {
     using KF = KeyFmt<KB>;
     const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
@@ -200,8 +325,7 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     for (int tile = 0; tile < 4; ++tile) {
         const uint64_t i = base + 16 * tile + c;
         const u64x2 a = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
-        Activations A;
-        const float yt = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
+        const float yt = mlp_infer(R, C, b3, a.x, a.y);
         if (g == tile) {
             y = yt;
             xhi = a.x;
@@ -259,16 +383,197 @@ __global__ void __launch_bounds__(kLearnBlock)
 learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out,
                FallbackQueue fq)
 {
-    __shared__ float sb1[kH], sb2[kH], sw3[kH];
-    stage_small(M, sb1, sb2, sw3);
-    __syncthreads();
-    MlpRegs R;
-    load_regs(M.wb, R);
+    InferRegs R;
+    load_infer(M.wb, R);
+    InferConsts C;
+    load_consts(M, C);
     const float b3 = M.w[ob3];
     const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
     for (uint64_t base = wave * 64; base < n; base += nwaves * 64)
-        learned_step<B, KB, true>(t, M, R, sb1, sb2, sw3, b3, addrs, base, n, out, nullptr, fq);
+        learned_step<B, KB, true>(t, M, R, C, b3, addrs, base, n, out, nullptr, fq);
+}
+
+// ---------------------------------------------------------------- learned lookup over leaf tops
+// The learned lookup for trees with 64-bit key slots whose leaf minima fit in
+// LDS.  Every leaf's first key is kept as its top 32 bits ("leaf tops", built
+// once per FIB); each workgroup stages them, with the error table, in LDS.
+// The model's window [p - w, p + w] of interval positions maps to a range of
+// leaves; a binary search over that range of the tops (in LDS) finds the last
+// leaf whose top is <= x's top half.  The window is verified on the tops
+// themselves: the first leaf of the range must have a top <= x's, and the
+// leaf after the range a top > x's.  A tie (the found leaf's top equals x's)
+// is settled with whole keys, walking back over the tied leaves, exactly as
+// the plain lookup settles the bottom internal level; the first such read is
+// issued before the lane hand-off and used after it.  Then G = 4 lanes per
+// lookup read the leaf (one line) and pick the answer as the plain lookup
+// does.  A lookup whose window fails its check goes to the fallback queue.
+struct LeafTops {
+    const uint32_t* tops;  // top 32 bits of each leaf's first key
+    uint32_t nleaves;
+};
+
+__host__ __device__ inline size_t learned_tops_lds_bytes(uint32_t nleaves, uint32_t segments)
+{
+    return ((size_t)nleaves + 3) / 4 * 16 + ((size_t)segments + 3) / 4 * 16;
+}
+
+template <int B, int KPL, int R, int BS>
+__global__ void __launch_bounds__(BS)
+learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restrict__ addrs, uint64_t n,
+                    uint16_t* __restrict__ out, FallbackQueue fq)
+{
+    using D = Descent<B, KPL, R, 8, true>;
+    static_assert(D::G == 4 && D::kBlockLane, "one 32-byte leaf block per lane");
+    constexpr int G = D::G, LPW = D::LPW, T = R * G;
+    constexpr uint32_t LC = (uint32_t)D::kLC;
+    extern __shared__ uint4 lds_raw[];
+    uint32_t* tops = reinterpret_cast<uint32_t*>(lds_raw);
+    uint32_t* eps = tops + ((size_t)lt.nleaves + 3) / 4 * 4;
+    for (uint32_t i = threadIdx.x; i < lt.nleaves; i += BS) tops[i] = lt.tops[i];
+    for (uint32_t i = threadIdx.x; i < M.segments; i += BS) eps[i] = M.eps[i];
+    __syncthreads();
+    InferRegs Rg;
+    load_infer(M.wb, Rg);
+    InferConsts C;
+    load_consts(M, C);
+    const float b3 = M.w[ob3];
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const uint64_t m = t.m_minus_1 + 1;
+    const uint32_t last_leaf = lt.nleaves - 1;
+    const auto* gkeys = static_cast<const uint64_t*>(t.keys);
+    const uint64_t wave = (uint64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (BS / 64);
+    const uint64_t stride = nwaves * 64 * R;
+    // column c's address of each MFMA tile, loaded one wavefront step ahead so
+    // that the model's arithmetic overlaps the next step's HBM reads
+    u64x2 ahead[R][4];
+    auto load_step = [&](uint64_t b) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile) {
+                const uint64_t i = b + 64 * r + 16 * tile + c;
+                ahead[r][tile] = __builtin_nontemporal_load(addrs + (i < n ? i : n - 1));
+            }
+    };
+    if (wave * 64 * R < n) load_step(wave * 64 * R);
+    for (uint64_t base = wave * 64 * R; base < n; base += stride) {
+        u64x2 cur[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile) cur[r][tile] = ahead[r][tile];
+        if (base + stride < n) load_step(base + stride);
+        uint64_t xh[R];
+        uint32_t q[R], lastq[R];
+        bool ok[R];
+        uint64_t tk[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            // the model, 16 addresses per MFMA tile; this lane's address is base + 64r + l
+            float y = 0.f;
+            uint64_t xhi = 0;
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile) {
+                const float yt = mlp_infer(Rg, C, b3, cur[r][tile].x, cur[r][tile].y);
+                if (g == tile) {
+                    y = yt;
+                    xhi = cur[r][tile].x;
+                }
+            }
+            xh[r] = xhi;
+            const uint32_t tx = (uint32_t)(xhi >> 32);
+            const uint64_t p = predict_position(y, m);
+            const uint32_t e0 = eps[(uint32_t)(p * M.segments / m)];
+            // window of positions -> range of leaves (an empty segment searches every leaf)
+            uint32_t q0 = 0, q1 = last_leaf;
+            if (e0 != kEmpty) {
+                const uint64_t w = 2 * (uint64_t)e0 + 16;
+                q0 = (uint32_t)((p > w ? p - w : 0) / LC);
+                q1 = (uint32_t)min((p + w) / LC, (uint64_t)last_leaf);
+            }
+            // last leaf in [q0, q1] whose top is <= tx
+            uint32_t lo = q0, len = q1 - q0 + 1;
+            while (len > 0) {
+                const uint32_t half = len >> 1;
+                if (tops[lo + half] <= tx) {
+                    lo += half + 1;
+                    len -= half + 1;
+                } else {
+                    len = half;
+                }
+            }
+            // verified on the tops: some leaf of the range starts at or below x's
+            // top, and the leaf after the range starts above it
+            ok[r] = lo > q0 && (lo <= q1 || q1 == last_leaf || tops[q1 + 1] > tx);
+            const uint32_t L = lo > q0 ? lo - 1 : q0;
+            q[r] = L;
+            lastq[r] = tops[L];
+            // the whole first key of a tied leaf; untied lanes all read key 0
+            const bool tie = ok[r] && lastq[r] == tx;
+            tk[r] = gkeys[tie ? t.leaf_base + L * (uint32_t)D::kLS : 0u];
+        }
+        // hand-off: G lanes per lookup; round u serves owner lane (u % G) * LPW + lane / G
+        const int grp = l / G, j = l % G;
+        uint64_t yh[T], yl[T];
+        uint32_t pq[T];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const int owner = (u % G) * LPW + grp;
+            yh[u] = D::shfl64(xh[u / G], owner);
+            yl[u] = 0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) asm volatile("" : "+v"(tk[r]));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t tx = (uint32_t)(xh[r] >> 32);
+            uint32_t L = q[r];
+            if (ok[r] && lastq[r] == tx && tk[r] > xh[r]) {  // walk back over leaves whose tops tie
+                --L;
+                while (L > 0 && tops[L] == tx && gkeys[t.leaf_base + L * (uint32_t)D::kLS] > xh[r]) --L;
+            }
+            q[r] = L;
+        }
+#pragma unroll
+        for (int u = 0; u < T; ++u) pq[u] = (uint32_t)__shfl((int)q[u / G], (u % G) * LPW + grp, 64);
+        uint32_t res[T];
+        D::template leaf_blocks<T>(t, gkeys, pq, yh, yl, j, l - j, 0, res);
+        const int gsel = l / LPW, src = (l % LPW) * G;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const uint32_t got = (uint32_t)__shfl((int)res[r * G + k], src, 64);
+                v = k == gsel ? got : v;
+            }
+            const uint64_t i = base + (uint64_t)r * 64 + l;
+            const bool need = !ok[r] && i < n;
+            const uint64_t mask = __ballot(need);
+            if (mask) {
+                const int first_lane = __builtin_ctzll(mask);
+                uint32_t first = 0;
+                if (l == first_lane) first = atomicAdd(fq.count, (uint32_t)__popcll(mask));
+                first = (uint32_t)__builtin_amdgcn_readlane((int)first, first_lane);
+                const uint32_t slot = first + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
+                if (need && slot < fq.cap) fq.idx[slot] = (uint32_t)i;  // cap >= n: always taken
+            }
+            if (ok[r] && i < n) __builtin_nontemporal_store((uint16_t)v, out + i);
+        }
+    }
+}
+
+// Leaf tops of a tree with 64-bit key slots: the high 32 bits of each leaf's first key.
+template <int B>
+__global__ void leaf_tops_kernel(TreeDesc t, uint32_t* __restrict__ tops, uint32_t nleaves)
+{
+    constexpr int LS = leaf_slots_for(B, 8);
+    const auto* keys = static_cast<const uint64_t*>(t.keys);
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nleaves; q += gridDim.x * blockDim.x)
+        tops[q] = (uint32_t)(keys[t.leaf_base + (uint64_t)q * LS] >> 32);
 }
 
 // Clears the fallback queue before a learned lookup (a kernel, not a memset,
@@ -307,16 +612,15 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
     extern __shared__ uint32_t lds_u32[];
     uint32_t* tile_off = lds_u32;                                   // max_bursts + 1
     uint32_t* part = tile_off + max_bursts + 1;                     // kLearnBlock
-    float* small = reinterpret_cast<float*>(part + kLearnBlock) + (threadIdx.x >> 6) * 3 * kH;  // this wave's
-    float *sb1 = small, *sb2 = small + kH, *sw3 = small + 2 * kH;
     auto live = [&](uint32_t tb) { return tb < n_tables && tables[tb].depth != 0; };
     const uint32_t nb = plan_burst_tiles<kLearnBlock>(bursts, count, max_bursts, 64, live, tile_off, part);
     const uint32_t total = tile_off[nb];
     const uint32_t nwaves = gridDim.x * (kLearnBlock / 64);
     const int l = threadIdx.x & 63;
-    MlpRegs R;
+    InferRegs R;
+    InferConsts C;
     float b3 = 0.f;
-    uint32_t loaded = 0xFFFFFFFFu;  // table whose model R and the staged vectors hold
+    uint32_t loaded = 0xFFFFFFFFu;  // table whose model R and C hold
     for (uint32_t tile = blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6); tile < total; tile += nwaves) {
         const uint32_t k = burst_of_tile(tile_off, nb, tile);
         const BurstRec br = bursts[k];
@@ -334,18 +638,12 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
             continue;
         }
         if (br.table != loaded) {  // uniform across the wavefront
-            load_regs(M.wb, R);
+            load_infer(M.wb, R);
+            load_consts(M, C);
             b3 = M.w[ob3];
-            sb1[l] = M.w[ob1 + l];
-            sb2[l] = M.w[ob2 + l];
-            sw3[l] = bf2f(M.wb[ow3 + l]);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             loaded = br.table;
         }
-        learned_step<B, KB, false>(t, M, R, sb1, sb2, sw3, b3, addrs, base, br.n, out, fallbacks, FallbackQueue{});
-        __builtin_amdgcn_wave_barrier();  // the next tile may restage the vectors
+        learned_step<B, KB, false>(t, M, R, C, b3, addrs, base, br.n, out, fallbacks, FallbackQueue{});
     }
 }
 
@@ -353,20 +651,21 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
 __global__ void __launch_bounds__(kLearnBlock)
 predict_kernel(ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, float* __restrict__ y)
 {
-    __shared__ float sb1[kH], sb2[kH], sw3[kH];
-    stage_small(M, sb1, sb2, sw3);
-    __syncthreads();
-    MlpRegs R;
-    load_regs(M.wb, R);
+    InferRegs R;
+    load_infer(M.wb, R);
+    InferConsts C;
+    load_consts(M, C);
     const float b3 = M.w[ob3];
     const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
     const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
+    // each step's address is loaded one step ahead
+    u64x2 next = addrs[min(wave * 16 + c, n - 1)];
     for (uint64_t base = wave * 16; base < n; base += nwaves * 16) {
         const uint64_t i = base + c;
-        const u64x2 a = addrs[i < n ? i : n - 1];
-        Activations A;
-        const float yt = mlp_forward(R, sb1, sb2, sw3, b3, a.x, a.y, A);
+        const u64x2 a = next;
+        next = addrs[min(base + nwaves * 16 + c, n - 1)];
+        const float yt = mlp_infer(R, C, b3, a.x, a.y);
         if (g == 0 && i < n) y[i] = yt;
     }
 }
@@ -614,6 +913,8 @@ struct LearnedModel {
     uint32_t max_parts = 256;
     uint64_t adam_steps = 0;
     bool has_eps = false;
+    uint32_t* leaf_tops = nullptr;  // 64-bit key slots: top 32 bits of each leaf's first key
+    uint32_t nleaves = 0;
 };
 
 namespace {
@@ -634,6 +935,21 @@ template <int B>
 LearnedFns learned_by_kb(int kb)
 {
     return kb == 4 ? learned_fns<B, 4>() : kb == 8 ? learned_fns<B, 8>() : learned_fns<B, 16>();
+}
+
+// The leaf-tops learned kernel: B in {8, 16} (128-byte leaves, 4 lanes of one
+// 32-byte block each), R in {1, 2}, 512 threads (the model's registers leave
+// no room for 1024-thread workgroups without spills).
+constexpr int kLearnTopsBlock = 512;
+
+void* pick_learned_tops(int B, int R)
+{
+    auto by = [&](auto b) -> void* {
+        constexpr int Bc = decltype(b)::value;
+        return R == 1 ? reinterpret_cast<void*>(learned_tops_kernel<Bc, Bc / 4, 1, kLearnTopsBlock>)
+             : R == 2 ? reinterpret_cast<void*>(learned_tops_kernel<Bc, Bc / 4, 2, kLearnTopsBlock>) : nullptr;
+    };
+    return B == 8 ? by(std::integral_constant<int, 8>{}) : B == 16 ? by(std::integral_constant<int, 16>{}) : nullptr;
 }
 
 LearnedFns pick_learned(int B, int kb)
@@ -672,6 +988,26 @@ int ensure_model(planb_fib_t* f, uint32_t segments)
         (e = get(&L->partials, (size_t)L->max_parts * kParams * 4)) != hipSuccess) {
         release_learned(f);
         return fail(PLANB_ENOMEM, std::string("device allocation: ") + hipGetErrorString(e));
+    }
+    if (f->desc.key_bytes == 8 && f->desc.depth >= 1) {  // the tree never changes: its leaf tops are built once
+        const TreeDesc& t = f->desc;
+        L->nleaves = t.last[t.depth - 1] + 1;
+        if ((e = get(&L->leaf_tops, (size_t)L->nleaves * 4)) != hipSuccess) {
+            release_learned(f);
+            return fail(PLANB_ENOMEM, std::string("device allocation: ") + hipGetErrorString(e));
+        }
+        const unsigned grid = std::min<unsigned>((L->nleaves + 255) / 256, 1024);
+        switch (t.fanout) {
+        case 8: hipLaunchKernelGGL(leaf_tops_kernel<8>, dim3(grid), dim3(256), 0, nullptr, t, L->leaf_tops, L->nleaves); break;
+        case 16: hipLaunchKernelGGL(leaf_tops_kernel<16>, dim3(grid), dim3(256), 0, nullptr, t, L->leaf_tops, L->nleaves); break;
+        case 32: hipLaunchKernelGGL(leaf_tops_kernel<32>, dim3(grid), dim3(256), 0, nullptr, t, L->leaf_tops, L->nleaves); break;
+        default: break;
+        }
+        if ((e = hipGetLastError()) == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) {
+            release_learned(f);
+            return fail_hip(e, "building the leaf tops");
+        }
     }
     return PLANB_OK;
 }
@@ -809,15 +1145,17 @@ void release_learned(planb_fib_t* f)
     if (!L) return;
     // lookups already enqueued may still read the model: freed after them
     free_after(f->uses, f->device,
-               {(void*)L->w, (void*)L->m1, (void*)L->m2, (void*)L->wb, (void*)L->eps, (void*)L->partials});
+               {(void*)L->w, (void*)L->m1, (void*)L->m2, (void*)L->wb, (void*)L->eps, (void*)L->partials,
+                (void*)L->leaf_tops});
     delete L;
     f->learned = nullptr;
 }
 
-size_t learned_model_bytes(uint32_t segments)
+size_t learned_model_bytes(uint32_t segments, uint64_t nleaves)
 {
     if (segments == 0) segments = 4096;
-    return (size_t)kParams * (3 * 4 + 2) + (size_t)segments * 4 + (size_t)LearnedModel{}.max_parts * kParams * 4;
+    return (size_t)kParams * (3 * 4 + 2) + (size_t)segments * 4 + (size_t)LearnedModel{}.max_parts * kParams * 4 +
+           (size_t)nleaves * 4;
 }
 
 ModelDesc ready_model_desc(const planb_fib_t* f)
@@ -856,7 +1194,7 @@ int plan_multi_learned(int fanout, int kb, uint32_t max_bursts, MultiLaunch* L)
     if (e != hipSuccess) return fail_hip(e, "device properties");
     L->fn = fn;
     L->block = kLearnBlock;
-    L->lds = ((size_t)max_bursts + 1 + kLearnBlock) * 4 + (size_t)(kLearnBlock / 64) * 3 * kH * 4;
+    L->lds = ((size_t)max_bursts + 1 + kLearnBlock) * 4;
     if (L->lds > (size_t)p.max_lds) return fail(PLANB_ERANGE, "too many bursts per launch for the LDS");
     int nb = 1;
     if ((e = occupancy(fn, kLearnBlock, L->lds, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
@@ -929,18 +1267,36 @@ int launch_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, 
     DevProps p;
     hipError_t e = dev_props(&p);
     if (e != hipSuccess) return fail_hip(e, "device properties");
-    int nb = 1;
-    if ((e = occupancy(fns.lookup, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
-    const uint64_t want = (n + (kLearnBlock / 64) * 64 - 1) / ((kLearnBlock / 64) * 64);
-    const unsigned grid = (unsigned)std::min<uint64_t>(want, (uint64_t)p.cus * nb);
     TreeDesc t = fib->desc;
-    ModelDesc M = model_desc(fib->learned);
+    const LearnedModel* LM = fib->learned;
+    ModelDesc M = model_desc(LM);
     const u64x2* a = reinterpret_cast<const u64x2*>(addrs);
     uint64_t nn = n;
+    // the leaf-tops kernel when the tree has 64-bit key slots and its leaf tops
+    // and error table fit a workgroup's LDS (lookups per group from the FIB's
+    // tuning: 1, or 2 for 2 and more), else the window search over the leaf keys
+    const int R = fib->tune.R >= 2 ? 2 : 1, bs = kLearnTopsBlock;
+    void* tops_fn = LM->leaf_tops ? pick_learned_tops((int)t.fanout, R) : nullptr;
+    const size_t tops_lds = learned_tops_lds_bytes(LM->nleaves, LM->segments);
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, fq.count);
-    void* args[] = {&t, &M, &a, &nn, &out, &fq};
-    if ((e = hipLaunchKernel(fns.lookup, dim3(grid), dim3(kLearnBlock), args, 0, st)) != hipSuccess)
-        return fail_hip(e, "learned lookup launch");
+    if (tops_fn && tops_lds <= (size_t)p.max_lds) {
+        int nb = 1;
+        if ((e = occupancy(tops_fn, bs, tops_lds, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
+        const uint64_t per_block = (uint64_t)(bs / 64) * 64 * R;
+        const unsigned grid = (unsigned)std::min<uint64_t>((n + per_block - 1) / per_block, (uint64_t)p.cus * nb);
+        LeafTops lt{LM->leaf_tops, LM->nleaves};
+        void* args[] = {&t, &M, &lt, &a, &nn, &out, &fq};
+        if ((e = hipLaunchKernel(tops_fn, dim3(grid), dim3(bs), args, tops_lds, st)) != hipSuccess)
+            return fail_hip(e, "learned lookup launch");
+    } else {
+        int nb = 1;
+        if ((e = occupancy(fns.lookup, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
+        const uint64_t want = (n + (kLearnBlock / 64) * 64 - 1) / ((kLearnBlock / 64) * 64);
+        const unsigned grid = (unsigned)std::min<uint64_t>(want, (uint64_t)p.cus * nb);
+        void* args[] = {&t, &M, &a, &nn, &out, &fq};
+        if ((e = hipLaunchKernel(fns.lookup, dim3(grid), dim3(kLearnBlock), args, 0, st)) != hipSuccess)
+            return fail_hip(e, "learned lookup launch");
+    }
     // the queue's length is known only on the device: a fixed grid walks it
     const unsigned fgrid = (unsigned)std::min<uint64_t>((n + kLearnBlock - 1) / kLearnBlock, (uint64_t)p.cus * 2);
     void* fargs[] = {&t, &a, &out, &fq, &fallback_count};
@@ -1077,9 +1433,9 @@ int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg_in, void* stream,
     const uint64_t npts_all = kPointsPerInterval * (uint64_t)fib->iv.starts.size();
     if (cfg.batch == 0)  // about 32 steps per epoch, 64..4096 points per step
         cfg.batch = (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(64, npts_all / 32 / 16 * 16));
-    if (cfg.epochs == 0) {  // about 3000 Adam steps in all
+    if (cfg.epochs == 0) {  // about 30,000 Adam steps in all (about 1.4 s for 400k intervals)
         const uint64_t per_epoch = (npts_all + cfg.batch - 1) / cfg.batch;
-        cfg.epochs = (uint32_t)std::min<uint64_t>(400, std::max<uint64_t>(8, (3000 + per_epoch - 1) / per_epoch));
+        cfg.epochs = (uint32_t)std::min<uint64_t>(400, std::max<uint64_t>(8, (30000 + per_epoch - 1) / per_epoch));
     }
     if (cfg.lr <= 0.f) cfg.lr = 3e-3f;
     cfg.segments = effective_segments(cfg.segments, fib->iv.starts.size());

@@ -16,8 +16,9 @@ struct ModelDesc {
 };
 
 // Device bytes a model with `segments` error-table entries holds (weights,
-// their bf16 copy, Adam moments, error table, gradient partials).
-size_t learned_model_bytes(uint32_t segments);
+// their bf16 copy, Adam moments, error table, gradient partials), plus its
+// leaf tops for a tree of `nleaves` leaves with 64-bit key slots (else 0).
+size_t learned_model_bytes(uint32_t segments, uint64_t nleaves);
 
 // The model of a FIB that has a trained model and error table, else all zero.
 ModelDesc ready_model_desc(const planb_fib_t* f);

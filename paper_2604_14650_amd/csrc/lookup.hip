@@ -65,11 +65,11 @@ lookup_v4_kernel(TreeDesc t, const uint32_t* __restrict__ addrs, uint64_t n, voi
 // a lookup's only tree access outside the CU is its leaf, unless its address
 // ties a key's top half; then its lane re-reads that node whole).  Results
 // are those of lookup_kernel.
-template <int B, int KPL, int R, int BS>
+template <int B, int KPL, int R, int KB, int BS>
 __global__ void __launch_bounds__(BS)
 lookup_tops_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
 {
-    using D = Descent<B, KPL, R, 8, true>;
+    using D = Descent<B, KPL, R, KB, true>;
     extern __shared__ uint4 lds_raw[];
     D::stage_bottom_tops(t, lds_raw, threadIdx.x, BS);
     __syncthreads();
@@ -130,26 +130,34 @@ KernelFn pick(int B, int kpl, int R, int kb, int bs, bool bin)
     return VariantTable<PlainKernel>::pick(B, kpl, R, kb, bs, bin);
 }
 
-// Key-tops kernels: B in {8, 16, 32}, B / KPL in {2, 4}, R in {1, 2, 4}, BS in {512, 1024}.
-template <int B, int KPL>
+// Key-tops kernels: B in {8, 16, 32}, B / KPL in {2, 4}, R in {1, 2, 4}, KB in {8, 16}, BS in {512, 1024}.
+template <int B, int KPL, int KB>
 KernelFn pick_tops_r(int R, int bs)
 {
     auto by_bs = [&](auto r) -> KernelFn {
         constexpr int Rc = decltype(r)::value;
-        return bs == 512 ? lookup_tops_kernel<B, KPL, Rc, 512> : bs == 1024 ? lookup_tops_kernel<B, KPL, Rc, 1024> : nullptr;
+        return bs == 512    ? lookup_tops_kernel<B, KPL, Rc, KB, 512>
+               : bs == 1024 ? lookup_tops_kernel<B, KPL, Rc, KB, 1024>
+                            : nullptr;
     };
     return R == 1 ? by_bs(std::integral_constant<int, 1>{}) : R == 2 ? by_bs(std::integral_constant<int, 2>{})
          : R == 4 ? by_bs(std::integral_constant<int, 4>{}) : nullptr;
 }
 
-KernelFn pick_tops(int B, int kpl, int R, int bs)
+template <int KB>
+KernelFn pick_tops_kb(int B, int kpl, int R, int bs)
 {
     if (kpl <= 0 || B % kpl) return nullptr;
     const int G = B / kpl;
-    if (B == 8) return G == 2 ? pick_tops_r<8, 4>(R, bs) : G == 4 ? pick_tops_r<8, 2>(R, bs) : nullptr;
-    if (B == 16) return G == 2 ? pick_tops_r<16, 8>(R, bs) : G == 4 ? pick_tops_r<16, 4>(R, bs) : nullptr;
-    if (B == 32) return G == 2 ? pick_tops_r<32, 16>(R, bs) : G == 4 ? pick_tops_r<32, 8>(R, bs) : nullptr;
+    if (B == 8) return G == 2 ? pick_tops_r<8, 4, KB>(R, bs) : G == 4 ? pick_tops_r<8, 2, KB>(R, bs) : nullptr;
+    if (B == 16) return G == 2 ? pick_tops_r<16, 8, KB>(R, bs) : G == 4 ? pick_tops_r<16, 4, KB>(R, bs) : nullptr;
+    if (B == 32) return G == 2 ? pick_tops_r<32, 16, KB>(R, bs) : G == 4 ? pick_tops_r<32, 8, KB>(R, bs) : nullptr;
     return nullptr;
+}
+
+KernelFn pick_tops(int B, int kpl, int R, int kb, int bs)
+{
+    return kb == 8 ? pick_tops_kb<8>(B, kpl, R, bs) : kb == 16 ? pick_tops_kb<16>(B, kpl, R, bs) : nullptr;
 }
 
 std::mutex g_mu;
@@ -208,7 +216,7 @@ hipError_t occupancy(const void* fn, int bs, size_t lds, int* blocks)
 
 bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin) { return pick(B, kpl, R, 16, bs, bin) != nullptr; }
 
-bool lookup_tops_variant_exists(int B, int kpl, int R, int bs) { return pick_tops(B, kpl, R, bs) != nullptr; }
+bool lookup_tops_variant_exists(int B, int kpl, int R, int kb, int bs) { return pick_tops(B, kpl, R, kb, bs) != nullptr; }
 
 int max_lds_bytes()
 {
@@ -276,12 +284,12 @@ hipError_t launch_lookup(const TreeDesc& td, const LookupTuning& tu, const void*
     // workgroup per CU loading up to 160 KB) costs more than it saves: such
     // batches take the whole-key hybrid descent of the same tuning.
     if (tu.tops && n >= kTopsMinLookups) {
-        if (t.key_bytes != 8) return hipErrorInvalidValue;
+        if (t.key_bytes != 8 && t.key_bytes != 16) return hipErrorInvalidValue;
         // exact levels above the bottom internal one, then that level's key tops
         t.lds_levels = t.depth >= 2 ? t.depth - 2 : 0;
         t.lds_slots = t.off[t.lds_levels] * t.fanout;
         if (t.depth >= 2) extra = (size_t)(t.off[t.depth - 1] - t.off[t.depth - 2]) * (t.fanout - 1) * 4;
-        fn = pick_tops((int)t.fanout, tu.kpl, tu.R, tu.block);
+        fn = pick_tops((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block);
     } else {
         fn = pick((int)t.fanout, tu.kpl, tu.R, (int)t.key_bytes, tu.block, tu.bin);
     }

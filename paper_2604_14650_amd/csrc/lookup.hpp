@@ -13,8 +13,8 @@ struct LookupTuning {
     int R = 2;        // lookups each lane group keeps in flight
     int block = 512;  // threads per workgroup
     bool bin = false; // one lane per lookup, binary search, in the LDS-staged levels
-    bool tops = false; // planb_lookup only: every internal level in LDS as 32-bit key tops
-                       // (64-bit key slots, hybrid shapes); the other paths run as bin
+    bool tops = false; // the bottom internal level in LDS as 32-bit key tops (64- and 128-bit
+                       // key slots, hybrid shapes); the multi-FIB and IPv4 paths run as bin
 };
 
 // Lookups one wavefront handles per step of the descent for this shape.
@@ -26,8 +26,8 @@ inline uint64_t lookups_per_wave_step(int B, const LookupTuning& tu)
 
 // Whether a (fanout, keys per lane, lookups per group, block size) kernel is compiled in.
 bool lookup_variant_exists(int B, int kpl, int R, int bs, bool bin = false);
-// The same for the key-tops kernel (64-bit key slots).
-bool lookup_tops_variant_exists(int B, int kpl, int R, int bs);
+// The same for the key-tops kernel (64- and 128-bit key slots, kb = 8 or 16).
+bool lookup_tops_variant_exists(int B, int kpl, int R, int kb, int bs);
 
 // Largest dynamic LDS allocation a workgroup may request on the current device.
 int max_lds_bytes();

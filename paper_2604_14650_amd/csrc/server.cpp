@@ -142,7 +142,8 @@ size_t table_bytes(const Table& t, uint32_t fanout, uint32_t key_bits, bool lear
     if (plan_layout(t.m, fanout, fanout, (uint32_t)leaf_cap_for((int)fanout, kb),
                     (uint32_t)leaf_slots_for((int)fanout, kb), true, &lay, &err) != 0)
         return SIZE_MAX;
-    return lay.total_slots() * kb + (t.m + 63) / 64 * 64 * 2 + (learned ? learned_model_bytes(0) : 0);
+    const uint64_t leaves = kb == 8 ? lay.nodes[lay.depth - 1] : 0;
+    return lay.total_slots() * kb + (t.m + 63) / 64 * 64 * 2 + (learned ? learned_model_bytes(0, leaves) : 0);
 }
 
 // Make table `id` resident; false if the budget cannot be met right now
@@ -182,12 +183,14 @@ int admit(planb_server_t* s, uint32_t id, bool* ok)
     planb_fib_t* f = planb_build_ex(t.pfx.data(), t.len.data(), t.nh.data(), t.len.size(), &p);
     if (!f) return planb_last_status() ? planb_last_status() : PLANB_EDEVICE;
     int rc = PLANB_OK;
-    if (s->cfg.learned && (rc = planb_train(f, nullptr, nullptr, nullptr)) != PLANB_OK) {
+    planb_train_cfg_t tc{};
+    tc.epochs = 8;  // a short run: admission waits for it
+    if (s->cfg.learned && (rc = planb_train(f, &tc, nullptr, nullptr)) != PLANB_OK) {
         planb_free(f);
         return rc;
     }
     t.fib = f;
-    t.bytes = f->key_bytes + f->value_bytes + (f->learned ? learned_model_bytes(0) : 0);
+    t.bytes = table_bytes(t, s->cfg.fanout, s->cfg.key_bits, s->cfg.learned != 0);
     s->used_bytes += t.bytes;
     ++s->stats.admissions;
     return PLANB_OK;

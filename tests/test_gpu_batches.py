@@ -137,16 +137,17 @@ def test_autotune_keeps_results_exact(P, tmp_path):
     assert json.load(open(cache))
 
 
-def test_batches_and_graph_with_key_tops(P):
+@pytest.mark.parametrize("fanout,key_bits", [(8, 0), (16, 128)])
+def test_batches_and_graph_with_key_tops(P, fanout, key_bits):
     """A tuning with lds_search 2: the persistent batch kernel stages the bottom
     internal level as key tops when they fit beside the batch table (else
-    whole keys); device descriptors, graph replays and eager lookups between
-    them all equal the oracle."""
+    whole keys), with 64- and with 128-bit key slots; device descriptors,
+    graph replays and eager lookups between them all equal the oracle."""
     import torch
     fib = fib_of("backbone", 22)
     trie = oracle_trie("backbone", 22)
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
-    P.planb_set_tuning(h, 2, 5, 2, 1024, 2)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
+    P.planb_set_tuning(h, fanout // 4, -1, 2, 1024, 2)
     rng = np.random.default_rng(31)
     sizes = np.concatenate([[0, 1, 127, 128, 129], S.log_uniform_sizes(rng, 40, 1, 1 << 17)])
     addrs, offs = _uneven(fib, sizes, 131)

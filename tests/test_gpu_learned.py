@@ -211,24 +211,28 @@ def test_learned_lookup_exact_tiny(P, trained_tiny):
     assert fb < 0.05 * len(addrs)
 
 
-def test_forced_fallbacks_stay_exact(P, trained_tiny):
-    fib, h, _ = trained_tiny
+@pytest.mark.parametrize("key_bits", [0, 128])
+def test_forced_fallbacks_stay_exact(P, key_bits):
+    """Error bounds forced to zero (windows of a few positions), to "empty" and
+    to the whole range.  With 64-bit key slots the leaf-tops kernel runs: an
+    empty segment searches every leaf's top (no fallback).  With 128-bit slots
+    the leaf-key window search runs: an empty segment always falls back.  Every
+    result equals the oracle's."""
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, key_bits=key_bits)
+    P.planb_train(h, seed=7)
     addrs = S.tiny_traffic(fib, 1 << 16, seed=12)
     want = oracle_trie("tiny", 11).lookup(addrs)
-    saved = P.planb_model_get_eps(h, 4096)
-    G = len(saved)
-    try:
-        P.planb_model_set_eps(h, np.zeros(G, np.uint32))  # windows of +-16 positions only
-        got, fb = _learned(P, h, addrs)
-        assert np.array_equal(got, want) and fb > 0
-        P.planb_model_set_eps(h, np.full(G, 0xFFFFFFFF, np.uint32))
-        got, fb = _learned(P, h, addrs)
-        assert np.array_equal(got, want) and fb == len(addrs)
-        P.planb_model_set_eps(h, np.full(G, 1 << 30, np.uint32))  # whole-range windows
-        got, fb = _learned(P, h, addrs)
-        assert np.array_equal(got, want) and fb == 0
-    finally:
-        P.planb_model_set_eps(h, saved)
+    G = len(P.planb_model_get_eps(h, 4096))
+    P.planb_model_set_eps(h, np.zeros(G, np.uint32))  # windows of +-16 positions only
+    got, fb = _learned(P, h, addrs)
+    assert np.array_equal(got, want) and fb > 0
+    P.planb_model_set_eps(h, np.full(G, 0xFFFFFFFF, np.uint32))
+    got, fb = _learned(P, h, addrs)
+    assert np.array_equal(got, want) and fb == (0 if key_bits == 0 else len(addrs))
+    P.planb_model_set_eps(h, np.full(G, 1 << 30, np.uint32))  # whole-range windows
+    got, fb = _learned(P, h, addrs)
+    assert np.array_equal(got, want) and fb == 0
 
 
 def test_random_weights_stay_exact(P):

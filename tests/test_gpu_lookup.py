@@ -320,17 +320,19 @@ def test_top_of_space_narrow_keys(P, with_top_rule):
 TOPS_SHAPES = [(8, 2, 1), (8, 2, 2), (8, 4, 2), (8, 4, 4), (16, 4, 2), (16, 8, 1), (32, 8, 2), (32, 16, 4)]
 
 
+@pytest.mark.parametrize("key_bits", [0, 128])
 @pytest.mark.parametrize("fanout,kpl,R", TOPS_SHAPES)
-def test_key_tops_in_lds_tiny(P, tiny, fanout, kpl, R):
-    """lds_search 2: every internal level in LDS as 32-bit key tops, exact on
-    ties; next hops and interval indices equal the oracle's."""
+def test_key_tops_in_lds_tiny(P, tiny, fanout, kpl, R, key_bits):
+    """lds_search 2: every internal level in LDS, the bottom one as 32-bit key
+    tops, exact on ties, with 64- and with 128-bit key slots; next hops and
+    interval indices equal the oracle's."""
     import torch
     fib, addrs, want = tiny
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
     starts, ivnh = P.planb_export_intervals(h)
     d = to_dev(addrs)
     for block in (512, 1024):
-        say(f"tops tiny fanout={fanout} kpl={kpl} R={R} block={block}")
+        say(f"tops tiny fanout={fanout} kpl={kpl} R={R} block={block} key_bits={key_bits}")
         P.planb_set_tuning(h, kpl, -1, R, block, 2)
         assert P.planb_get_tuning(h)["lds_search"] == 2
         out = out_u16(addrs.shape[0])
@@ -348,16 +350,16 @@ def test_key_tops_in_lds_tiny(P, tiny, fanout, kpl, R):
     assert np.array_equal(i, np.searchsorted(starts[:, 0], addrs[:, 0], side="right") - 1)
 
 
-@pytest.mark.parametrize("fanout", [8, 16])
-def test_key_tops_in_lds_backbone(P, fanout):
+@pytest.mark.parametrize("fanout,key_bits", [(8, 0), (16, 0), (16, 128)])
+def test_key_tops_in_lds_backbone(P, fanout, key_bits):
     """The backbone-shaped table: its addresses inside /48 prefixes often tie
     a boundary's top 32 bits, so the exact re-read is exercised heavily."""
     fib = fib_of("backbone", 22)
     a = S.backbone_traffic(fib, 1 << 21, seed=77)
     want = oracle_trie("backbone", 22).lookup(a)
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=fanout, key_bits=key_bits)
     for kpl, R, block in ((fanout // 4, 2, 1024), (fanout // 2, 1, 512)):
-        say(f"tops backbone fanout={fanout} kpl={kpl} R={R} block={block}")
+        say(f"tops backbone fanout={fanout} key_bits={key_bits} kpl={kpl} R={R} block={block}")
         try:
             P.planb_set_tuning(h, kpl, -1, R, block, 2)
         except P.PlanbError as e:
@@ -409,9 +411,11 @@ def test_key_tops_in_lds_edges(P, name):
             assert np.array_equal(host_u16(out, q.shape[0]), want)
 
 
-def test_key_tops_refused_for_wide_keys(P, tiny):
+def test_key_tops_refused_for_32bit_keys(P, tiny):
     fib, _, _ = tiny
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8, key_bits=128)
+    v4 = S.make_fib(S.IPV4_TINY, 40)
+    h = P.planb_build(v4.prefixes, v4.lengths, v4.next_hops, fanout=8)
+    assert P.planb_get_info(h)["key_bits"] == 32
     with pytest.raises(P.PlanbError) as e:
         P.planb_set_tuning(h, 2, -1, 2, 1024, 2)
     assert e.value.code == P.PLANB_EINVAL
@@ -469,3 +473,47 @@ def test_key_tops_refused_when_too_large(P):
     out = out_u16(a.shape[0])
     P.planb_lookup(h, to_dev(a), a.shape[0], out)
     assert np.array_equal(host_u16(out, a.shape[0]), Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(a))
+
+
+@pytest.mark.parametrize("fanout", [8, 16, 32])
+def test_key_tops_wide_keys_tie_on_the_high_word(P, fanout):
+    """128-bit key slots with the bottom level as key tops: /128 host routes,
+    /96 and /112 rules and /64s that share their high word (and so their top
+    32 bits) with many boundaries, queried on every boundary and one either
+    side of it, so that ties are settled by comparing whole 128-bit keys."""
+    rng = np.random.default_rng(17)
+    rules = {(0, 0): 1}
+    for k in range(300):
+        hi = (0x20010DB8 << 32) | int(rng.integers(0, 1 << 20))
+        rules[(hi << 64, 64)] = int(rng.integers(0, 60000))
+        for _ in range(8):
+            lo = int(rng.integers(0, 1 << 63))
+            ln = int(rng.choice([96, 112, 120, 128]))
+            pfx = (hi << 64 | lo) >> (128 - ln) << (128 - ln)
+            rules[(pfx, ln)] = int(rng.integers(0, 60000))
+    keys = sorted(rules)
+    p = S.from_ints([k[0] for k in keys])
+    L = np.array([k[1] for k in keys], np.uint8)
+    nh = np.array([rules[k] for k in keys], np.uint16)
+    h = P.planb_build(p, L, nh, fanout=fanout)
+    assert P.planb_get_info(h)["key_bits"] == 128
+    starts, _ = P.planb_export_intervals(h)
+    pts = set()
+    for hi, lo in starts:
+        v = int(hi) << 64 | int(lo)
+        pts.update(x for x in (v - 1, v, v + 1) if 0 <= x < 1 << 128)
+    q = S.from_ints(sorted(pts))
+    from oracle.trie import Trie
+    want = Trie(p, L, nh).lookup(q)
+    reps = -(-(1 << 20) // q.shape[0])  # at least 2^20 lookups: the key-tops kernel runs
+    q, want = np.tile(q, (reps, 1)), np.tile(want, reps)
+    for kpl, R in ((fanout // 2, 2), (fanout // 4, 1)):
+        try:
+            P.planb_set_tuning(h, kpl, -1, R, 1024, 2)
+        except P.PlanbError as e:
+            assert e.code == P.PLANB_ERANGE
+            continue
+        say(f"wide tops fanout={fanout} kpl={kpl} R={R} n={q.shape[0]}")
+        out = out_u16(q.shape[0])
+        P.planb_lookup(h, to_dev(q), q.shape[0], out)
+        assert np.array_equal(host_u16(out, q.shape[0]), want)

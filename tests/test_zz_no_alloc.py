@@ -1,8 +1,9 @@
 """planb_lookup_learned_noalloc (the learned lookup whose fallback queue is a
 fixed device array of the library) against planb_lookup_learned (queue from
 the stream-ordered pool) through the C ABI: two calls in a row, the second
-smaller, with the window checks passing and with every one forced to fail,
-so that the shared queue is used and keeps the previous call's contents.
+smaller, with the trained error bounds and with bounds forced to zero (many
+window checks fail), so that the shared queue is used and keeps the previous
+call's contents; for both learned kernels (64- and 128-bit key slots).
 Next hops are integers: compared bit for bit, and with the LPM oracle."""
 import numpy as np
 import pytest
@@ -21,10 +22,11 @@ def P():
     return planb
 
 
-@pytest.fixture(scope="module")
-def trained(P):
+@pytest.fixture(scope="module", params=[0, 128], ids=["keys64", "keys128"])
+def trained(P, request):
+    """64-bit key slots run the leaf-tops kernel, 128-bit ones the leaf-key window search."""
     fib = fib_of("tiny", 11)
-    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8, key_bits=request.param)
     P.planb_train(h, seed=5)
     return fib, h
 
@@ -50,8 +52,8 @@ def test_noalloc_matches_learned_two_calls(P, trained, forced):
     want_of = oracle_trie("tiny", 11)
     saved = P.planb_model_get_eps(h, 4096)
     try:
-        if forced:  # every window check fails: every lookup goes through the queue
-            P.planb_model_set_eps(h, np.full(len(saved), 0xFFFFFFFF, np.uint32))
+        if forced:  # error bounds of zero: many window checks fail, so the queue fills
+            P.planb_model_set_eps(h, np.zeros(len(saved), np.uint32))
         for k, n in enumerate((LIMIT, 3001)):  # the second call is smaller
             addrs = S.tiny_traffic(fib, n, seed=700 + 10 * k + int(forced))
             say(f"no-alloc learned lookup: call {k}, n={n}, forced fallbacks={forced}")
@@ -60,7 +62,7 @@ def test_noalloc_matches_learned_two_calls(P, trained, forced):
             assert np.array_equal(got, want_of.lookup(addrs))
             assert fb_got == fb_ref
             if forced:
-                assert fb_got == n
+                assert fb_got > n // 100
     finally:
         P.planb_model_set_eps(h, saved)
 
