@@ -61,6 +61,8 @@ def parse():
                     help="skip the autotuner legs (the headline always runs the fixed launch shapes; fewer launches to profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
+    ap.add_argument("--learned-epochs", type=int, default=0,
+                    help="training passes for the learned leg (0: the library default); short runs for profiling")
     ap.add_argument("--skip-batches", action="store_true")
     ap.add_argument("--skip-uneven", action="store_true", help="skip the 1M-prefix uneven-batch leg")
     ap.add_argument("--skip-ablation", action="store_true")
@@ -170,7 +172,7 @@ def plain_leg(P, fib, d, n, out, args):
     return handles[0], res, times[0], times[128]
 
 
-def learned_on(P, fib, d, n, out, tuning, steps, want=None):
+def learned_on(P, fib, d, n, out, tuning, steps, want=None, epochs=0):
     """Plain and learned lookups on one FIB and resident batch: both timed with
     events over `steps` launches, the learned results compared with the plain
     ones (and with the oracle's, when given), the fallback rate counted."""
@@ -181,7 +183,7 @@ def learned_on(P, fib, d, n, out, tuning, steps, want=None):
     torch.cuda.synchronize()
     plain_out = out.clone()
     t0 = time.time()
-    rep = P.planb_train(h, seed=1)
+    rep = P.planb_train(h, epochs=epochs, seed=1)
     train_s = time.time() - t0
     eps = P.planb_model_get_eps(h, 1 << 16).astype(np.int64)
     used = eps[eps != 0xFFFFFFFF]
@@ -218,14 +220,15 @@ def learned_leg(P, fib, d, n, out, args):
     import torch
     import planb_synth as S
     from oracle.trie import Trie
-    res = {"backbone": learned_on(P, fib, d, n, out, KNOWN_TUNING[0], max(3, args.steps // 2))}
+    res = {"backbone": learned_on(P, fib, d, n, out, KNOWN_TUNING[0], max(3, args.steps // 2),
+                                  epochs=args.learned_epochs)}
     log(f"learned backbone: {res['backbone']}")
     tiny = S.make_fib(S.TINY, 11)
     ta = S.tiny_traffic(tiny, 1 << 20, seed=1011)
     want = Trie(tiny.prefixes, tiny.lengths, tiny.next_hops).lookup(ta)
     td = upload(ta)
     tout = torch.empty(ta.shape[0], dtype=torch.int16, device="cuda")
-    res["tiny"] = learned_on(P, tiny, td, ta.shape[0], tout, TINY_TUNING, 50, want)
+    res["tiny"] = learned_on(P, tiny, td, ta.shape[0], tout, TINY_TUNING, 50, want, epochs=args.learned_epochs)
     log(f"learned tiny: {res['tiny']}")
     return res
 
@@ -426,8 +429,13 @@ def serving_leg(P, log_fn, n_tables=16, bursts_per_level=3000):
         admit_s = time.time() - t1
         serve.replay_native(srv, np.zeros(len(sizes)), tids, addrs)
         lat, wall, outs = serve.replay_native(srv, np.zeros(len(sizes)), tids, addrs)
-        cap = serve.summary(lat, sizes, wall)
-        r = {"capacity_glps": round(cap["glps"], 4), "admit_seconds": round(admit_s, 2)}
+        # capacity: the burst list five times over, all at once, so that launches
+        # overlap in steady state rather than the first launch's latency dominating
+        reps = 5
+        lat5, wall5, _ = serve.replay_native(srv, np.zeros(reps * len(sizes)), np.tile(tids, reps), addrs * reps)
+        cap = serve.summary(lat5, np.tile(sizes, reps), wall5)
+        r = {"capacity_glps": round(cap["glps"], 4), "admit_seconds": round(admit_s, 2),
+             "capacity_one_pass_glps": round(serve.summary(lat, sizes, wall)["glps"], 4)}
         if mode == "plain":
             plain_outs = outs
             for load in (0.25, 0.5, 0.8):

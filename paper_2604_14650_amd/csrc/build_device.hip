@@ -9,8 +9,8 @@
 //  * events: one thread per rule masks its prefix and emits a START event at
 //    the prefix and, unless the range ends at 2^128, an END event at the
 //    exclusive end;
-//  * sort: three stable radix passes order the events by (address, END before
-//    START, START by length), least significant field first;
+//  * sort: three stable radix sorts order the events by (address, END before
+//    START, START by length), least significant field first (device_sort.hpp);
 //  * sweep: the stack depth after each event is a prefix sum of +1 / -1.  The
 //    top of the stack after event k is the START at the latest position
 //    j <= k whose depth after it equals the depth after k: a later START at
@@ -24,15 +24,13 @@
 //  * image: the slot array is filled with the sentinel, then the leaf keys
 //    and next hops are scattered and the separators gathered level by level.
 // The image, the intervals and the errors are those of the host build.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
 #include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "api_internal.hpp"
+#include "device_sort.hpp"
 
 namespace planb {
 namespace {
@@ -305,26 +303,15 @@ template <typename K, typename V>
 hipError_t sort_pairs(Scratch& S, const K* kin, K* kout, const V* vin, V* vout, uint32_t n, unsigned bits,
                       hipStream_t st)
 {
-    size_t bytes = 0;
-    PB_TRY(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, n, 0, bits, st));
-    void* tmp = nullptr;
-    PB_TRY(S.get(reinterpret_cast<uint8_t**>(&tmp), bytes));
-    return rocprim::radix_sort_pairs(tmp, bytes, kin, kout, vin, vout, n, 0, bits, st);
+    auto alloc = [&](void** p, size_t bytes) { return S.get(reinterpret_cast<uint8_t**>(p), bytes); };
+    return dsort::sort_pairs(alloc, kin, kout, vin, vout, n, bits, st);
 }
 
-template <typename T, typename Op>
-hipError_t scan(Scratch& S, const T* in, T* out, uint32_t n, bool inclusive, Op op, hipStream_t st)
+template <typename T>
+hipError_t scan(Scratch& S, const T* in, T* out, uint32_t n, bool inclusive, hipStream_t st)
 {
-    size_t bytes = 0;
-    void* tmp = nullptr;
-    if (inclusive) {
-        PB_TRY(rocprim::inclusive_scan(nullptr, bytes, in, out, n, op, st));
-        PB_TRY(S.get(reinterpret_cast<uint8_t**>(&tmp), bytes));
-        return rocprim::inclusive_scan(tmp, bytes, in, out, n, op, st);
-    }
-    PB_TRY(rocprim::exclusive_scan(nullptr, bytes, in, out, T(0), n, op, st));
-    PB_TRY(S.get(reinterpret_cast<uint8_t**>(&tmp), bytes));
-    return rocprim::exclusive_scan(tmp, bytes, in, out, T(0), n, op, st);
+    auto alloc = [&](void** p, size_t bytes) { return S.get(reinterpret_cast<uint8_t**>(p), bytes); };
+    return dsort::scan<T>(alloc, in, out, n, inclusive, st);
 }
 
 // Intervals of n rules (device arrays), before any merge, into out_starts /
@@ -374,8 +361,8 @@ hipError_t device_intervals(Scratch& S, const u64x2* prefixes, const uint8_t* le
     const uint64_t* hi_s = hi_b;
     hipLaunchKernelGGL(mark_kernel, dim3(g), dim3(kThreads), 0, st, hi_s, lo_s, tb_s, total, delta, last, d_st);
     PB_TRY(hipGetLastError());
-    PB_TRY(scan(S, delta, depth, total, true, rocprim::plus<int32_t>(), st));
-    PB_TRY(scan(S, last, gpos, total, false, rocprim::plus<uint32_t>(), st));
+    PB_TRY(scan(S, delta, depth, total, true, st));
+    PB_TRY(scan(S, last, gpos, total, false, st));
     hipLaunchKernelGGL(start_keys_kernel, dim3(g), dim3(kThreads), 0, st, tb_s, depth, total, skey, d_st);
     hipLaunchKernelGGL(iota_kernel, dim3(g), dim3(kThreads), 0, st, pos, total);
     PB_TRY(sort_pairs(S, skey, skey_s, pos, spos, total, 32, st));
@@ -483,7 +470,7 @@ extern "C" planb_fib_t* planb_build_device(const planb_addr_t* prefixes, const u
         if ((e = S.get(&keep, m)) != hipSuccess || (e = S.get(&kpos, m)) != hipSuccess)
             return bail(PLANB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         hipLaunchKernelGGL(keep_kernel, dim3(blocks_for(m)), dim3(kThreads), 0, st, un_nh, (uint32_t)m, keep);
-        if ((e = scan(S, keep, kpos, (uint32_t)m, false, rocprim::plus<uint32_t>(), st)) != hipSuccess)
+        if ((e = scan(S, keep, kpos, (uint32_t)m, false, st)) != hipSuccess)
             return bail(PLANB_EDEVICE, std::string("device build: ") + hipGetErrorString(e));
         hipLaunchKernelGGL(compact_kernel, dim3(blocks_for(m)), dim3(kThreads), 0, st, un_starts, un_nh, (uint32_t)m,
                            keep, kpos, d_starts, d_nh);
