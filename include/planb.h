@@ -519,8 +519,16 @@ typedef struct planb_server_cfg {
     uint64_t memory_budget; /* device bytes for resident trees (0 = unlimited) */
     uint32_t learned;       /* 1: train a learned model (a short run: 8 passes) for every table when it is admitted and
                                serve bursts with planb_lookup_multi_learned (0: planb_lookup_multi) */
-    uint32_t reserved;      /* 0 */
+    uint32_t flags;         /* PLANB_SERVER_* (0: bursts staged through pinned copies) */
 } planb_server_cfg_t;
+
+/* Zero-copy serving: the lookup kernels read each burst's addresses from, and
+ * write its next hops to, the caller's host memory directly over PCIe; there
+ * are no staging copies on the host nor DMA copies per launch.  Every burst's
+ * addrs and out must then lie in pinned host memory registered with
+ * planb_server_register_io (planb_server_submit returns PLANB_EINVAL
+ * otherwise).  Completion (poll) means the next hops are in out. */
+#define PLANB_SERVER_ZERO_COPY 1u
 
 typedef struct planb_completion {
     int64_t tag;      /* the submitter's tag */
@@ -545,9 +553,15 @@ int planb_server_set_table(planb_server_t* server, uint32_t id, const planb_addr
 /* Queues a burst: addrs (host, n records) must stay valid and unchanged, and
  * out (host, n uint16) is written, until poll returns the burst's completion
  * (the addresses are copied to pinned staging when the burst joins a launch,
- * so submitting costs no copy). */
+ * so submitting costs no copy; with PLANB_SERVER_ZERO_COPY the kernels read
+ * and write the caller's registered buffers themselves). */
 int planb_server_submit(planb_server_t* server, uint32_t table, const planb_addr_t* addrs, uint32_t n,
                         uint16_t* out, int64_t tag);
+/* Registers [base, base + bytes) as I/O memory for zero-copy bursts.  It must
+ * be pinned host memory the device can address at the same addresses
+ * (hipHostMalloc, or a pinned torch tensor); PLANB_EINVAL otherwise.  At most
+ * 64 ranges; the memory must stay allocated while the server may use it. */
+int planb_server_register_io(planb_server_t* server, const void* base, size_t bytes);
 /* Progresses the server and returns up to cap completions (count >= 0 or a
  * status).  block != 0 waits until at least one completion is available or
  * nothing is queued or in flight. */

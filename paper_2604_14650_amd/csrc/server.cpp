@@ -107,6 +107,7 @@ struct planb_server {
     std::deque<Pending> queue;
     std::vector<Slot> slots;
     std::deque<planb_completion_t> done;
+    std::vector<std::pair<uintptr_t, uintptr_t>> io;  // registered zero-copy ranges [lo, hi)
     uint64_t used_bytes = 0;
     planb_server_stats_t stats{};
 };
@@ -196,11 +197,14 @@ int admit(planb_server_t* s, uint32_t id, bool* ok)
     return PLANB_OK;
 }
 
+bool zero_copy(const planb_server_t* s) { return (s->cfg.flags & PLANB_SERVER_ZERO_COPY) != 0; }
+
 void finish_slot(planb_server_t* s, Slot& sl)
 {
     const double t = now_us();
     for (Pending& p : sl.bursts) {
-        std::memcpy(p.out, sl.h_out + p.offset, (size_t)p.n * sizeof(uint16_t));
+        if (!zero_copy(s))  // zero-copy launches wrote the caller's buffer themselves
+            std::memcpy(p.out, sl.h_out + p.offset, (size_t)p.n * sizeof(uint16_t));
         planb_completion_t c{};
         c.tag = p.tag;
         c.table = p.table;
@@ -320,8 +324,12 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
             fibs.push_back(t.fib);
             ++t.inflight;  // no eviction of this table while the launch is built or runs
         }
-        copies.push_back(CopyJob{sl.h_in + na, p.addrs, (size_t)p.n * sizeof(planb_addr_t)});
-        desc[nb] = BurstRec{s->local[p.table], p.n, reinterpret_cast<const u64x2*>(sl.d_in + na), sl.d_out + na};
+        if (zero_copy(s)) {  // registered pinned memory, addressed by the device as it is
+            desc[nb] = BurstRec{s->local[p.table], p.n, reinterpret_cast<const u64x2*>(p.addrs), p.out};
+        } else {
+            copies.push_back(CopyJob{sl.h_in + na, p.addrs, (size_t)p.n * sizeof(planb_addr_t)});
+            desc[nb] = BurstRec{s->local[p.table], p.n, reinterpret_cast<const u64x2*>(sl.d_in + na), sl.d_out + na};
+        }
         p.offset = na;
         na += p.n;
         ++nb;
@@ -339,7 +347,7 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
         trees[k].lds_slots = 0;
         models[k] = ready_model_desc(fibs[k]);
     }
-    run_copies(copies, (size_t)na * sizeof(planb_addr_t));
+    if (!copies.empty()) run_copies(copies, (size_t)na * sizeof(planb_addr_t));
     std::memcpy(sl.h_desc, &nb, sizeof(uint32_t));
     const BurstRec* d_bursts = reinterpret_cast<const BurstRec*>(sl.d_desc + s->lay.bursts);
     const TreeDesc* d_trees = reinterpret_cast<const TreeDesc*>(sl.d_desc + s->lay.trees);
@@ -347,12 +355,13 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
     const uint32_t* d_count = reinterpret_cast<const uint32_t*>(sl.d_desc);
     const uint32_t nt = (uint32_t)tabs.size();
     hipError_t e;
-    if ((e = hipMemcpyAsync(sl.d_in, sl.h_in, (size_t)na * 16, hipMemcpyHostToDevice, sl.st)) != hipSuccess ||
+    const bool zc = zero_copy(s);
+    if ((!zc && (e = hipMemcpyAsync(sl.d_in, sl.h_in, (size_t)na * 16, hipMemcpyHostToDevice, sl.st)) != hipSuccess) ||
         (e = hipMemcpyAsync(sl.d_desc, sl.h_desc, s->lay.bytes, hipMemcpyHostToDevice, sl.st)) != hipSuccess ||
         (e = s->cfg.learned ? launch_multi_learned(s->launch, d_trees, d_models, nt, d_bursts, d_count, maxb, nullptr,
                                                    sl.st)
                             : launch_multi(s->launch, d_trees, nt, d_bursts, d_count, maxb, sl.st)) != hipSuccess ||
-        (e = hipMemcpyAsync(sl.h_out, sl.d_out, (size_t)na * 2, hipMemcpyDeviceToHost, sl.st)) != hipSuccess ||
+        (!zc && (e = hipMemcpyAsync(sl.h_out, sl.d_out, (size_t)na * 2, hipMemcpyDeviceToHost, sl.st)) != hipSuccess) ||
         (e = hipEventRecord(sl.done->ev, sl.st)) != hipSuccess) {
         // work already enqueued on the stream may still read the staging buffers:
         // wait for it before they can be refilled
@@ -394,7 +403,8 @@ planb_server_t* planb_server_create(const planb_server_cfg_t* cfg_in)
         fail(PLANB_EINVAL, "server fanout must be 8/16/32 and key_bits 32, 64 or 128");
         return nullptr;
     }
-    if (cfg.streams > 8 || cfg.max_tables > 65536 || cfg.max_bursts > 16384 || cfg.learned > 1 || cfg.reserved) {
+    if (cfg.streams > 8 || cfg.max_tables > 65536 || cfg.max_bursts > 16384 || cfg.learned > 1 ||
+        (cfg.flags & ~PLANB_SERVER_ZERO_COPY)) {
         fail(PLANB_EINVAL, "server configuration out of range");
         return nullptr;
     }
@@ -478,6 +488,18 @@ int planb_server_submit(planb_server_t* s, uint32_t table, const planb_addr_t* a
     if (table >= s->cfg.max_tables || !s->tables[table].registered) return fail(PLANB_EINVAL, "unknown table id");
     if (n > s->cfg.max_lookups) return fail(PLANB_ERANGE, "burst larger than max_lookups");
     if (n && (!addrs || !out)) return fail(PLANB_EINVAL, "NULL host buffer");
+    if (n && zero_copy(s)) {  // the kernels will address both buffers: they must be registered pinned memory
+        auto inside = [&](const void* p, size_t bytes) {
+            const uintptr_t lo = reinterpret_cast<uintptr_t>(p), hi = lo + bytes;
+            for (const auto& r : s->io)
+                if (lo >= r.first && hi <= r.second) return true;
+            return false;
+        };
+        if (!inside(addrs, (size_t)n * sizeof(planb_addr_t)) || !inside(out, (size_t)n * sizeof(uint16_t)))
+            return fail(PLANB_EINVAL, "zero-copy bursts must lie in memory registered with planb_server_register_io");
+        if (reinterpret_cast<uintptr_t>(addrs) % 16 || reinterpret_cast<uintptr_t>(out) % 2)
+            return fail(PLANB_EINVAL, "misaligned burst buffer");
+    }
     Pending p;
     p.tag = tag;
     p.table = table;
@@ -486,6 +508,26 @@ int planb_server_submit(planb_server_t* s, uint32_t table, const planb_addr_t* a
     p.out = out;
     p.submit_us = now_us();
     s->queue.push_back(std::move(p));
+    return PLANB_OK;
+}
+
+int planb_server_register_io(planb_server_t* s, const void* base, size_t bytes)
+{
+    if (!s || !base || bytes == 0) return fail(PLANB_EINVAL, "NULL server or empty range");
+    if (s->io.size() >= 64) return fail(PLANB_ERANGE, "at most 64 I/O ranges");
+    // both ends must be pinned host memory that the device addresses as the host does
+    for (const char* p : {static_cast<const char*>(base), static_cast<const char*>(base) + bytes - 1}) {
+        hipPointerAttribute_t a{};
+        hipError_t e = hipPointerGetAttributes(&a, p);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PLANB_EINVAL, "I/O range is not pinned host memory (hipPointerGetAttributes failed)");
+        }
+        if (a.type != hipMemoryTypeHost || !a.devicePointer || a.devicePointer != a.hostPointer)
+            return fail(PLANB_EINVAL, "I/O range must be pinned host memory addressed by the device as by the host");
+    }
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(base);
+    s->io.emplace_back(lo, lo + bytes);
     return PLANB_OK;
 }
 

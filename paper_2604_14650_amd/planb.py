@@ -25,6 +25,7 @@ PLANB_ERANGE = -5
 PLANB_NO_ROUTE = 0xFFFF
 PLANB_FLAG_MERGE_EQUAL_NH = 1
 PLANB_MAX_LEVELS = 16
+PLANB_SERVER_ZERO_COPY = 1
 
 # torch bundles its own libamdhip64.so.7.  Loading torch first makes the
 # dynamic linker resolve this library's libamdhip64.so.7 to that same, already
@@ -85,7 +86,7 @@ class planb_burst_t(ctypes.Structure):
 class planb_server_cfg_t(ctypes.Structure):
     _fields_ = [("max_tables", ctypes.c_uint32), ("streams", ctypes.c_uint32), ("max_bursts", ctypes.c_uint32),
                 ("max_lookups", ctypes.c_uint32), ("fanout", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
-                ("memory_budget", ctypes.c_uint64), ("learned", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("memory_budget", ctypes.c_uint64), ("learned", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class planb_completion_t(ctypes.Structure):
@@ -160,6 +161,7 @@ _sig("planb_lookup_multi", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp)
 _sig("planb_lookup_multi_learned", ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, _vp, _vp)
 _sig("planb_tableset_free", None, _vp)
 _sig("planb_server_create", _vp, ctypes.POINTER(planb_server_cfg_t))
+_sig("planb_server_register_io", ctypes.c_int, _vp, _vp, _sz)
 _sig("planb_server_free", None, _vp)
 _sig("planb_server_set_table", ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp, _vp, _sz)
 _sig("planb_server_submit", ctypes.c_int, _vp, ctypes.c_uint32, _vp, ctypes.c_uint32, _vp, ctypes.c_int64)
@@ -730,9 +732,9 @@ class Server:
     """Owner of a planb_server_t* (see planb.h for the semantics)."""
 
     def __init__(self, max_tables=16, streams=2, max_bursts=1024, max_lookups=1 << 20, fanout=16, key_bits=128,
-                 memory_budget=0, learned=False):
+                 memory_budget=0, learned=False, zero_copy=False):
         self.cfg = planb_server_cfg_t(max_tables, streams, max_bursts, max_lookups, fanout, key_bits, memory_budget,
-                                      1 if learned else 0, 0)
+                                      1 if learned else 0, PLANB_SERVER_ZERO_COPY if zero_copy else 0)
         self.ptr = _lib.planb_server_create(ctypes.byref(self.cfg))
         if not self.ptr:
             raise PlanbError(planb_last_status(), planb_last_error())
@@ -779,6 +781,21 @@ class Server:
         wall = ctypes.c_double(0.0)
         _check(_lib.planb_server_replay(self.ptr, arr.shape[0], arr.ctypes.data, tb.ctypes.data, off.ctypes.data,
                                         a.ctypes.data, out.ctypes.data, lat.ctypes.data, ctypes.byref(wall)))
+        return lat, wall.value
+
+    def register_io(self, ptr: int, nbytes: int):
+        """Registers pinned host memory [ptr, ptr + nbytes) for zero-copy bursts."""
+        _check(_lib.planb_server_register_io(self.ptr, ptr, nbytes))
+
+    def replay_raw(self, arrival_us, tables, offsets, addrs_ptr: int, out_ptr: int):
+        """planb_server_replay over raw host pointers (e.g. pinned tensors); returns (latency_us, wall_s)."""
+        arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        tb = np.ascontiguousarray(tables, dtype=np.uint32)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        lat = np.zeros(arr.shape[0], dtype=np.float64)
+        wall = ctypes.c_double(0.0)
+        _check(_lib.planb_server_replay(self.ptr, arr.shape[0], arr.ctypes.data, tb.ctypes.data, off.ctypes.data,
+                                        addrs_ptr, out_ptr, lat.ctypes.data, ctypes.byref(wall)))
         return lat, wall.value
 
     def stats(self) -> dict:

@@ -283,3 +283,41 @@ def test_serving_replay_reports_latency(P, vrfs):
     for i in range(len(addrs)):
         assert np.array_equal(outs[i], tries[tids[i]].lookup(addrs[i]))
     srv.close()
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_zero_copy_server_equals_oracle(P, vrfs, learned):
+    """Zero-copy serving: the kernels read the bursts from, and write the next
+    hops to, registered pinned host memory; every burst equals the oracle, and
+    a burst outside the registered memory is refused before any launch."""
+    from paper_2604_14650_amd import serve
+    tabs, tries = vrfs
+    srv = P.Server(max_tables=len(tabs), streams=3, max_bursts=64, max_lookups=1 << 16, fanout=16, key_bits=64,
+                   learned=learned, zero_copy=True)
+    for k, t in enumerate(tabs):
+        srv.set_table(k, t.prefixes, t.lengths, t.next_hops)
+    sizes, tids, addrs = _bursts(tabs, 300, 11)
+    io = serve.pinned_io(addrs)
+    say(f"zero-copy server learned={learned}: {int(sizes.sum())} lookups in {len(addrs)} bursts")
+    lat, wall, outs = serve.replay_zero_copy(srv, np.zeros(len(addrs)), tids, io)
+    for i in range(len(addrs)):
+        assert np.array_equal(outs[i], tries[tids[i]].lookup(addrs[i])), i
+    # arrivals spread out: the same results
+    lat, wall, outs2 = serve.replay_zero_copy(srv, np.arange(len(addrs)) * 2e-6, tids, io)
+    assert all(np.array_equal(a, b) for a, b in zip(outs, outs2))
+    pageable = np.zeros((16, 2), np.uint64)
+    with pytest.raises(P.PlanbError) as e:
+        srv.submit(0, pageable, np.zeros(16, np.uint16), 99)
+    assert e.value.code == P.PLANB_EINVAL
+    srv.close()
+
+
+def test_zero_copy_registration_refuses_pageable_memory(P, vrfs):
+    tabs, _ = vrfs
+    srv = P.Server(max_tables=2, streams=1, max_bursts=16, max_lookups=1 << 12, fanout=16, key_bits=64,
+                   zero_copy=True)
+    buf = np.zeros(4096, np.uint64)
+    with pytest.raises(P.PlanbError) as e:
+        srv.register_io(buf.ctypes.data, buf.nbytes)
+    assert e.value.code == P.PLANB_EINVAL
+    srv.close()
