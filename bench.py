@@ -142,7 +142,7 @@ def profiled_kernel_ns(per_launch_lookups: int, config: str):
 
 
 # Launch shapes the autotuner chose for this workload on MI355X (used with --no-autotune).
-KNOWN_TUNING = {0: {"fanout": 8, "tuning": (2, 5, 2, 1024, 2)}, 128: {"fanout": 8, "tuning": (4, 5, 1, 1024, 1)}}
+KNOWN_TUNING = {0: {"fanout": 8, "tuning": (2, 5, 2, 1024, 2)}, 128: {"fanout": 8, "tuning": (2, 5, 1, 1024, 1)}}
 # the tiny FIB (2,003 intervals): every level in LDS, one lane group per lookup
 TINY_TUNING = {"fanout": 8, "tuning": (2, -1, 2, 1024, 1)}
 

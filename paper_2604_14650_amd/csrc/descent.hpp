@@ -36,12 +36,44 @@ struct Descent {
     // Bytes of LDS the top levels of t take.
     static __host__ __device__ size_t lds_bytes(const TreeDesc& t) { return (size_t)t.lds_slots * sizeof(K); }
 
-    // Copy the first t.lds_slots slots (the top t.lds_levels levels) to LDS.
+    // LDS slot permutation of the hybrid descent over 16-byte keys.  Its
+    // lanes binary-search different nodes, probing the same slot of each:
+    // with nodes laid out contiguously, that slot of every node falls in the
+    // few banks a node's offset within a 256-byte row of the 64 four-byte
+    // banks allows, and the wavefront's reads conflict.  So internal node n
+    // keeps key k at slot k ^ lds_swz(n) of its LDS copy, lds_swz(n) taken
+    // from the bits of n above those that place the node in its row.  At
+    // b = 8 this took 128-bit key slots from 45.7 to 54.7 GLPS on the 200k
+    // backbone FIB; with 8-byte keys (four 64-byte nodes per row) it cost
+    // 1.7% on the same FIB, so narrower keys keep the plain layout.
+    static constexpr bool kSwz = kHybrid && sizeof(K) == 16;
+    static constexpr uint32_t kRowNodes = B * sizeof(K) >= 256 ? 1u : (uint32_t)(256 / (B * sizeof(K)));
+    static __device__ __forceinline__ uint32_t lds_swz(uint32_t n)
+    {
+        if constexpr (kSwz)
+            return (n / kRowNodes) & (uint32_t)(B - 1);
+        else
+            return 0;
+    }
+
+    // Copy the first t.lds_slots slots (the top t.lds_levels levels) to LDS,
+    // internal nodes permuted by lds_swz, leaves (a whole tree in LDS) as they are.
     static __device__ void stage(const TreeDesc& t, uint4* lds_raw, int tid, int nthreads)
     {
+        uint32_t done = 0;  // slots copied with the permutation
+        if constexpr (kSwz) {
+            done = t.lds_slots < t.leaf_base ? t.lds_slots : t.leaf_base;
+            const K* src = static_cast<const K*>(t.keys);
+            K* dst = reinterpret_cast<K*>(lds_raw);
+            for (uint32_t i = tid; i < done; i += nthreads) {
+                const uint32_t n = i / (uint32_t)B, k = i % (uint32_t)B;
+                dst[n * (uint32_t)B + (k ^ lds_swz(n))] = src[i];
+            }
+        }
+        // internal nodes are B * sizeof(K) >= 32 bytes: done is a whole number of 16-byte units
         const uint32_t units = (uint32_t)(t.lds_slots * sizeof(K) / 16);
         const uint4* src = static_cast<const uint4*>(t.keys);
-        for (uint32_t i = tid; i < units; i += nthreads) lds_raw[i] = src[i];
+        for (uint32_t i = (uint32_t)(done * sizeof(K) / 16) + tid; i < units; i += nthreads) lds_raw[i] = src[i];
     }
 
     // The bottom internal level (level t.depth - 2) in LDS as the top 32 bits
@@ -347,9 +379,12 @@ struct Descent {
     template <bool FROM_LDS>
     static __device__ __forceinline__ uint32_t lane_bincount(const K* keys, size_t node0, uint64_t xhi, uint64_t xlo)
     {
+        // from LDS, 16-byte keys are permuted within the node (stage)
+        const uint32_t sw = FROM_LDS ? lds_swz((uint32_t)(node0 / B)) : 0u;
         uint32_t c = 0;  // keys <= x among slots 0..B-2 (see node_count)
 #pragma unroll
-        for (int step = B / 2; step >= 1; step >>= 1) c += KF::le(keys[node0 + c + step - 1], xhi, xlo) ? step : 0;
+        for (int step = B / 2; step >= 1; step >>= 1)
+            c += KF::le(keys[node0 + ((c + (uint32_t)step - 1) ^ sw)], xhi, xlo) ? step : 0;
         return c;
     }
 
@@ -370,7 +405,7 @@ struct Descent {
     static __device__ __forceinline__ void bottom_search(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
                                                          const uint32_t* q, Bottom& bs)
     {
-        const uint32_t lvl = bottom_level(t), off = t.off[lvl];
+        const uint32_t lvl = bottom_level(t), lim = t.last[lvl + 1];
         const K* gkeys = static_cast<const K*>(t.keys);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -385,25 +420,36 @@ struct Descent {
             }
             bs.c[r] = c;
             bs.last[r] = last;
-            // every lane loads; the untied ones all read slot 0 (one shared line), so
-            // the load is not in a branch and its wait can follow the shuffles
+            // Key c - 1 of node q separates leaves qB + c - 1 and qB + c, and is
+            // the first key of leaf qB + c, whose slot 0 holds it too.  Reading it
+            // there keeps the bottom level out of the caches, and when the tie
+            // resolves to "<=" that leaf is the one read next.  Past the last leaf
+            // the separator is the sentinel; the last leaf's first key then gives
+            // the same child once clamped to the last leaf (if it is <= x, both
+            // end at the last leaf; if > x, both step back).  Every lane loads;
+            // the untied ones all read slot 0 (one shared line), so the load is
+            // not in a branch and its wait can follow the shuffles.
             const bool tie = c > 0 && last == tx;
-            bs.tk[r] = *slot_ptr(gkeys, tie ? (SlotIdx)(off + q[r]) * (SlotIdx)B + c - 1 : (SlotIdx)0);
+            const uint32_t leaf = min(q[r] * (uint32_t)B + c, lim);
+            bs.tk[r] = *slot_ptr(gkeys, tie ? (SlotIdx)t.leaf_base + (SlotIdx)leaf * (SlotIdx)kLS : (SlotIdx)0);
         }
     }
     static __device__ __forceinline__ void bottom_finish(const TreeDesc& t, const uint32_t* tops, const uint64_t* xh,
                                                          const uint64_t* xl, uint32_t* q, const Bottom& bs)
     {
-        const uint32_t lvl = bottom_level(t), off = t.off[lvl], lim = t.last[lvl + 1];
+        const uint32_t lvl = bottom_level(t), lim = t.last[lvl + 1];
         const K* gkeys = static_cast<const K*>(t.keys);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t tx = (uint32_t)(xh[r] >> 32), n0 = q[r] * (uint32_t)(B - 1);
             uint32_t c = bs.c[r];
             if (c > 0 && bs.last[r] == tx && key_gt(bs.tk[r], xh[r], xl[r])) {
-                const SlotIdx node = (SlotIdx)(off + q[r]) * (SlotIdx)B;
-                --c;
-                while (c > 0 && tops[n0 + c - 1] == tx && key_gt(*slot_ptr(gkeys, node + c - 1), xh[r], xl[r])) --c;
+                --c;  // further steps read key c - 1 from its leaf's slot 0 as well
+                while (c > 0 && tops[n0 + c - 1] == tx &&
+                       key_gt(*slot_ptr(gkeys, (SlotIdx)t.leaf_base + (SlotIdx)min(q[r] * (uint32_t)B + c, lim) *
+                                                                          (SlotIdx)kLS),
+                              xh[r], xl[r]))
+                    --c;
             }
             q[r] = min(q[r] * B + c, lim);
         }
