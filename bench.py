@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--skip-rebuild", action="store_true")
     ap.add_argument("--skip-ipv4", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="also time FIBs of 25k..1M prefixes with the backbone's length mix (not in the default run)")
     return ap.parse_args()
 
 
@@ -510,6 +512,42 @@ def cpu_leg(fib, addrs, got):
                        f"{dt:.1f} s"}, int((got != want).sum()))
 
 
+def size_sweep_leg(P, log_fn, n_log=26):
+    """FIBs of 25k..1M prefixes with the backbone FIB's length mix and the same
+    traffic recipe: the autotuner's pick per size (fanout 8 or 16, every
+    launch shape) timed on 2^n_log addresses, a 2^20 sample checked against
+    the oracle's trie."""
+    import dataclasses
+    import torch
+    import planb_synth as S
+    from oracle.trie import Trie, default_threads
+    from paper_2604_14650_amd import autotune
+    n = 1 << n_log
+    res = []
+    for k in (25_000, 50_000, 100_000, 200_000, 400_000, 1_000_000):
+        fib = S.make_fib(dataclasses.replace(S.BACKBONE, name=f"backbone_{k}", n_prefixes=k), 22)
+        addrs = S.backbone_traffic(fib, n, seed=1022)
+        d = upload(addrs)
+        out = torch.empty(n, dtype=torch.int16, device="cuda")
+        h, rec = autotune.tune(fib.prefixes, fib.lengths, fib.next_hops, d, min(n, 1 << 24), fanouts=(8, 16),
+                               cache_path=None, reps=3)
+        ts = time_steps(lambda: P.planb_lookup(h, d, n, out), 10, 2)
+        info = P.planb_get_info(h)
+        m = 1 << 20
+        P.planb_lookup(h, d, m, out)
+        torch.cuda.synchronize()
+        got = out[:m].cpu().numpy().view(np.uint16)
+        want = Trie(fib.prefixes, fib.lengths, fib.next_hops).lookup(addrs[:m], default_threads())
+        r = {"prefixes": k, "intervals": info["intervals"], "depth": info["depth"], "fanout": rec["fanout"],
+             "tree_bytes": info["key_bytes"] + info["value_bytes"], "tuning": rec["tuning"],
+             "glps": round(n / (sum(ts) / len(ts)) / 1e9, 2), "mismatches_2e20": int((got != want).sum())}
+        log_fn(f"size sweep: {r}")
+        res.append(r)
+        del h, d, out
+        torch.cuda.empty_cache()
+    return {"addresses": n, "sizes": res}
+
+
 def ablation_leg(P, fib, d, n, out, got, steps=3):
     """The design ladder on the headline FIB and batch (the GPU analogue of the
     paper's Section 4 ablation): binary search over the sorted starts, then
@@ -762,6 +800,8 @@ def main():
     if traffic is not None:
         result["roofline"]["traffic_bytes_per_launch"] = int(traffic)
     log(f"plain: {glps:.2f} GLPS ({info})")
+    if args.size_sweep:
+        result["size_sweep"] = size_sweep_leg(P, log)
     if not args.quick:
         if not args.skip_learned:
             result["learned"] = learned_leg(P, fib, d, n, out, args)
