@@ -411,6 +411,49 @@ def test_key_tops_in_lds_edges(P, name):
             assert np.array_equal(host_u16(out, q.shape[0]), want)
 
 
+@pytest.mark.parametrize("background", [190, 201, 213])
+def test_key_tops_ties_at_the_top_of_the_space(P, background):
+    """lds_search 2 on trees whose last leaves start with keys whose top 32 bits
+    are all ones: an address with that top ties those separators and the
+    sentinel slots after the last leaf, and walks back over several leaves
+    (each tie read comes from a leaf's first slot, clamped to the last leaf).
+    Fill levels vary with the background, so the last bottom node ends at
+    different slots."""
+    from oracle.brute import lpm_bruteforce_np
+    H = (1 << 64) - 1
+    TOP = 0xFFFFFFFF << 32
+    rng = np.random.default_rng(background)
+    rules = [(0, 0, 1)]
+    for k, v in enumerate(rng.choice(1 << 16, size=background, replace=False)):
+        hi = (0x20010DB8 << 32) | (int(v) << 16)
+        rules.append((hi << 64, 48, 2 + k % 1000))
+    tops_hi = sorted({TOP | int(v) for v in rng.integers(0, 1 << 32, size=15)})
+    for k, hi in enumerate(tops_hi):
+        rules.append((hi << 64, 64, 3000 + k))
+    p = S.from_ints([r[0] for r in rules])
+    L = np.array([r[1] for r in rules], np.uint8)
+    nh = np.array([r[2] for r in rules], np.uint16)
+    his = {H, H - 1, TOP, TOP - 1, TOP + 1}
+    for hi in tops_hi:
+        his |= {hi - 1, hi, hi + 1, hi + 2}
+    his |= {TOP | int(v) for v in rng.integers(0, 1 << 32, size=200)}
+    his |= {(0x20010DB8 << 32) | int(v) for v in rng.integers(0, 1 << 32, size=200)}
+    q = S.from_ints(sorted(h << 64 | int(rng.integers(0, 2**63)) for h in his))
+    want = lpm_bruteforce_np(p, L, nh, q)
+    reps = -(-(1 << 20) // q.shape[0])  # at least 2^20 lookups: the key-tops kernel runs
+    q, want = np.tile(q, (reps, 1)), np.tile(want, reps)
+    d = to_dev(q)
+    for fanout in (8, 16, 32):
+        h = P.planb_build(p, L, nh, fanout=fanout, key_bits=64)
+        assert P.planb_get_info(h)["depth"] >= 2
+        for kpl, R in ((fanout // 2, 2), (fanout // 4, 1)):
+            say(f"tops top-of-space background={background} fanout={fanout} kpl={kpl} R={R}")
+            P.planb_set_tuning(h, kpl, -1, R, 1024, 2)
+            out = out_u16(q.shape[0])
+            P.planb_lookup(h, d, q.shape[0], out)
+            assert np.array_equal(host_u16(out, q.shape[0]), want)
+
+
 def test_key_tops_refused_for_32bit_keys(P, tiny):
     fib, _, _ = tiny
     v4 = S.make_fib(S.IPV4_TINY, 40)
