@@ -22,8 +22,12 @@
 // themselves are freed after the launches recorded on them (planb_free).
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -40,6 +44,74 @@ double now_us()
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+
+// Host threads for the staging copies, started with the server: a launch's
+// gather of its bursts into pinned staging is split over them, since one
+// core's memcpy (about 10 GB/s) would bound the launch rate far below what
+// the PCIe link carries.  run(fn, parts) calls fn(0) on the calling thread and
+// fn(1..parts-1) on the workers, and returns when all have finished.
+class CopyPool {
+   public:
+    explicit CopyPool(unsigned workers)
+    {
+        for (unsigned k = 0; k < workers; ++k) th_.emplace_back([this, k] { loop(k + 1); });
+    }
+    ~CopyPool()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    unsigned size() const { return (unsigned)th_.size() + 1; }
+    void run(const std::function<void(unsigned)>& fn, unsigned parts)
+    {
+        parts = std::max(1u, std::min(parts, size()));
+        if (parts > 1) {
+            std::lock_guard<std::mutex> g(mu_);
+            fn_ = &fn;
+            parts_ = parts;
+            left_ = parts - 1;
+            ++gen_;
+        }
+        if (parts > 1) cv_.notify_all();
+        fn(0);
+        if (parts > 1) {
+            std::unique_lock<std::mutex> g(mu_);
+            done_cv_.wait(g, [&] { return left_ == 0; });
+            fn_ = nullptr;
+        }
+    }
+
+   private:
+    void loop(unsigned part)
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(unsigned)>* fn = nullptr;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                if (part < parts_) fn = fn_;
+            }
+            if (!fn) continue;
+            (*fn)(part);
+            std::lock_guard<std::mutex> g(mu_);
+            if (--left_ == 0) done_cv_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(unsigned)>* fn_ = nullptr;
+    unsigned parts_ = 0, left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
 
 struct Pending {
     int64_t tag;
@@ -108,6 +180,7 @@ struct planb_server {
     std::vector<Slot> slots;
     std::deque<planb_completion_t> done;
     std::vector<std::pair<uintptr_t, uintptr_t>> io;  // registered zero-copy ranges [lo, hi)
+    std::unique_ptr<CopyPool> pool;                    // staging copies (not with zero-copy bursts)
     uint64_t used_bytes = 0;
     planb_server_stats_t stats{};
 };
@@ -230,14 +303,12 @@ struct CopyJob {
     size_t bytes;
 };
 
-// Host copies into pinned staging: split over a few threads once a launch
-// carries more than a couple of MB, where one core's memcpy would otherwise
-// bound the launch rate well below what the PCIe link carries.
-void run_copies(const std::vector<CopyJob>& jobs, size_t total)
+// Host copies into pinned staging, split over the server's copy threads in
+// parts of at least 256 KB.
+void run_copies(CopyPool& pool, const std::vector<CopyJob>& jobs, size_t total)
 {
-    constexpr size_t kPerThread = 2u << 20;
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const unsigned T = (unsigned)std::min<size_t>({(size_t)8, (size_t)hw, std::max<size_t>(1, total / kPerThread)});
+    constexpr size_t kPerPart = 256u << 10;
+    const unsigned T = (unsigned)std::min<size_t>(pool.size(), std::max<size_t>(1, total / kPerPart));
     auto copy_range = [&](size_t lo, size_t hi) {  // bytes [lo, hi) of the concatenated jobs
         size_t pos = 0;
         for (const CopyJob& j : jobs) {
@@ -248,15 +319,8 @@ void run_copies(const std::vector<CopyJob>& jobs, size_t total)
             if (pos >= hi) break;
         }
     };
-    if (T <= 1) {
-        copy_range(0, total);
-        return;
-    }
-    std::vector<std::thread> th;
     const size_t chunk = (total + T - 1) / T;
-    for (unsigned k = 1; k < T; ++k) th.emplace_back(copy_range, k * chunk, std::min(total, (k + 1) * chunk));
-    copy_range(0, std::min(total, chunk));
-    for (auto& t : th) t.join();
+    pool.run([&](unsigned k) { copy_range(std::min(total, k * chunk), std::min(total, (k + 1) * chunk)); }, T);
 }
 
 void complete_with_error(planb_server_t* s, const Pending& p, int status)
@@ -347,7 +411,7 @@ int fill_slot(planb_server_t* s, Slot& sl, bool* launched)
         trees[k].lds_slots = 0;
         models[k] = ready_model_desc(fibs[k]);
     }
-    if (!copies.empty()) run_copies(copies, (size_t)na * sizeof(planb_addr_t));
+    if (!copies.empty()) run_copies(*s->pool, copies, (size_t)na * sizeof(planb_addr_t));
     std::memcpy(sl.h_desc, &nb, sizeof(uint32_t));
     const BurstRec* d_bursts = reinterpret_cast<const BurstRec*>(sl.d_desc + s->lay.bursts);
     const TreeDesc* d_trees = reinterpret_cast<const TreeDesc*>(sl.d_desc + s->lay.trees);
@@ -429,18 +493,32 @@ planb_server_t* planb_server_create(const planb_server_cfg_t* cfg_in)
     }
     s->slots.resize(cfg.streams);
     const size_t dbytes = s->lay.bytes;
+    const bool staged = !zero_copy(s);  // zero-copy launches need no address or output staging
     hipError_t e = hipSuccess;
     for (auto& sl : s->slots) {
         sl.done = std::make_shared<UseEvent>();
         if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&sl.done->ev, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_in), (size_t)cfg.max_lookups * 16, 0)) != hipSuccess ||
-            (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_out), (size_t)cfg.max_lookups * 2, 0)) != hipSuccess ||
+            (staged &&
+             (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_in), (size_t)cfg.max_lookups * 16, 0)) != hipSuccess) ||
+            (staged &&
+             (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_out), (size_t)cfg.max_lookups * 2, 0)) != hipSuccess) ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_desc), dbytes, 0)) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void**>(&sl.d_in), (size_t)cfg.max_lookups * 16)) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void**>(&sl.d_out), (size_t)cfg.max_lookups * 2)) != hipSuccess ||
+            (staged && (e = hipMalloc(reinterpret_cast<void**>(&sl.d_in), (size_t)cfg.max_lookups * 16)) != hipSuccess) ||
+            (staged && (e = hipMalloc(reinterpret_cast<void**>(&sl.d_out), (size_t)cfg.max_lookups * 2)) != hipSuccess) ||
             (e = hipMalloc(reinterpret_cast<void**>(&sl.d_desc), dbytes)) != hipSuccess)
             break;
+    }
+    if (e == hipSuccess && staged) {
+        // up to 8 copying threads in all (the caller's and 7 workers)
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        try {
+            s->pool = std::make_unique<CopyPool>(std::min(7u, hw > 1 ? hw - 1 : 0u));
+        } catch (...) {
+            fail(PLANB_ENOMEM, "cannot start the server's copy threads");
+            server_release(s);
+            return nullptr;
+        }
     }
     if (e != hipSuccess) {
         fail_hip(e, "creating the server");
