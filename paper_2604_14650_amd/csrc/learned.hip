@@ -938,18 +938,19 @@ LearnedFns learned_by_kb(int kb)
 }
 
 // The leaf-tops learned kernel: B in {8, 16} (128-byte leaves, 4 lanes of one
-// 32-byte block each), R in {1, 2}, 512 threads (the model's registers leave
-// no room for 1024-thread workgroups without spills).
-constexpr int kLearnTopsBlock = 512;
+// 32-byte block each), one lookup per lane and 768 threads.  The leaf tops
+// take most of the LDS, so one workgroup runs per CU; at 168 VGPRs a
+// 768-thread workgroup gives 3 waves per SIMD.  Two lookups per lane need 228
+// VGPRs, so only 512 threads (2 waves per SIMD): 30.9 against 33.1 GLPS on
+// the 200k backbone FIB (2^26 addresses), 26.8 against 28.2 on the tiny one.
+// 1024 threads would leave 128 VGPRs, and the model's registers spill.
+constexpr int kLearnTopsBlock = 768;
 
-void* pick_learned_tops(int B, int R)
+void* pick_learned_tops(int B)
 {
-    auto by = [&](auto b) -> void* {
-        constexpr int Bc = decltype(b)::value;
-        return R == 1 ? reinterpret_cast<void*>(learned_tops_kernel<Bc, Bc / 4, 1, kLearnTopsBlock>)
-             : R == 2 ? reinterpret_cast<void*>(learned_tops_kernel<Bc, Bc / 4, 2, kLearnTopsBlock>) : nullptr;
-    };
-    return B == 8 ? by(std::integral_constant<int, 8>{}) : B == 16 ? by(std::integral_constant<int, 16>{}) : nullptr;
+    return B == 8    ? reinterpret_cast<void*>(learned_tops_kernel<8, 2, 1, kLearnTopsBlock>)
+           : B == 16 ? reinterpret_cast<void*>(learned_tops_kernel<16, 4, 1, kLearnTopsBlock>)
+                     : nullptr;
 }
 
 LearnedFns pick_learned(int B, int kb)
@@ -1273,10 +1274,10 @@ int launch_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, 
     const u64x2* a = reinterpret_cast<const u64x2*>(addrs);
     uint64_t nn = n;
     // the leaf-tops kernel when the tree has 64-bit key slots and its leaf tops
-    // and error table fit a workgroup's LDS (lookups per group from the FIB's
-    // tuning: 1, or 2 for 2 and more), else the window search over the leaf keys
-    const int R = fib->tune.R >= 2 ? 2 : 1, bs = kLearnTopsBlock;
-    void* tops_fn = LM->leaf_tops ? pick_learned_tops((int)t.fanout, R) : nullptr;
+    // and error table fit a workgroup's LDS, else the window search over the
+    // leaf keys
+    const int R = 1, bs = kLearnTopsBlock;
+    void* tops_fn = LM->leaf_tops ? pick_learned_tops((int)t.fanout) : nullptr;
     const size_t tops_lds = learned_tops_lds_bytes(LM->nleaves, LM->segments);
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, fq.count);
     if (tops_fn && tops_lds <= (size_t)p.max_lds) {
