@@ -155,20 +155,23 @@ struct InferConsts {
     uint32_t w3[8];  // w3[16mb + 4g + 2k], w3[16mb + 4g + 2k + 1] as bf16 bits, low half first
 };
 
+// Both loaders read runs of 4 consecutive parameters with one 8- or 16-byte
+// load (every offset below is a multiple of 4 parameters, and the parameter
+// arrays are allocation-aligned): the multi-FIB kernel reloads them whenever
+// a wavefront's tile changes table, so their cost is paid per 64 lookups.
 __device__ inline void load_consts(const ModelDesc& M, InferConsts& C)
 {
     const int g = (threadIdx.x & 63) >> 4;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            C.b1[mb][i] = M.w[ob1 + 16 * mb + 4 * g + i];
-            C.b2[mb][i] = M.w[ob2 + 16 * mb + 4 * g + i];
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-            C.w3[2 * mb + k] = (uint32_t)M.wb[ow3 + 16 * mb + 4 * g + 2 * k] |
-                               ((uint32_t)M.wb[ow3 + 16 * mb + 4 * g + 2 * k + 1] << 16);
+        const float4 v1 = *reinterpret_cast<const float4*>(M.w + ob1 + 16 * mb + 4 * g);
+        const float4 v2 = *reinterpret_cast<const float4*>(M.w + ob2 + 16 * mb + 4 * g);
+        C.b1[mb] = f4{v1.x, v1.y, v1.z, v1.w};
+        C.b2[mb] = f4{v2.x, v2.y, v2.z, v2.w};
+        // w3[16mb + 4g + 2k], w3[16mb + 4g + 2k + 1]: low half first, as stored
+        const uint2 w3 = *reinterpret_cast<const uint2*>(M.wb + ow3 + 16 * mb + 4 * g);
+        C.w3[2 * mb] = w3.x;
+        C.w3[2 * mb + 1] = w3.y;
     }
 }
 
@@ -176,21 +179,27 @@ __device__ inline void load_infer(const uint16_t* wb, InferRegs& R)
 {
     const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < 4; ++mb) {
+        const uint2 v = *reinterpret_cast<const uint2*>(wb + oW1 + (16 * mb + c) * kF + 4 * g);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const __bf16 w = (__bf16)(bf2f(wb[oW1 + (16 * mb + c) * kF + 4 * g + i]) * (1.0f / 256.0f));
+            const uint32_t word = i < 2 ? v.x : v.y;
+            const uint16_t bits = (uint16_t)((i & 1) ? word >> 16 : word & 0xFFFFu);
+            const __bf16 w = (__bf16)(bf2f(bits) * (1.0f / 256.0f));
             R.w1[mb][i] = (short)__builtin_bit_cast(uint16_t, w);
         }
+    }
+    // K slots 0..3 of chunk q are units 32q + 4g + j, slots 4..7 units 32q + 16 + 4g + j
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int unit = 32 * q + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
-                R.w2[mb][q][j] = bf_bits(wb[oW2 + (16 * mb + c) * kH + unit]);
-            }
+        for (int q = 0; q < 2; ++q) {
+            const uint16_t* row = wb + oW2 + (16 * mb + c) * kH + 32 * q;
+            const uint2 lo = *reinterpret_cast<const uint2*>(row + 4 * g);
+            const uint2 hi = *reinterpret_cast<const uint2*>(row + 16 + 4 * g);
+            typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+            R.w2[mb][q] = __builtin_bit_cast(bf8, u4{lo.x, lo.y, hi.x, hi.y});
+        }
 }
 
 // ReLU on the bit pattern: one integer max.  A float whose sign bit is set
@@ -272,14 +281,15 @@ __device__ inline uint64_t predict_position(float y, uint64_t m)
 }
 
 
-// Plain one-lane descent (every key of each node), used for fallbacks.
+// One-lane descent (every key of each node) of the subtree rooted at node
+// `node` of level `level`: the interval of x, when it lies in that subtree.
 template <int B, int KB>
-__device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_t xlo)
+__device__ inline uint64_t descend_from(const TreeDesc& t, uint32_t level, uint32_t node, uint64_t xhi, uint64_t xlo)
 {
     using KF = KeyFmt<KB>;
     const auto* keys = static_cast<const typename KF::T*>(t.keys);
-    uint32_t q = 0;
-    for (uint32_t l = 0; l + 1 < t.depth; ++l) {
+    uint32_t q = node;
+    for (uint32_t l = level; l + 1 < t.depth; ++l) {
         const size_t nb = (size_t)(t.off[l] + q) * B;
         uint32_t c = 0;
 #pragma unroll
@@ -293,6 +303,13 @@ __device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_
     for (int s = 0; s < LC; ++s) c += KF::le(keys[nb + leaf_key_slot(s, (int)sizeof(typename KF::T))], xhi, xlo);
     const uint64_t idx = (uint64_t)q * LC + c - 1;
     return idx < t.m_minus_1 ? idx : t.m_minus_1;
+}
+
+// The whole tree, one lane (fallbacks).
+template <int B, int KB>
+__device__ inline uint64_t descend_lane(const TreeDesc& t, uint64_t xhi, uint64_t xlo)
+{
+    return descend_from<B, KB>(t, 0, 0, xhi, xlo);
 }
 
 constexpr int kLearnBlock = 256;
@@ -338,20 +355,26 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     const uint32_t e0 = M.eps[seg];
     bool ok = e0 != kEmpty;
     // widen the bound by half plus 16: interior addresses can err a little
-    // more than the sampled points; each doubling costs one probe
+    // more than the sampled points; a wider window costs at most a level more
     const uint64_t e = ok ? (uint64_t)e0 + (e0 >> 1) + 16 : 0;
     uint64_t j = 0;
     if (ok) {
-        uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
+        const uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
+        // The window is verified by key[lo] <= x < key[hi + 1], so x's interval
+        // lies in [lo, hi], and its leaf in the smallest subtree holding the
+        // leaves of lo and hi: descend that subtree (a few whole-node reads)
+        // instead of binary-searching the window key by key (one dependent
+        // read per halving).  Both start at once; the check decides.
         ok = KF::le(leaf_key<B, KB>(t, lo), xhi, xlo) &&
              (hi == m - 1 || !KF::le(leaf_key<B, KB>(t, hi + 1), xhi, xlo));
-        if (ok) {  // last index in [lo, hi] whose key is <= x
-            while (lo < hi) {
-                const uint64_t mid = (lo + hi + 1) >> 1;
-                if (KF::le(leaf_key<B, KB>(t, mid), xhi, xlo)) lo = mid; else hi = mid - 1;
-            }
-            j = lo;
+        constexpr uint32_t LC = (uint32_t)leaf_cap_for(B, (int)sizeof(typename KF::T));
+        uint32_t a = (uint32_t)(lo / LC), b = (uint32_t)(hi / LC), level = t.depth - 1;
+        while (a != b) {
+            a /= (uint32_t)B;
+            b /= (uint32_t)B;
+            --level;
         }
+        j = descend_from<B, KB>(t, level, a, xhi, xlo);
     }
     const uint64_t i = base + l;
     const bool need = !ok && i < n;
