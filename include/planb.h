@@ -242,7 +242,8 @@ int planb_get_info(const planb_fib_t* fib, planb_info_t* info);
  *                      lds_levels: the bottom one as the top 32 bits of each
  *                      key, the levels above it whole, so that only the leaf is
  *                      read from device memory; a lookup whose address ties a
- *                      bottom key's top half re-reads that node whole.
+ *                      bottom key's top half reads that whole key (from the
+ *                      first slot of the leaf it starts).
  *                      The many-FIB and IPv4 paths run this tuning as 1 with
  *                      lds_levels.  PLANB_ERANGE when those tops exceed a
  *                      workgroup's LDS.

@@ -60,11 +60,12 @@ lookup_v4_kernel(TreeDesc t, const uint32_t* __restrict__ addrs, uint64_t n, voi
 }
 
 // Hybrid descent with the bottom internal level in LDS too, as the top 32
-// bits of its 64-bit keys (half the bytes: for trees like the 200k-prefix
-// backbone table that level then fits beside the exact levels above it, and
-// a lookup's only tree access outside the CU is its leaf, unless its address
-// ties a key's top half; then its lane re-reads that node whole).  Results
-// are those of lookup_kernel.
+// bits of its 64- or 128-bit keys (a quarter or half of the bytes: for trees
+// like the 200k-prefix backbone table that level then fits beside the exact
+// levels above it, and a lookup's only tree access outside the CU is its
+// leaf, unless its address ties a key's top half; then its lane reads that
+// whole key, from the first slot of the leaf the key starts).  Results are
+// those of lookup_kernel.
 template <int B, int KPL, int R, int KB, int BS>
 __global__ void __launch_bounds__(BS)
 lookup_tops_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint64_t n, void* __restrict__ out, int index_out)
