@@ -395,7 +395,9 @@ typedef struct planb_train_report {
 /* Trains the FIB's model from scratch with the hand-written kernels (forward,
  * backward and Adam; per-workgroup gradient partials reduced in a fixed
  * order, so a seed gives the same model every run), then builds the error
- * table.  Synchronises `stream`.  report may be NULL. */
+ * table.  Synchronises `stream`.  report may be NULL.  PLANB_ERANGE for a FIB
+ * of 2^32 or more intervals (here and in planb_model_set_params): the learned
+ * kernels keep positions in 32 bits. */
 int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg, void* stream, planb_train_report_t* report);
 
 /* Exact lookup through the model (see above).  The lookups whose window check

@@ -280,6 +280,36 @@ __device__ inline uint64_t predict_position(float y, uint64_t m)
     return p < m ? p : m - 1;
 }
 
+// The error table's segment of position p: floor(p * S / m), exactly (p < m <
+// 2^32; inv_m = 1.0f / m), as the table is built.  While S <= 2^20 a float
+// estimate is within one of the quotient (q < 2^20 and the estimate's
+// relative error is a few 2^-24), and one exact 64-bit product corrects it;
+// larger tables divide.
+__device__ inline uint32_t segment_of(uint64_t p, uint32_t S, uint64_t m, float inv_m)
+{
+    const uint64_t a = p * (uint64_t)S;
+    if (S > (1u << 20)) return (uint32_t)(a / m);
+    uint64_t q = (uint64_t)((float)a * inv_m);
+    const uint64_t qm = q * m;
+    if (qm > a)
+        --q;  // one too high
+    else if (a - qm >= m)
+        ++q;  // one too low
+    return (uint32_t)q;
+}
+
+// A lookup's segment: the float estimate p * S / m, without the correction
+// (within one of the exact segment, from 4 instructions instead of a 64-bit
+// division of about 55).  An estimate off by one at a segment boundary reads
+// the neighbouring segment's bound; if that window then misses x, the
+// window's verification fails and the lookup falls back, so results stay
+// exact.
+__device__ inline uint32_t lookup_segment(uint64_t p, const ModelDesc& M)
+{
+    const uint32_t s = (uint32_t)((float)p * M.seg_scale);
+    return s < M.segments ? s : M.segments - 1;
+}
+
 
 // One-lane descent (every key of each node) of the subtree rooted at node
 // `node` of level `level`: the interval of x, when it lies in that subtree.
@@ -351,7 +381,7 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     }
     // this lane's address is base + 16g + c = base + l
     const uint64_t p = predict_position(y, m);
-    const uint32_t seg = (uint32_t)(p * M.segments / m);
+    const uint32_t seg = lookup_segment(p, M);
     const uint32_t e0 = M.eps[seg];
     bool ok = e0 != kEmpty;
     // widen the bound by half plus 16: interior addresses can err a little
@@ -368,7 +398,7 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
         ok = KF::le(leaf_key<B, KB>(t, lo), xhi, xlo) &&
              (hi == m - 1 || !KF::le(leaf_key<B, KB>(t, hi + 1), xhi, xlo));
         constexpr uint32_t LC = (uint32_t)leaf_cap_for(B, (int)sizeof(typename KF::T));
-        uint32_t a = (uint32_t)(lo / LC), b = (uint32_t)(hi / LC), level = t.depth - 1;
+        uint32_t a = (uint32_t)lo / LC, b = (uint32_t)hi / LC, level = t.depth - 1;  // lo <= hi < m < 2^32
         while (a != b) {
             a /= (uint32_t)B;
             b /= (uint32_t)B;
@@ -508,13 +538,14 @@ learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restric
             xh[r] = xhi;
             const uint32_t tx = (uint32_t)(xhi >> 32);
             const uint64_t p = predict_position(y, m);
-            const uint32_t e0 = eps[(uint32_t)(p * M.segments / m)];
-            // window of positions -> range of leaves (an empty segment searches every leaf)
+            const uint32_t e0 = eps[lookup_segment(p, M)];
+            // window of positions -> range of leaves (an empty segment searches
+            // every leaf); positions are below m < 2^32
             uint32_t q0 = 0, q1 = last_leaf;
             if (e0 != kEmpty) {
                 const uint64_t w = 2 * (uint64_t)e0 + 16;
-                q0 = (uint32_t)((p > w ? p - w : 0) / LC);
-                q1 = (uint32_t)min((p + w) / LC, (uint64_t)last_leaf);
+                q0 = (uint32_t)(p > w ? p - w : 0) / LC;
+                q1 = (uint32_t)min(p + w, m - 1) / LC;
             }
             // last leaf in [q0, q1] whose top is <= tx
             uint32_t lo = q0, len = q1 - q0 + 1;
@@ -695,13 +726,13 @@ predict_kernel(ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, float* 
 
 // eps_acc[seg] = max over points of (|p - idx| + 1); 0 = no point.
 __global__ void eps_accumulate_kernel(const float* __restrict__ y, const uint32_t* __restrict__ idx, uint64_t npts,
-                                      uint64_t m, uint32_t segments, uint32_t* __restrict__ eps_acc)
+                                      uint64_t m, uint32_t segments, float inv_m, uint32_t* __restrict__ eps_acc)
 {
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts; k += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t p = predict_position(y[k], m);
         const uint64_t want = idx[k];
         const uint64_t err = p > want ? p - want : want - p;
-        const uint32_t seg = (uint32_t)(p * segments / m);
+        const uint32_t seg = segment_of(p, segments, m, inv_m);
         atomicMax(eps_acc + seg, (uint32_t)min(err + 1, (uint64_t)0xFFFFFFFEu));
     }
 }
@@ -932,6 +963,7 @@ struct LearnedModel {
     uint16_t* wb = nullptr;  // bf16 copy
     uint32_t* eps = nullptr;
     uint32_t segments = 0;
+    float seg_scale = 0.f;  // segments / m
     float* partials = nullptr;
     uint32_t max_parts = 256;
     uint64_t adam_steps = 0;
@@ -988,12 +1020,14 @@ LearnedFns pick_learned(int B, int kb)
 
 ModelDesc model_desc(const LearnedModel* L)
 {
-    return ModelDesc{L->wb, L->w, L->eps, L->segments};
+    return ModelDesc{L->wb, L->w, L->eps, L->segments, L->seg_scale};
 }
 
 int ensure_model(planb_fib_t* f, uint32_t segments)
 {
     if (segments == 0) segments = 4096;
+    // the learned kernels keep positions in 32 bits
+    if (f->desc.m_minus_1 >= 0xFFFFFFFFull) return fail(PLANB_ERANGE, "a learned model needs fewer than 2^32 intervals");
     LearnedModel* L = f->learned;
     if (L && L->segments != segments) {
         release_learned(f);
@@ -1004,6 +1038,7 @@ int ensure_model(planb_fib_t* f, uint32_t segments)
     if (!L) return fail(PLANB_ENOMEM, "out of host memory");
     f->learned = L;
     L->segments = segments;
+    L->seg_scale = (float)((double)segments / (double)(f->desc.m_minus_1 + 1));
     hipError_t e;
     auto get = [&](auto** p, size_t bytes) { return fib_alloc(f->device, reinterpret_cast<void**>(p), bytes); };
     if ((e = get(&L->w, kParams * 4)) != hipSuccess || (e = get(&L->m1, kParams * 4)) != hipSuccess ||
@@ -1144,7 +1179,7 @@ int build_eps(planb_fib_t* f, const u64x2* d_pts, const uint32_t* d_idx, uint64_
     hipError_t e = hipMemsetAsync(L->eps, 0, (size_t)L->segments * 4, st);
     if (e != hipSuccess) return fail_hip(e, "clearing the epsilon table");
     hipLaunchKernelGGL(eps_accumulate_kernel, dim3((unsigned)std::min<uint64_t>((npts + 255) / 256, 4096)), dim3(256), 0,
-                       st, d_y, d_idx, npts, m, L->segments, L->eps);
+                       st, d_y, d_idx, npts, m, L->segments, 1.0f / (float)m, L->eps);
     hipLaunchKernelGGL(eps_finalize_kernel, dim3((L->segments + 255) / 256), dim3(256), 0, st, L->eps, L->segments);
     e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "epsilon table launch");
@@ -1184,7 +1219,7 @@ size_t learned_model_bytes(uint32_t segments, uint64_t nleaves)
 
 ModelDesc ready_model_desc(const planb_fib_t* f)
 {
-    if (!f || !f->learned || !f->learned->has_eps) return ModelDesc{nullptr, nullptr, nullptr, 0};
+    if (!f || !f->learned || !f->learned->has_eps) return ModelDesc{nullptr, nullptr, nullptr, 0, 0.f};
     return model_desc(f->learned);
 }
 

@@ -13,6 +13,7 @@ struct ModelDesc {
     const float* w;      // float32 master vector (biases are read from it)
     const uint32_t* eps; // per-segment error bound, kEmpty = no training point predicts there
     uint32_t segments;
+    float seg_scale;      // segments / m for m intervals: a lookup's error-table segment is about p * seg_scale
 };
 
 // Device bytes a model with `segments` error-table entries holds (weights,
