@@ -216,11 +216,13 @@ __device__ inline float mlp_infer(const InferRegs& R, const InferConsts& C, floa
     const int g = (threadIdx.x & 63) >> 4;
     // bytes 4g .. 4g + 3 of the address, most significant first, as bf16 integers
     const uint32_t w = (uint32_t)((g < 2 ? xhi : xlo) >> ((g & 1) ? 0 : 32));
-    s4 xb;
-    xb[0] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)(w >> 24));
-    xb[1] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)((w >> 16) & 0xFFu));
-    xb[2] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)((w >> 8) & 0xFFu));
-    xb[3] = (short)__builtin_bit_cast(uint16_t, (__bf16)(float)(w & 0xFFu));
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    typedef float fl2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    // two bytes per conversion instruction (exact: integers below 256)
+    const bf2 b01 = __builtin_convertvector(fl2{(float)(w >> 24), (float)((w >> 16) & 0xFFu)}, bf2);
+    const bf2 b23 = __builtin_convertvector(fl2{(float)((w >> 8) & 0xFFu), (float)(w & 0xFFu)}, bf2);
+    const s4 xb = __builtin_bit_cast(s4, u2{__builtin_bit_cast(uint32_t, b01), __builtin_bit_cast(uint32_t, b23)});
     // h1 = bf16(ReLU(z)) = ReLU(bf16(z)) (rounding keeps the sign), so round two
     // values at a time and take the ReLU of the packed pair with one 16-bit max
     uint32_t hp[2][4];
@@ -229,8 +231,6 @@ __device__ inline float mlp_infer(const InferRegs& R, const InferConsts& C, floa
         const f4 z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[mb], xb, C.b1[mb], 0, 0, 0);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-            typedef float fl2 __attribute__((ext_vector_type(2)));
             typedef short sh2 __attribute__((ext_vector_type(2)));
             const bf2 pr = __builtin_convertvector(fl2{z[2 * k], z[2 * k + 1]}, bf2);
             const sh2 v = __builtin_elementwise_max(__builtin_bit_cast(sh2, pr), sh2{0, 0});
