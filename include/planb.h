@@ -393,7 +393,7 @@ typedef struct planb_train_report {
     float seconds;           /* wall time of planb_train */
     uint32_t max_eps;        /* largest error bound over non-empty segments */
     float mean_eps;          /* mean error bound over non-empty segments */
-    uint32_t empty_segments; /* segments no point predicts into (always fall back) */
+    uint32_t empty_segments; /* segments no point predicts into (searched over the whole tree) */
 } planb_train_report_t;
 
 /* Trains the FIB's model from scratch with the hand-written kernels (forward,
@@ -437,7 +437,7 @@ int planb_lookup_learned_noalloc(const planb_fib_t* fib, const planb_addr_t* add
 /* Model access (tests, checkpoints).  The flat parameter vector holds W1
  * (64 x 16, row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1):
  * planb_model_num_params() floats.  set_params creates the model if needed,
- * resets the Adam state and leaves every segment "empty" (always fall back)
+ * resets the Adam state and leaves every segment "empty" (whole-tree searches)
  * until planb_model_build_eps or planb_model_set_eps. */
 int planb_model_num_params(void);
 int planb_model_set_params(planb_fib_t* fib, const float* params, uint32_t segments);

@@ -383,28 +383,68 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     const uint64_t p = predict_position(y, m);
     const uint32_t seg = lookup_segment(p, M);
     const uint32_t e0 = M.eps[seg];
-    bool ok = e0 != kEmpty;
     // widen the bound by half plus 16: interior addresses can err a little
-    // more than the sampled points; a wider window costs at most a level more
-    const uint64_t e = ok ? (uint64_t)e0 + (e0 >> 1) + 16 : 0;
-    uint64_t j = 0;
-    if (ok) {
-        const uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
-        // The window is verified by key[lo] <= x < key[hi + 1], so x's interval
-        // lies in [lo, hi], and its leaf in the smallest subtree holding the
-        // leaves of lo and hi: descend that subtree (a few whole-node reads)
-        // instead of binary-searching the window key by key (one dependent
-        // read per halving).  Both start at once; the check decides.
-        ok = KF::le(leaf_key<B, KB>(t, lo), xhi, xlo) &&
-             (hi == m - 1 || !KF::le(leaf_key<B, KB>(t, hi + 1), xhi, xlo));
-        constexpr uint32_t LC = (uint32_t)leaf_cap_for(B, (int)sizeof(typename KF::T));
-        uint32_t a = (uint32_t)lo / LC, b = (uint32_t)hi / LC, level = t.depth - 1;  // lo <= hi < m < 2^32
-        while (a != b) {
-            a /= (uint32_t)B;
-            b /= (uint32_t)B;
-            --level;
-        }
-        j = descend_from<B, KB>(t, level, a, xhi, xlo);
+    // more than the sampled points; a wider window costs at most a level more.
+    // An empty segment (no bound) takes the whole tree.
+    const uint64_t e = e0 != kEmpty ? (uint64_t)e0 + (e0 >> 1) + 16 : m;
+    const uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
+    // The window is verified by key[lo] <= x < key[hi + 1], so x's interval
+    // lies in [lo, hi], and its leaf in the smallest subtree holding the
+    // leaves of lo and hi: lane groups descend that subtree with whole-node
+    // reads (a few levels) instead of one lane binary-searching the window
+    // key by key (one dependent read per halving).  Both start at once; the
+    // check decides.
+    const bool ok = KF::le(leaf_key<B, KB>(t, lo), xhi, xlo) &&
+                    (hi == m - 1 || !KF::le(leaf_key<B, KB>(t, hi + 1), xhi, xlo));
+    constexpr uint32_t LC = (uint32_t)leaf_cap_for(B, (int)sizeof(typename KF::T));
+    uint32_t a = (uint32_t)lo / LC, b = (uint32_t)hi / LC, level = t.depth - 1;  // lo <= hi < m < 2^32
+    while (a != b) {
+        a /= (uint32_t)B;
+        b /= (uint32_t)B;
+        --level;
+    }
+    // groups of G = 4 lanes take the wavefront's 64 subtrees in G rounds: round
+    // u serves owner lane (u % G) * LPW + lane / G (the plain lookup's hand-off)
+    using D = Descent<B, B / 4, 1, KB, false>;
+    constexpr int G = D::G, LPW = D::LPW, T = G;
+    const int grp = l / G, jg = l % G;
+    uint64_t yh[T], yl[T];
+    uint32_t pv[T], sl[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int owner = (u % G) * LPW + grp;
+        yh[u] = D::shfl64(xhi, owner);
+        yl[u] = KB == 16 ? D::shfl64(xlo, owner) : 0;
+        pv[u] = (uint32_t)__shfl((int)a, owner, 64);
+        sl[u] = (uint32_t)__shfl((int)level, owner, 64);
+    }
+    const auto* gkeys = static_cast<const typename D::K*>(t.keys);
+    for (uint32_t lv = 0; lv + 1 < t.depth; ++lv) {
+        const uint32_t off = t.off[lv], lim = t.last[lv + 1];
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+            if (lv >= sl[u])  // the same for the group's G lanes
+                pv[u] = min(pv[u] * B + D::template node_count<false>(gkeys, (typename D::SlotIdx)(off + pv[u]) * B,
+                                                                      jg, yh[u], yl[u]),
+                            lim);
+    }
+    uint32_t res[T];
+    if constexpr (D::kBlockLane) {
+        D::template leaf_blocks<T>(t, gkeys, pv, yh, yl, jg, l - jg, 0, res);
+    } else {
+        uint32_t idx[T];
+        uint16_t hop[T];
+        D::template leaf_groups<T>(t, gkeys, pv, yh, yl, jg, l - jg, idx, hop);
+#pragma unroll
+        for (int u = 0; u < T; ++u) res[u] = hop[u];
+    }
+    // this lane's own result: round r * G + lane / LPW, from group lane % LPW
+    const int gsel = l / LPW, src = (l % LPW) * G;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const uint32_t got = (uint32_t)__shfl((int)res[k], src, 64);
+        v = k == gsel ? got : v;
     }
     const uint64_t i = base + l;
     const bool need = !ok && i < n;
@@ -419,10 +459,10 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
             const uint32_t slot = first + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
             if (need && slot < fq.cap) fq.idx[slot] = (uint32_t)i;  // cap >= n: always taken
         }
-        if (ok && i < n) __builtin_nontemporal_store(t.vals[j], out + i);
+        if (ok && i < n) __builtin_nontemporal_store((uint16_t)v, out + i);
     } else {
-        if (need) j = descend_lane<B, KB>(t, xhi, xlo);
-        if (i < n) __builtin_nontemporal_store(t.vals[j], out + i);
+        if (need) v = t.vals[descend_lane<B, KB>(t, xhi, xlo)];
+        if (i < n) __builtin_nontemporal_store((uint16_t)v, out + i);
         if (fallbacks) {
             const uint64_t mask = __ballot(need);
             if (l == 0 && mask) atomicAdd(fallbacks, (uint32_t)__popcll(mask));

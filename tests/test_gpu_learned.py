@@ -214,10 +214,9 @@ def test_learned_lookup_exact_tiny(P, trained_tiny):
 @pytest.mark.parametrize("key_bits", [0, 128])
 def test_forced_fallbacks_stay_exact(P, key_bits):
     """Error bounds forced to zero (windows of a few positions), to "empty" and
-    to the whole range.  With 64-bit key slots the leaf-tops kernel runs: an
-    empty segment searches every leaf's top (no fallback).  With 128-bit slots
-    the leaf-key window search runs: an empty segment always falls back.  Every
-    result equals the oracle's."""
+    to the whole range.  With 64-bit key slots the leaf-tops kernel runs, with
+    128-bit slots the subtree search; in both an empty segment searches the
+    whole tree (no fallback).  Every result equals the oracle's."""
     fib = fib_of("tiny", 11)
     h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, key_bits=key_bits)
     P.planb_train(h, seed=7)
@@ -229,7 +228,7 @@ def test_forced_fallbacks_stay_exact(P, key_bits):
     assert np.array_equal(got, want) and fb > 0
     P.planb_model_set_eps(h, np.full(G, 0xFFFFFFFF, np.uint32))
     got, fb = _learned(P, h, addrs)
-    assert np.array_equal(got, want) and fb == (0 if key_bits == 0 else len(addrs))
+    assert np.array_equal(got, want) and fb == 0
     P.planb_model_set_eps(h, np.full(G, 1 << 30, np.uint32))  # whole-range windows
     got, fb = _learned(P, h, addrs)
     assert np.array_equal(got, want) and fb == 0
