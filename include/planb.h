@@ -566,8 +566,9 @@ int planb_server_submit(planb_server_t* server, uint32_t table, const planb_addr
                         uint16_t* out, int64_t tag);
 /* Registers [base, base + bytes) as I/O memory for zero-copy bursts.  It must
  * be pinned host memory the device can address at the same addresses
- * (hipHostMalloc, or a pinned torch tensor); PLANB_EINVAL otherwise.  At most
- * 64 ranges; the memory must stay allocated while the server may use it. */
+ * (hipHostMalloc, or a pinned torch tensor), within one allocation;
+ * PLANB_EINVAL otherwise.  At most 64 ranges; the memory must stay allocated
+ * while the server may use it. */
 int planb_server_register_io(planb_server_t* server, const void* base, size_t bytes);
 /* Progresses the server and returns up to cap completions (count >= 0 or a
  * status).  block != 0 waits until at least one completion is available or

@@ -604,7 +604,15 @@ int planb_server_register_io(planb_server_t* s, const void* base, size_t bytes)
         if (a.type != hipMemoryTypeHost || !a.devicePointer || a.devicePointer != a.hostPointer)
             return fail(PLANB_EINVAL, "I/O range must be pinned host memory addressed by the device as by the host");
     }
-    const uintptr_t lo = reinterpret_cast<uintptr_t>(base);
+    // and one allocation: two adjacent pinned blocks could enclose memory that is not
+    void* abase = nullptr;
+    size_t asize = 0;
+    if (hipMemGetAddressRange(&abase, &asize, const_cast<void*>(base)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PLANB_EINVAL, "I/O range: the allocation holding it is unknown to the runtime");
+    }
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(base), alo = reinterpret_cast<uintptr_t>(abase);
+    if (lo < alo || lo + bytes > alo + asize) return fail(PLANB_EINVAL, "I/O range spans more than one allocation");
     s->io.emplace_back(lo, lo + bytes);
     return PLANB_OK;
 }
