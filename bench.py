@@ -53,7 +53,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--addresses", type=int, default=28, help="log2 of the batch size")
     ap.add_argument("--quick", action="store_true", help="headline plain lookup only (for profiling)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (PMC scaling)")
