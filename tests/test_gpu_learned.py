@@ -212,6 +212,27 @@ def test_learned_lookup_exact_tiny(P, trained_tiny):
 
 
 @pytest.mark.parametrize("key_bits", [0, 128])
+def test_learned_lookup_ragged_sizes(P, key_bits):
+    """Batches of 0, 1, 63, 64, 65, 1000, 4097 and 12345 addresses, through the
+    leaf-tops kernel (64-bit key slots) and the subtree search (128-bit): every
+    result equals the oracle's and nothing past n is written."""
+    import torch
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, key_bits=key_bits)
+    P.planb_train(h, seed=5)
+    addrs = S.tiny_traffic(fib, 12345, seed=77)
+    want = oracle_trie("tiny", 11).lookup(addrs)
+    d = to_dev(addrs)
+    for n in (0, 1, 63, 64, 65, 1000, 4097, 12345):
+        say(f"learned ragged key_bits={key_bits} n={n}")
+        out = torch.full((len(addrs) + 64,), -1, dtype=torch.int16, device="cuda")
+        P.planb_lookup_learned(h, d, n, out)
+        got = host_u16(out, len(addrs) + 64)
+        assert np.array_equal(got[:n], want[:n]), n
+        assert np.all(got[n:] == 0xFFFF), n
+
+
+@pytest.mark.parametrize("key_bits", [0, 128])
 def test_forced_fallbacks_stay_exact(P, key_bits):
     """Error bounds forced to zero (windows of a few positions), to "empty" and
     to the whole range.  With 64-bit key slots the leaf-tops kernel runs, with
