@@ -484,8 +484,9 @@ struct Descent {
         lo = 0;
     }
 
-    // TOPS: lds holds the key tops of every internal level (stage_tops);
-    // else the first t.lds_levels levels' keys (stage).
+    // TOPS: lds holds the exact levels above the bottom internal one, then
+    // that level's key tops (stage_bottom_tops); else the first t.lds_levels
+    // levels' keys (stage).
     template <typename A, bool TOPS = false>
     static __device__ __forceinline__ void step_hybrid(const TreeDesc& t, const void* lds, const A* addrs,
                                                        uint64_t base, uint64_t n, void* out, int index_out)

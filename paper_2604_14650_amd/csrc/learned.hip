@@ -276,7 +276,9 @@ __device__ inline uint64_t predict_position(float y, uint64_t m)
     const float pm = y * (float)m;
     if (!(pm >= 1.0f)) return 0;  // negative, tiny or NaN
     if (pm >= (float)m) return m - 1;
-    const uint64_t p = (uint64_t)floorf(pm);
+    // m < 2^32 for a learned model, so 1 <= pm < (float)m <= 2^32 and the
+    // floor fits 32 bits (a 32-bit conversion, not the 64-bit sequence)
+    const uint64_t p = (uint32_t)floorf(pm);
     return p < m ? p : m - 1;
 }
 
@@ -306,7 +308,7 @@ __device__ inline uint32_t segment_of(uint64_t p, uint32_t S, uint64_t m, float 
 // exact.
 __device__ inline uint32_t lookup_segment(uint64_t p, const ModelDesc& M)
 {
-    const uint32_t s = (uint32_t)((float)p * M.seg_scale);
+    const uint32_t s = (uint32_t)((float)(uint32_t)p * M.seg_scale);  // p < m < 2^32: the same float
     return s < M.segments ? s : M.segments - 1;
 }
 
@@ -506,9 +508,11 @@ struct LeafTops {
     uint32_t nleaves;
 };
 
+// LDS of learned_tops_kernel: the leaf tops, the error table, and 16 bytes
+// for the workgroup's largest error bound.
 __host__ __device__ inline size_t learned_tops_lds_bytes(uint32_t nleaves, uint32_t segments)
 {
-    return ((size_t)nleaves + 3) / 4 * 16 + ((size_t)segments + 3) / 4 * 16;
+    return ((size_t)nleaves + 3) / 4 * 16 + ((size_t)segments + 3) / 4 * 16 + 16;
 }
 
 template <int B, int KPL, int R, int BS>
@@ -523,9 +527,31 @@ learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restric
     extern __shared__ uint4 lds_raw[];
     uint32_t* tops = reinterpret_cast<uint32_t*>(lds_raw);
     uint32_t* eps = tops + ((size_t)lt.nleaves + 3) / 4 * 4;
-    for (uint32_t i = threadIdx.x; i < lt.nleaves; i += BS) tops[i] = lt.tops[i];
-    for (uint32_t i = threadIdx.x; i < M.segments; i += BS) eps[i] = M.eps[i];
+    uint32_t* emax_lds = eps + ((size_t)M.segments + 3) / 4 * 4;  // the largest bound (kEmpty if a segment is empty)
+    if (threadIdx.x == 0) *emax_lds = 0;
     __syncthreads();
+    for (uint32_t i = threadIdx.x; i < lt.nleaves; i += BS) tops[i] = lt.tops[i];
+    uint32_t emax = 0;
+    for (uint32_t i = threadIdx.x; i < M.segments; i += BS) {
+        const uint32_t e = M.eps[i];
+        eps[i] = e;
+        emax = max(emax, e);
+    }
+    if (emax) atomicMax(emax_lds, emax);
+    __syncthreads();
+    // Every window covers at most `span` leaves: positions p - w .. p + w with
+    // w = 2 e0 + 16 <= 2 emax + 16 span at most 2w / LC + 2 leaves, and an empty
+    // segment's window is every leaf.  The window search below takes the same
+    // power-of-two steps in every lane, from `top`, the largest power of two
+    // <= span, down to 1; they reach any count up to 2 top - 1 >= span.
+    uint32_t top;
+    {
+        const uint32_t em = *emax_lds;
+        uint64_t span = lt.nleaves;
+        if (em != kEmpty) span = min(span, 2 * (2 * (uint64_t)em + 16) / LC + 2);
+        top = 1u << (31 - __builtin_clz((uint32_t)span));  // span >= 1
+        top = (uint32_t)__builtin_amdgcn_readfirstlane((int)top);
+    }
     InferRegs Rg;
     load_infer(M.wb, Rg);
     InferConsts C;
@@ -587,17 +613,16 @@ learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restric
                 q0 = (uint32_t)(p > w ? p - w : 0) / LC;
                 q1 = (uint32_t)min(p + w, m - 1) / LC;
             }
-            // last leaf in [q0, q1] whose top is <= tx
-            uint32_t lo = q0, len = q1 - q0 + 1;
-            while (len > 0) {
-                const uint32_t half = len >> 1;
-                if (tops[lo + half] <= tx) {
-                    lo += half + 1;
-                    len -= half + 1;
-                } else {
-                    len = half;
-                }
+            // lo = q0 + the number of leaves in [q0, q1] whose top is <= tx (the
+            // tops are sorted): counted over that range extended past q1 by
+            // copies of tops[q1], which keeps it sorted, with the same steps in
+            // every lane (no divergent loop), then clamped to the range
+            uint32_t cnt = 0;
+            for (uint32_t s = top; s != 0; s >>= 1) {
+                const uint32_t more = cnt + s;
+                cnt = tops[min(q0 + more - 1, q1)] <= tx ? more : cnt;
             }
+            const uint32_t lo = q0 + min(cnt, q1 - q0 + 1);
             // verified on the tops: some leaf of the range starts at or below x's
             // top, and the leaf after the range starts above it
             ok[r] = lo > q0 && (lo <= q1 || q1 == last_leaf || tops[q1 + 1] > tx);
