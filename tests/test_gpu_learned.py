@@ -255,6 +255,45 @@ def test_forced_fallbacks_stay_exact(P, key_bits):
     assert np.array_equal(got, want) and fb == 0
 
 
+def _interval_edges(fib):
+    """Every prefix's first and last address and their outer neighbours, plus
+    the two ends of the address space: the addresses where one interval ends
+    and the next begins (computed from the rules alone, as 128-bit integers)."""
+    pts = {0, (1 << 128) - 1}
+    for (hi, lo), ln in zip(fib.prefixes.tolist(), fib.lengths.tolist()):
+        span = 1 << (128 - ln)
+        a = ((hi << 64) | lo) & ~(span - 1)
+        for v in (a - 1, a, a + span - 1, a + span):
+            if 0 <= v < (1 << 128):
+                pts.add(v)
+    v = sorted(pts)
+    return np.array([[x >> 64, x & ((1 << 64) - 1)] for x in v], dtype=np.uint64)
+
+
+@pytest.mark.parametrize("key_bits", [0, 128])
+def test_mixed_windows_at_interval_edges(P, key_bits):
+    """Error bounds that differ wildly from segment to segment (zero, small,
+    large, beyond the table, "empty"), so that one wavefront's lanes search
+    windows of very different widths with the same steps, on addresses at every
+    interval edge of the FIB and at both ends of the address space.  Every
+    result equals the oracle's."""
+    fib = fib_of("tiny", 11)
+    h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, key_bits=key_bits)
+    P.planb_train(h, seed=9)
+    edges = _interval_edges(fib)
+    rng = np.random.default_rng(31)
+    addrs = np.concatenate([edges, S.tiny_traffic(fib, 1 << 14, seed=14)])
+    addrs = addrs[rng.permutation(len(addrs))]
+    want = oracle_trie("tiny", 11).lookup(addrs)
+    G = len(P.planb_model_get_eps(h, 4096))
+    for trial in range(3):
+        eps = rng.choice(np.array([0, 3, 40, 700, 1 << 20, 0xFFFFFFFF], dtype=np.uint32), size=G)
+        P.planb_model_set_eps(h, eps)
+        got, fb = _learned(P, h, addrs)
+        say(f"mixed windows key_bits={key_bits} trial {trial}: {len(addrs)} addresses, {fb} fallbacks")
+        assert np.array_equal(got, want), trial
+
+
 def test_random_weights_stay_exact(P):
     fib = fib_of("tiny", 11)
     h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=8)
