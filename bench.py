@@ -185,10 +185,11 @@ def plain_leg(P, fib, d, n, out, args):
     return handles[0], res, times[0], times[128]
 
 
-def learned_on(P, fib, d, n, out, tuning, steps, want=None, epochs=0):
+def learned_on(P, fib, d, n, out, tuning, steps, want=None, epochs=0, keep=None):
     """Plain and learned lookups on one FIB and resident batch: both timed with
     events over `steps` launches, the learned results compared with the plain
-    ones (and with the oracle's, when given), the fallback rate counted."""
+    ones (and with the oracle's, when given), the fallback rate counted.  With
+    a list as `keep`, the learned results (host array) are appended to it."""
     import torch
     h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, fanout=tuning["fanout"])
     P.planb_set_tuning(h, *tuning["tuning"])
@@ -207,6 +208,8 @@ def learned_on(P, fib, d, n, out, tuning, steps, want=None, epochs=0):
     fallbacks = int(fb.item())
     same = bool(torch.equal(lout, plain_out))
     mism = None if want is None else int((lout.cpu().numpy().view(np.uint16) != want).sum())
+    if keep is not None:
+        keep.append(lout.cpu().numpy().view(np.uint16))
     tl = time_steps(lambda: P.planb_lookup_learned(h, d, n, lout), steps, 2)
     plain_glps = n / (sum(tp) / len(tp)) / 1e9
     glps = n / (sum(tl) / len(tl)) / 1e9
@@ -226,15 +229,16 @@ def learned_on(P, fib, d, n, out, tuning, steps, want=None, epochs=0):
             "train_seconds": round(train_s, 2), "train_steps": rep["steps"], "final_loss": rep["final_loss"]}
 
 
-def learned_leg(P, fib, d, n, out, args):
+def learned_leg(P, fib, d, n, out, args, keep=None):
     """The learned position model on the two FIBs it is specified for: the
-    backbone FIB with the headline batch, and the tiny FIB with its 2^20
-    addresses (checked against the oracle)."""
+    backbone FIB with the headline batch (its results appended to `keep`, for
+    the oracle's check once the oracle has run), and the tiny FIB with its 2^20
+    addresses (checked against the oracle here)."""
     import torch
     import planb_synth as S
     from oracle.trie import Trie
     res = {"backbone": learned_on(P, fib, d, n, out, KNOWN_TUNING[0], max(3, args.steps // 2),
-                                  epochs=args.learned_epochs)}
+                                  epochs=args.learned_epochs, keep=keep)}
     log(f"learned backbone: {res['backbone']}")
     tiny = S.make_fib(S.TINY, 11)
     ta = S.tiny_traffic(tiny, 1 << 20, seed=1011)
@@ -516,7 +520,7 @@ def cpu_leg(fib, addrs, got):
     dt = time.perf_counter() - t0
     return ({"value": round(addrs.shape[0] / dt / 1e9, 5), "unit": "GLPS", "cores": thr, "kind": "oracle",
              "sample": f"the whole batch ({addrs.shape[0]} addresses), binary-trie oracle, {thr} threads, "
-                       f"{dt:.1f} s"}, int((got != want).sum()))
+                       f"{dt:.1f} s"}, int((got != want).sum()), want)
 
 
 def size_sweep_leg(P, log_fn, n_log=26):
@@ -809,9 +813,10 @@ def main():
     log(f"plain: {glps:.2f} GLPS ({info})")
     if args.size_sweep:
         result["size_sweep"] = size_sweep_leg(P, log)
+    learned_out = []  # the learned lookup's results on the headline batch, for the oracle's check
     if not args.quick:
         if not args.skip_learned:
-            result["learned"] = learned_leg(P, fib, d, n, out, args)
+            result["learned"] = learned_leg(P, fib, d, n, out, args, keep=learned_out)
         if not args.skip_ablation:
             result["ablation"] = ablation_leg(P, fib, d, n, out, got)
         if not args.skip_rebuild:
@@ -834,9 +839,12 @@ def main():
             result["serving"] = serving_leg(P, log)
             log(f"serving: {result['serving']}")
     if not args.no_cpu_baseline:
-        cb, mism = cpu_leg(fib, addrs, got)
+        cb, mism, want = cpu_leg(fib, addrs, got)
         result["cpu_baseline"] = cb
         result["mismatches_vs_oracle"] = mism
+        if learned_out:  # the learned lookup's results on the same batch, against the oracle's
+            result["learned"]["backbone"]["mismatches_vs_oracle"] = int((learned_out[0] != want).sum())
+        del want, learned_out[:]
         result["cpu_btree_baseline"] = cpu_btree_leg(fib, addrs, got)
         log(f"cpu B+-tree: {result['cpu_btree_baseline']}")
     print(json.dumps(result), flush=True)
