@@ -526,8 +526,8 @@ def cpu_leg(fib, addrs, got):
 def size_sweep_leg(P, log_fn, n_log=26):
     """FIBs of 25k..1M prefixes with the backbone FIB's length mix and the same
     traffic recipe: the autotuner's pick per size (fanout 8 or 16, every
-    launch shape) timed on 2^n_log addresses, a 2^20 sample checked against
-    the oracle's trie."""
+    launch shape, tuned on the timed batch itself) timed on 2^n_log
+    addresses, a 2^20 sample checked against the oracle's trie."""
     import dataclasses
     import torch
     import planb_synth as S
@@ -540,7 +540,7 @@ def size_sweep_leg(P, log_fn, n_log=26):
         addrs = S.backbone_traffic(fib, n, seed=1022)
         d = upload(addrs)
         out = torch.empty(n, dtype=torch.int16, device="cuda")
-        h, rec = autotune.tune(fib.prefixes, fib.lengths, fib.next_hops, d, min(n, 1 << 24), fanouts=(8, 16),
+        h, rec = autotune.tune(fib.prefixes, fib.lengths, fib.next_hops, d, n, fanouts=(8, 16),
                                cache_path=None, reps=3)
         ts = time_steps(lambda: P.planb_lookup(h, d, n, out), 10, 2)
         info = P.planb_get_info(h)
