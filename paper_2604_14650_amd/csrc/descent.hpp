@@ -65,15 +65,21 @@ struct Descent {
             done = t.lds_slots < t.leaf_base ? t.lds_slots : t.leaf_base;
             const K* src = static_cast<const K*>(t.keys);
             K* dst = reinterpret_cast<K*>(lds_raw);
-            for (uint32_t i = tid; i < done; i += nthreads) {
-                const uint32_t n = i / (uint32_t)B, k = i % (uint32_t)B;
-                dst[n * (uint32_t)B + (k ^ lds_swz(n))] = src[i];
-            }
+            stage_items<4>(
+                done, (uint32_t)tid, (uint32_t)nthreads, [&](uint32_t i) { return src[i]; },
+                [&](uint32_t i, const K& v) {
+                    const uint32_t n = i / (uint32_t)B, k = i % (uint32_t)B;
+                    dst[n * (uint32_t)B + (k ^ lds_swz(n))] = v;
+                });
         }
         // internal nodes are B * sizeof(K) >= 32 bytes: done is a whole number of 16-byte units
-        const uint32_t units = (uint32_t)(t.lds_slots * sizeof(K) / 16);
-        const uint4* src = static_cast<const uint4*>(t.keys);
-        for (uint32_t i = (uint32_t)(done * sizeof(K) / 16) + tid; i < units; i += nthreads) lds_raw[i] = src[i];
+        const uint32_t first = (uint32_t)(done * sizeof(K) / 16);
+        const uint32_t units = (uint32_t)(t.lds_slots * sizeof(K) / 16) - first;
+        const uint4* src = static_cast<const uint4*>(t.keys) + first;
+        uint4* dst = lds_raw + first;
+        stage_items<4>(
+            units, (uint32_t)tid, (uint32_t)nthreads, [&](uint32_t i) { return src[i]; },
+            [&](uint32_t i, const uint4& v) { dst[i] = v; });
     }
 
     // The bottom internal level (level t.depth - 2) in LDS as the top 32 bits
@@ -95,10 +101,14 @@ struct Descent {
         const uint32_t keys = (t.off[lvl + 1] - t.off[lvl]) * (uint32_t)(B - 1);
         const uint32_t* src = static_cast<const uint32_t*>(t.keys);
         uint32_t* tops = bottom_tops(lds_raw, t);
-        for (uint32_t i = tid; i < keys; i += nthreads) {
-            const uint32_t node = i / (uint32_t)(B - 1), s = i - node * (uint32_t)(B - 1);
-            tops[i] = src[(size_t)W * ((t.off[lvl] + node) * (uint32_t)B + s) + 1];
-        }
+        const uint32_t off = t.off[lvl];
+        stage_items<16>(
+            keys, (uint32_t)tid, (uint32_t)nthreads,
+            [&](uint32_t i) {
+                const uint32_t node = i / (uint32_t)(B - 1), s = i - node * (uint32_t)(B - 1);
+                return src[(size_t)W * ((off + node) * (uint32_t)B + s) + 1];
+            },
+            [&](uint32_t i, uint32_t v) { tops[i] = v; });
     }
 
     // NW consecutive 32-bit words at p, with the widest loads their alignment

@@ -14,6 +14,28 @@ constexpr int kDevMaxLevels = 16;
 // A 16-byte address record {hi, lo} as a native vector (for streaming loads).
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
+// Staging from device memory into LDS: item i (i < count) is read by
+// load(i) and written by store(i, v), the workgroup's threads taking items
+// tid, tid + nthreads, ...  Each thread issues U reads before their stores, so
+// a round of U items costs one memory round trip: a plain strided copy loop
+// waits for every read before the next, and with a few dozen items per
+// thread that wait was most of a launch's fixed cost.  Indices past the end
+// are clamped to the last item, so every read and store is unconditional (a
+// conditional store let the compiler sink its read behind the others' wait);
+// the last item is then written more than once, always with its own value.
+template <int U, typename Load, typename Store>
+__device__ inline void stage_items(uint32_t count, uint32_t tid, uint32_t nthreads, Load load, Store store)
+{
+    if (count == 0) return;
+    for (uint32_t i = tid; i < count; i += (uint32_t)U * nthreads) {
+        decltype(load(0u)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load(min(i + (uint32_t)u * nthreads, count - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) store(min(i + (uint32_t)u * nthreads, count - 1), v[u]);
+    }
+}
+
 // What a kernel needs to descend one built tree.  Passed by value (kernarg).
 struct TreeDesc {
     const void* keys;        // slot array: internal nodes of B slots, then leaves

@@ -530,13 +530,15 @@ learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restric
     uint32_t* emax_lds = eps + ((size_t)M.segments + 3) / 4 * 4;  // the largest bound (kEmpty if a segment is empty)
     if (threadIdx.x == 0) *emax_lds = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < lt.nleaves; i += BS) tops[i] = lt.tops[i];
+    stage_items<8>(
+        lt.nleaves, threadIdx.x, BS, [&](uint32_t i) { return lt.tops[i]; }, [&](uint32_t i, uint32_t v) { tops[i] = v; });
     uint32_t emax = 0;
-    for (uint32_t i = threadIdx.x; i < M.segments; i += BS) {
-        const uint32_t e = M.eps[i];
-        eps[i] = e;
-        emax = max(emax, e);
-    }
+    stage_items<8>(
+        M.segments, threadIdx.x, BS, [&](uint32_t i) { return M.eps[i]; },
+        [&](uint32_t i, uint32_t e) {
+            eps[i] = e;
+            emax = max(emax, e);
+        });
     if (emax) atomicMax(emax_lds, emax);
     __syncthreads();
     // Every window covers at most `span` leaves: positions p - w .. p + w with
