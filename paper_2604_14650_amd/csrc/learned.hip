@@ -541,11 +541,11 @@ learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restric
         });
     if (emax) atomicMax(emax_lds, emax);
     __syncthreads();
-    // Every window covers at most `span` leaves: positions p - w .. p + w with
-    // w = 2 e0 + 16 <= 2 emax + 16 span at most 2w / LC + 2 leaves, and an empty
-    // segment's window is every leaf.  The window search below takes the same
-    // power-of-two steps in every lane, from `top`, the largest power of two
-    // <= span, down to 1; they reach any count up to 2 top - 1 >= span.
+    // Every window covers at most `span` leaves: its positions p - w .. p + w
+    // (w = 2 e0 + 16 <= 2 emax + 16) fall in at most 2w / LC + 2 leaves, and an
+    // empty segment's window is every leaf.  The window search below takes the
+    // same power-of-two steps in every lane, from `top`, the largest power of
+    // two <= span, down to 1; they reach any count up to 2 top - 1 >= span.
     uint32_t top;
     {
         const uint32_t em = *emax_lds;
