@@ -736,8 +736,8 @@ def cpu_btree_leg(fib, addrs, got, warmup=3, reps=20, single_sample=1 << 24):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU (got --gpus {args.gpus}); the lookup shards by replicating the FIB "
-              "and splitting the batch across GPUs, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}); across GPUs the lookup would replicate "
+              "the FIB on each and split the batch between them, with no exchange", file=sys.stderr)
         sys.exit(2)
     import torch
 
