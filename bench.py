@@ -293,8 +293,10 @@ def uneven_leg(P, log_fn, n_batches=512, seed=1033, buckets=(256, 4096, 1 << 16,
     all of them in one persistent launch, and in one graph replay; then each
     batch alone (enqueue to completion, host clock) as a plain launch and as a
     graph replay of its bucket's shape, and empty graph replays (the replay's
-    own cost).  Every mode's output is compared with the trie oracle over all
-    batches."""
+    own cost).  The persistent launch and the graph over every batch take the
+    shape, of the two largest buckets' picks, that runs this batch set fastest
+    (autotune.tune_batches).  Every mode's output is compared with the trie
+    oracle over all batches."""
     import torch
     import planb_synth as S
     from oracle.trie import Trie, default_threads
@@ -336,7 +338,13 @@ def uneven_leg(P, log_fn, n_batches=512, seed=1033, buckets=(256, 4096, 1 << 16,
     desc = torch.from_numpy(np.frombuffer(bytes(P.batch_array(
         [(d[offs[i]:], out[offs[i]:], int(sizes[i])) for i in range(n_batches)])), dtype=np.uint8).copy()).cuda()
     cnt = torch.tensor([n_batches], dtype=torch.int32, device="cuda")
-    P.planb_set_tuning(h, **table[-1][1])  # the largest bucket's shape for launches over every batch
+    # launches over every batch: the shape, among the two largest buckets' picks, that runs this batch set fastest
+    cands = []
+    for _, tu in table[-2:]:
+        if tu not in cands:
+            cands.append(tu)
+    shape, shape_ms = autotune.tune_batches(h, desc, cnt, n_batches, cands)
+    res["persistent_shape"] = {"tuning": shape, "candidates_ms": {json.dumps(c): shape_ms[k] for k, c in enumerate(cands)}}
     ts = time_steps(lambda: P.planb_lookup_batches(h, desc, cnt, n_batches), 5, 1)
     res["persistent_glps"] = round(total / (sum(ts) / len(ts)) / 1e9, 3)
     check("persistent")

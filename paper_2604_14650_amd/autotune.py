@@ -128,3 +128,32 @@ def tune_sizes(prefixes, lengths, next_hops, sample, sizes, fanouts=(8, 16, 32),
         cache[key] = rec
         _save(cache_path, cache)
     return h, dict(rec, cached=False)
+
+
+def tune_batches(h, batches, n_batches, max_batches: int, candidates, reps: int = 2, stream=None):
+    """The launch shape for persistent multi-batch launches (planb_lookup_batches
+    and the graphs built on the handle afterwards): each candidate tuning is
+    timed on the caller's own batch set (one warm-up, then `reps` launches,
+    HIP events on `stream`) and the fastest is applied.  Returns (tuning,
+    {candidate index: ms per launch}).  The shape that wins one batch size
+    need not win a launch over many uneven batches, where the tiles of every
+    batch share the grid."""
+    import torch
+    stream = torch.cuda.current_stream() if stream is None else stream
+    times = {}
+    best = None
+    for k, tu in enumerate(candidates):
+        P.planb_set_tuning(h, **tu)
+        P.planb_lookup_batches(h, batches, n_batches, max_batches, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            P.planb_lookup_batches(h, batches, n_batches, max_batches, stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        times[k] = round(ms, 4)
+        if best is None or ms < best[0]:
+            best = (ms, tu)
+    P.planb_set_tuning(h, **best[1])
+    return best[1], times

@@ -213,6 +213,14 @@ def test_uneven_batches_up_to_4m_on_the_large_fib(P):
     cnt = torch.tensor([len(sizes)], dtype=torch.int32, device="cuda")
     P.planb_lookup_batches(h, desc, cnt, len(sizes))
     assert np.array_equal(host_u16(out, len(addrs)), want)
+    say("the persistent launch's shape chosen by timing this batch set")
+    cands = [table[-1][1], table[-2][1], table[0][1]]
+    shape, ms = autotune.tune_batches(h, desc, cnt, len(sizes), cands, reps=1)
+    assert shape in cands and sorted(ms) == list(range(len(cands)))
+    assert P.planb_get_tuning(h) == shape
+    out.fill_(-1)
+    P.planb_lookup_batches(h, desc, cnt, len(sizes))
+    assert np.array_equal(host_u16(out, len(addrs)), want)
     say("every batch in one graph replay")
     g = P.Graph(h, 64)
     out.fill_(-1)
