@@ -742,7 +742,14 @@ multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __res
     InferConsts C;
     float b3 = 0.f;
     uint32_t loaded = 0xFFFFFFFFu;  // table whose model R and C hold
-    for (uint32_t tile = blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6); tile < total; tile += nwaves) {
+    // Each wavefront takes a contiguous run of tiles, not every nwaves-th: a
+    // burst's tiles are consecutive, so the model's 80 registers of operands
+    // are reloaded about once per burst instead of once per tile.
+    const uint32_t wave = blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
+    const uint32_t per = (total + nwaves - 1) / nwaves;
+    const uint32_t first = (uint32_t)min((uint64_t)wave * per, (uint64_t)total);
+    const uint32_t last = (uint32_t)min((uint64_t)first + per, (uint64_t)total);
+    for (uint32_t tile = first; tile < last; ++tile) {
         const uint32_t k = burst_of_tile(tile_off, nb, tile);
         const BurstRec br = bursts[k];
         const TreeDesc& t = tables[br.table];
