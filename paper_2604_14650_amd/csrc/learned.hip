@@ -721,9 +721,9 @@ fallback_kernel(TreeDesc t, const u64x2* __restrict__ addrs, uint16_t* __restric
 
 // Learned lookups of bursts that each name a table: tiles of 64 addresses
 // (one wavefront step) never cross a burst, so every step runs one table's
-// model.  A wavefront reloads the weight operands, and restages the biases in
-// its own LDS area, when its tile's table changes; a table without a model
-// is searched by the tree descent.
+// model.  A wavefront reloads the model's operands and per-row constants (80
+// registers) when its tile's table changes; a table without a model is
+// searched by the tree descent.
 template <int B, int KB>
 __global__ void __launch_bounds__(kLearnBlock)
 multi_learned_kernel(const TreeDesc* __restrict__ tables, const ModelDesc* __restrict__ models, uint32_t n_tables,
