@@ -19,7 +19,7 @@ typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 // tid, tid + nthreads, ...  Each thread issues U reads before their stores, so
 // a round of U items costs one memory round trip: a plain strided copy loop
 // waits for every read before the next, and with a few dozen items per
-// thread that wait was most of a launch's fixed cost.  Indices past the end
+// thread that wait was a large part of a launch's fixed cost.  Indices past the end
 // are clamped to the last item, so every read and store is unconditional (a
 // conditional store let the compiler sink its read behind the others' wait);
 // the last item is then written more than once, always with its own value.
