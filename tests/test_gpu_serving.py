@@ -101,6 +101,38 @@ def test_multi_fib_learned_launch(P, vrfs):
             assert np.array_equal(seg, tries[tids[i]].lookup(addrs[i])), i
 
 
+def test_multi_fib_learned_long_runs(P, vrfs):
+    """Enough bursts (3000, 32..4096 addresses) that each wavefront takes a
+    run of many consecutive tiles, crossing bursts, tables with and without a
+    model, and empty bursts: every burst equals the oracle."""
+    import torch
+    tabs, tries = vrfs
+    ts = P.TableSet(len(tabs))
+    fibs = [P.planb_build(t.prefixes, t.lengths, t.next_hops, fanout=16) for t in tabs]
+    for k, f in enumerate(fibs):
+        if k != 3:  # table 3 keeps no model: the tree descent inside the runs
+            P.planb_train(f, seed=k, epochs=2)
+        ts.set(k, f)
+    sizes, tids, addrs = _bursts(tabs, 3000, 21, lo=32, hi=4096)
+    for i in (5, 1500, 2999):
+        sizes[i] = 0
+        addrs[i] = addrs[i][:0]
+    flat = np.concatenate(addrs)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    say(f"learned multi-FIB long runs: {len(sizes)} bursts, {len(flat)} lookups")
+    d = to_dev(flat)
+    out = torch.full((len(flat),), -1, dtype=torch.int16, device="cuda")
+    rows = [(int(tids[i]), d[offs[i]:], out[offs[i]:], int(sizes[i])) if sizes[i] else (int(tids[i]), 0, 0, 0)
+            for i in range(len(sizes))]
+    desc = torch.from_numpy(np.frombuffer(bytes(P.burst_array(rows)), dtype=np.uint8).copy()).cuda()
+    cnt = torch.tensor([len(rows)], dtype=torch.int32, device="cuda")
+    P.planb_lookup_multi_learned(ts, desc, cnt, len(rows))
+    got = host_u16(out, len(flat))
+    for i in range(len(sizes)):
+        if sizes[i]:
+            assert np.array_equal(got[offs[i]:offs[i + 1]], tries[tids[i]].lookup(addrs[i])), i
+
+
 def test_learned_server_equals_oracle(P, vrfs):
     tabs, tries = vrfs
     srv = P.Server(max_tables=len(tabs), streams=2, max_bursts=64, max_lookups=1 << 16, fanout=16, key_bits=64,
