@@ -327,7 +327,7 @@ struct Descent {
     template <int NR>
     static __device__ __forceinline__ void leaf_groups(const TreeDesc& t, const K* keys, const uint32_t* q,
                                                        const uint64_t* xh, const uint64_t* xl, int j, int lane0,
-                                                       uint32_t* idx, uint16_t* hop)
+                                                       uint32_t* idx, uint16_t* hop, uint32_t* cnt)
     {
         LeafWords L[NR];
 #pragma unroll
@@ -335,9 +335,18 @@ struct Descent {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const uint32_t c = (uint32_t)group_sum<G>(leaf_lane_count(L[u], j, xh[u], xl[u]));
+            cnt[u] = c;
             idx[u] = leaf_index(t, q[u], c);
             hop[u] = leaf_pick_hop(L[u], idx[u] - q[u] * (uint32_t)kLC, lane0);
         }
+    }
+    template <int NR>
+    static __device__ __forceinline__ void leaf_groups(const TreeDesc& t, const K* keys, const uint32_t* q,
+                                                       const uint64_t* xh, const uint64_t* xl, int j, int lane0,
+                                                       uint32_t* idx, uint16_t* hop)
+    {
+        uint32_t cnt[NR];
+        leaf_groups<NR>(t, keys, q, xh, xl, j, lane0, idx, hop, cnt);
     }
 
     // The same when every lane holds one block (kBlockLane); res[u] is the
@@ -345,7 +354,7 @@ struct Descent {
     template <int NR>
     static __device__ __forceinline__ void leaf_blocks(const TreeDesc& t, const K* keys, const uint32_t* q,
                                                        const uint64_t* xh, const uint64_t* xl, int j, int lane0,
-                                                       int index_out, uint32_t* res)
+                                                       int index_out, uint32_t* res, uint32_t* cnt)
     {
         LeafWords L[NR];
 #pragma unroll
@@ -366,7 +375,16 @@ struct Descent {
                 (uint32_t)__builtin_amdgcn_ds_bpermute((lane0 + (int)lanes - 1) << 2, (int)block_hop(L[u], cl));
             const uint32_t hop = key_all_ones(xh[u], xl[u]) ? last_hop : got;
             res[u] = index_out ? leaf_index(t, q[u], sum & 0xFFu) : hop;
+            cnt[u] = sum & 0xFFu;
         }
+    }
+    template <int NR>
+    static __device__ __forceinline__ void leaf_blocks(const TreeDesc& t, const K* keys, const uint32_t* q,
+                                                       const uint64_t* xh, const uint64_t* xl, int j, int lane0,
+                                                       int index_out, uint32_t* res)
+    {
+        uint32_t cnt[NR];
+        leaf_blocks<NR>(t, keys, q, xh, xl, j, lane0, index_out, res, cnt);
     }
 
     // One lane, leaf in LDS: the count by branch-free binary search over the

@@ -390,14 +390,17 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
     // An empty segment (no bound) takes the whole tree.
     const uint64_t e = e0 != kEmpty ? (uint64_t)e0 + (e0 >> 1) + 16 : m;
     const uint64_t lo = p > e ? p - e : 0, hi = p + e < m - 1 ? p + e : m - 1;
-    // The window is verified by key[lo] <= x < key[hi + 1], so x's interval
-    // lies in [lo, hi], and its leaf in the smallest subtree holding the
-    // leaves of lo and hi: lane groups descend that subtree with whole-node
-    // reads (a few levels) instead of one lane binary-searching the window
-    // key by key (one dependent read per halving).  Both start at once; the
-    // check decides.
-    const bool ok = KF::le(leaf_key<B, KB>(t, lo), xhi, xlo) &&
-                    (hi == m - 1 || !KF::le(leaf_key<B, KB>(t, hi + 1), xhi, xlo));
+    // x's interval lies in the window [lo, hi] when the model is within its
+    // bound, and then its leaf in the smallest subtree holding the leaves of lo
+    // and hi: lane groups descend that subtree with whole-node reads (a few
+    // levels) instead of one lane binary-searching the window key by key.  The
+    // descent itself tells whether x lies in the subtree, so no key of the
+    // window is read to check it: the separators it compared bound x from
+    // below by the first key of the leaf it reached and from above by the
+    // first key of the next leaf, except at the subtree's two ends.  So the
+    // leaf's count of keys <= x is the exact interval unless it is 0 (x below
+    // the subtree's first key) or counts every key of the subtree's last leaf
+    // while another leaf follows (x may lie beyond it); those lookups fall back.
     constexpr uint32_t LC = (uint32_t)leaf_cap_for(B, (int)sizeof(typename KF::T));
     uint32_t a = (uint32_t)lo / LC, b = (uint32_t)hi / LC, level = t.depth - 1;  // lo <= hi < m < 2^32
     while (a != b) {
@@ -420,25 +423,38 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
         pv[u] = (uint32_t)__shfl((int)a, owner, 64);
         sl[u] = (uint32_t)__shfl((int)level, owner, 64);
     }
+    // bit u: round u's descent has taken the last child at every level so far,
+    // so its leaf is the subtree's last (internal nodes are full except at the
+    // tree's right edge, where no leaf follows)
+    uint32_t rightmost = (1u << T) - 1u;
     const auto* gkeys = static_cast<const typename D::K*>(t.keys);
     for (uint32_t lv = 0; lv + 1 < t.depth; ++lv) {
         const uint32_t off = t.off[lv], lim = t.last[lv + 1];
 #pragma unroll
         for (int u = 0; u < T; ++u)
-            if (lv >= sl[u])  // the same for the group's G lanes
-                pv[u] = min(pv[u] * B + D::template node_count<false>(gkeys, (typename D::SlotIdx)(off + pv[u]) * B,
-                                                                      jg, yh[u], yl[u]),
-                            lim);
+            if (lv >= sl[u]) {  // the same for the group's G lanes
+                const uint32_t c =
+                    D::template node_count<false>(gkeys, (typename D::SlotIdx)(off + pv[u]) * B, jg, yh[u], yl[u]);
+                rightmost &= c == (uint32_t)(B - 1) ? ~0u : ~(1u << u);
+                pv[u] = min(pv[u] * B + c, lim);
+            }
     }
-    uint32_t res[T];
+    uint32_t res[T], cnt[T];
     if constexpr (D::kBlockLane) {
-        D::template leaf_blocks<T>(t, gkeys, pv, yh, yl, jg, l - jg, 0, res);
+        D::template leaf_blocks<T>(t, gkeys, pv, yh, yl, jg, l - jg, 0, res, cnt);
     } else {
         uint32_t idx[T];
         uint16_t hop[T];
-        D::template leaf_groups<T>(t, gkeys, pv, yh, yl, jg, l - jg, idx, hop);
+        D::template leaf_groups<T>(t, gkeys, pv, yh, yl, jg, l - jg, idx, hop, cnt);
 #pragma unroll
         for (int u = 0; u < T; ++u) res[u] = hop[u];
+    }
+    // bit 16 of a result marks a lookup that falls back (hops are 16 bits)
+    const uint32_t last_leaf = t.last[t.depth - 1];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const bool open_top = ((rightmost >> u) & 1u) && cnt[u] == LC && pv[u] < last_leaf;
+        res[u] = (res[u] & 0xFFFFu) | (cnt[u] == 0 || open_top ? 0x10000u : 0u);
     }
     // this lane's own result: round r * G + lane / LPW, from group lane % LPW
     const int gsel = l / LPW, src = (l % LPW) * G;
@@ -448,6 +464,8 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
         const uint32_t got = (uint32_t)__shfl((int)res[k], src, 64);
         v = k == gsel ? got : v;
     }
+    const bool ok = (v & 0x10000u) == 0;
+    v &= 0xFFFFu;
     const uint64_t i = base + l;
     const bool need = !ok && i < n;
     if constexpr (QUEUE) {
