@@ -370,14 +370,16 @@ int planb_autotune_sizes(planb_fib_t* fib, const planb_addr_t* sample, size_t n,
  * becomes a range of leaves; a binary search over their tops finds the leaf,
  * verified on the tops (the range's first leaf starts at or below x's top
  * half, the leaf after it above), ties settled with whole keys; lane groups
- * then read that one leaf.  Other trees: the window w = eps + eps/2 + 16 of
- * interval positions is accepted only if key[lo] <= x and (hi = m - 1 or
- * key[hi + 1] > x), and x's interval is found by descending the smallest
- * subtree that holds the leaves of lo and hi.  A lookup's error-table
- * segment is estimated in float arithmetic (within one of the exact one; a
- * neighbouring segment's bound only narrows or widens the window, which the
- * check covers).  A lookup that fails its check runs the tree descent, so
- * results are always those of planb_lookup.
+ * then read that one leaf.  Other trees: with the window w = eps + eps/2 + 16
+ * of interval positions, x's interval is found by descending the smallest
+ * subtree that holds the leaves of lo and hi, and the result is accepted
+ * unless the leaf reached counts no key <= x (x below the subtree) or counts
+ * every key of the subtree's last leaf while another leaf follows (x may lie
+ * beyond the subtree).  A lookup's error-table segment is estimated in float
+ * arithmetic (within one of the exact one; a neighbouring segment's bound
+ * only narrows or widens the window, which the check covers).  A lookup that
+ * fails its check runs the tree descent, so results are always those of
+ * planb_lookup.
  */
 typedef struct planb_train_cfg {
     uint32_t epochs;   /* passes over the 4m sample points (0 -> about 30,000 steps in all, 8..400 passes) */
