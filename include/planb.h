@@ -406,13 +406,16 @@ typedef struct planb_train_report {
  * kernels keep positions in 32 bits. */
 int planb_train(planb_fib_t* fib, const planb_train_cfg_t* cfg, void* stream, planb_train_report_t* report);
 
-/* Exact lookup through the model (see above).  The lookups whose window check
+/* Exact lookup through the model (see above).  From 2^21 lookups (2^18 when
+ * the tree does not take the leaf-tops kernel) the lookups whose window check
  * fails are appended to a fallback queue in scratch device memory (a counter
  * and one 4-byte entry per lookup: 256 + 4n bytes, allocated with
  * hipMallocAsync on `stream` and freed with hipFreeAsync behind the work, so
  * the host never waits); a second kernel then runs the tree descent for the
- * queued lookups.  fallback_count (device uint32, may be NULL) is incremented
- * by the number of lookups that fell back -- the caller zeroes it.
+ * queued lookups.  Smaller calls run one kernel, in which such lookups
+ * descend the tree in place, and allocate nothing.  fallback_count (device
+ * uint32, may be NULL) is incremented by the number of lookups that fell
+ * back -- the caller zeroes it.
  *   addrs  device, n records, 16-byte aligned;  out: device, n uint16
  *   n      0 is a no-op; must be < 2^32
  * Returns PLANB_OK, PLANB_EINVAL (no trained model, NULL or misaligned

@@ -491,7 +491,9 @@ __device__ inline void learned_step(const TreeDesc& t, const ModelDesc& M, const
 }
 
 // Learned lookup of one batch (grid stride over 64-address wavefront steps).
-template <int B, int KB>
+// QUEUE: failing lookups go to the queue fq; else each descends the tree in
+// place and fq.count (when not null) counts them.
+template <int B, int KB, bool QUEUE>
 __global__ void __launch_bounds__(kLearnBlock)
 learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_t n, uint16_t* __restrict__ out,
                FallbackQueue fq)
@@ -503,8 +505,12 @@ learned_kernel(TreeDesc t, ModelDesc M, const u64x2* __restrict__ addrs, uint64_
     const float b3 = M.w[ob3];
     const uint64_t wave = (uint64_t)blockIdx.x * (kLearnBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kLearnBlock / 64);
-    for (uint64_t base = wave * 64; base < n; base += nwaves * 64)
-        learned_step<B, KB, true>(t, M, R, C, b3, addrs, base, n, out, nullptr, fq);
+    for (uint64_t base = wave * 64; base < n; base += nwaves * 64) {
+        if constexpr (QUEUE)
+            learned_step<B, KB, true>(t, M, R, C, b3, addrs, base, n, out, nullptr, fq);
+        else
+            learned_step<B, KB, false>(t, M, R, C, b3, addrs, base, n, out, fq.count, FallbackQueue{});
+    }
 }
 
 // ---------------------------------------------------------------- learned lookup over leaf tops
@@ -533,7 +539,9 @@ __host__ __device__ inline size_t learned_tops_lds_bytes(uint32_t nleaves, uint3
     return ((size_t)nleaves + 3) / 4 * 16 + ((size_t)segments + 3) / 4 * 16 + 16;
 }
 
-template <int B, int KPL, int R, int BS>
+// QUEUE: failing lookups go to the queue fq; else each descends the tree in
+// place and fq.count (when not null) counts them.
+template <int B, int KPL, int R, int BS, bool QUEUE>
 __global__ void __launch_bounds__(BS)
 learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restrict__ addrs, uint64_t n,
                     uint16_t* __restrict__ out, FallbackQueue fq)
@@ -692,15 +700,21 @@ learned_tops_kernel(TreeDesc t, ModelDesc M, LeafTops lt, const u64x2* __restric
             const uint64_t i = base + (uint64_t)r * 64 + l;
             const bool need = !ok[r] && i < n;
             const uint64_t mask = __ballot(need);
-            if (mask) {
-                const int first_lane = __builtin_ctzll(mask);
-                uint32_t first = 0;
-                if (l == first_lane) first = atomicAdd(fq.count, (uint32_t)__popcll(mask));
-                first = (uint32_t)__builtin_amdgcn_readlane((int)first, first_lane);
-                const uint32_t slot = first + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
-                if (need && slot < fq.cap) fq.idx[slot] = (uint32_t)i;  // cap >= n: always taken
+            if constexpr (QUEUE) {
+                if (mask) {
+                    const int first_lane = __builtin_ctzll(mask);
+                    uint32_t first = 0;
+                    if (l == first_lane) first = atomicAdd(fq.count, (uint32_t)__popcll(mask));
+                    first = (uint32_t)__builtin_amdgcn_readlane((int)first, first_lane);
+                    const uint32_t slot = first + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
+                    if (need && slot < fq.cap) fq.idx[slot] = (uint32_t)i;  // cap >= n: always taken
+                }
+                if (ok[r] && i < n) __builtin_nontemporal_store((uint16_t)v, out + i);
+            } else {
+                if (need) v = t.vals[descend_lane<B, 8>(t, xh[r], 0)];
+                if (i < n) __builtin_nontemporal_store((uint16_t)v, out + i);
+                if (fq.count && l == 0 && mask) atomicAdd(fq.count, (uint32_t)__popcll(mask));
             }
-            if (ok[r] && i < n) __builtin_nontemporal_store((uint16_t)v, out + i);
         }
     }
 }
@@ -1070,12 +1084,14 @@ namespace {
 struct LearnedFns {
     void* lookup = nullptr;
     void* fallback = nullptr;
+    void* direct = nullptr;  // the lookup with fallbacks descended in place (no queue)
 };
 
 template <int B, int KB>
 LearnedFns learned_fns()
 {
-    return {reinterpret_cast<void*>(learned_kernel<B, KB>), reinterpret_cast<void*>(fallback_kernel<B, KB>)};
+    return {reinterpret_cast<void*>(learned_kernel<B, KB, true>), reinterpret_cast<void*>(fallback_kernel<B, KB>),
+            reinterpret_cast<void*>(learned_kernel<B, KB, false>)};
 }
 
 template <int B>
@@ -1093,10 +1109,20 @@ LearnedFns learned_by_kb(int kb)
 // 1024 threads would leave 128 VGPRs, and the model's registers spill.
 constexpr int kLearnTopsBlock = 768;
 
+// planb_lookup_learned calls of fewer lookups run the direct (queue-free)
+// kernel: one launch, no allocation.  Measured crossovers (200k backbone and
+// 1k tiny FIBs): the leaf-tops kernel's in-place fallbacks are rare and short
+// (2^20 lookups: 58.6 against 66.0 us queued; 2^22: 146 against 138), the
+// other kernel's whole-tree descents of 16-byte keys cost more (2^16: 20.5
+// against 31.9 us; 2^20: 103 against 93).
+constexpr uint64_t kLearnedDirectMaxTops = 1ull << 21;
+constexpr uint64_t kLearnedDirectMax = 1ull << 18;
+
+template <bool QUEUE>
 void* pick_learned_tops(int B)
 {
-    return B == 8    ? reinterpret_cast<void*>(learned_tops_kernel<8, 2, 1, kLearnTopsBlock>)
-           : B == 16 ? reinterpret_cast<void*>(learned_tops_kernel<16, 4, 1, kLearnTopsBlock>)
+    return B == 8    ? reinterpret_cast<void*>(learned_tops_kernel<8, 2, 1, kLearnTopsBlock, QUEUE>)
+           : B == 16 ? reinterpret_cast<void*>(learned_tops_kernel<16, 4, 1, kLearnTopsBlock, QUEUE>)
                      : nullptr;
 }
 
@@ -1408,11 +1434,24 @@ int learned_check(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, c
     return check_current_device(fib);
 }
 
+// Whether a learned lookup on this FIB runs the leaf-tops kernel: 64-bit key
+// slots, and the leaf tops and error table fit a workgroup's LDS.
+bool learned_uses_tops(const planb_fib_t* fib)
+{
+    const LearnedModel* LM = fib->learned;
+    DevProps p;
+    if (!LM->leaf_tops || dev_props(&p) != hipSuccess || !pick_learned_tops<true>((int)fib->desc.fanout)) return false;
+    return learned_tops_lds_bytes(LM->nleaves, LM->segments) <= (size_t)p.max_lds;
+}
+
 // Reset the queue, run the learned lookup, then the tree descent for the
-// queued lookups; fq.cap >= n.
+// queued lookups; fq.cap >= n.  With fq.count null (direct), one launch:
+// failing lookups descend the tree in place, counted in fallback_count.
 int launch_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, uint16_t* out,
                    uint32_t* fallback_count, FallbackQueue fq, hipStream_t st)
 {
+    const bool direct = fq.count == nullptr;
+    if (direct) fq = FallbackQueue{fallback_count, nullptr, 0};
     const LearnedFns fns = pick_learned((int)fib->desc.fanout, (int)fib->desc.key_bytes);
     if (!fns.lookup) return fail(PLANB_EINVAL, "no learned kernel for this fanout");
     DevProps p;
@@ -1427,10 +1466,13 @@ int launch_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, 
     // and error table fit a workgroup's LDS, else the window search over the
     // leaf keys
     const int R = 1, bs = kLearnTopsBlock;
-    void* tops_fn = LM->leaf_tops ? pick_learned_tops((int)t.fanout) : nullptr;
+    void* tops_fn = !learned_uses_tops(fib) ? nullptr
+                    : direct                 ? pick_learned_tops<false>((int)t.fanout)
+                                             : pick_learned_tops<true>((int)t.fanout);
+    void* lookup_fn = direct ? fns.direct : fns.lookup;
     const size_t tops_lds = learned_tops_lds_bytes(LM->nleaves, LM->segments);
-    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, fq.count);
-    if (tops_fn && tops_lds <= (size_t)p.max_lds) {
+    if (!direct) hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, fq.count);
+    if (tops_fn) {
         int nb = 1;
         if ((e = occupancy(tops_fn, bs, tops_lds, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
         const uint64_t per_block = (uint64_t)(bs / 64) * 64 * R;
@@ -1441,18 +1483,20 @@ int launch_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size_t n, 
             return fail_hip(e, "learned lookup launch");
     } else {
         int nb = 1;
-        if ((e = occupancy(fns.lookup, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
+        if ((e = occupancy(lookup_fn, kLearnBlock, 0, &nb)) != hipSuccess) return fail_hip(e, "occupancy");
         const uint64_t want = (n + (kLearnBlock / 64) * 64 - 1) / ((kLearnBlock / 64) * 64);
         const unsigned grid = (unsigned)std::min<uint64_t>(want, (uint64_t)p.cus * nb);
         void* args[] = {&t, &M, &a, &nn, &out, &fq};
-        if ((e = hipLaunchKernel(fns.lookup, dim3(grid), dim3(kLearnBlock), args, 0, st)) != hipSuccess)
+        if ((e = hipLaunchKernel(lookup_fn, dim3(grid), dim3(kLearnBlock), args, 0, st)) != hipSuccess)
             return fail_hip(e, "learned lookup launch");
     }
-    // the queue's length is known only on the device: a fixed grid walks it
-    const unsigned fgrid = (unsigned)std::min<uint64_t>((n + kLearnBlock - 1) / kLearnBlock, (uint64_t)p.cus * 2);
-    void* fargs[] = {&t, &a, &out, &fq, &fallback_count};
-    if ((e = hipLaunchKernel(fns.fallback, dim3(fgrid), dim3(kLearnBlock), fargs, 0, st)) != hipSuccess)
-        return fail_hip(e, "fallback launch");
+    if (!direct) {
+        // the queue's length is known only on the device: a fixed grid walks it
+        const unsigned fgrid = (unsigned)std::min<uint64_t>((n + kLearnBlock - 1) / kLearnBlock, (uint64_t)p.cus * 2);
+        void* fargs[] = {&t, &a, &out, &fq, &fallback_count};
+        if ((e = hipLaunchKernel(fns.fallback, dim3(fgrid), dim3(kLearnBlock), fargs, 0, st)) != hipSuccess)
+            return fail_hip(e, "fallback launch");
+    }
     if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "learned lookup launch");
     note_use(fib->uses, st);
     return PLANB_OK;
@@ -1674,9 +1718,14 @@ int planb_lookup_learned(const planb_fib_t* fib, const planb_addr_t* addrs, size
 {
     int rc = learned_check(fib, addrs, n, out, fallback_count);
     if (rc != PLANB_OK || n == 0) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // Small calls run one kernel that descends the tree in place for its few
+    // failing lookups: the queue's allocation and two more launches would
+    // cost them more than a wavefront waiting for one lane's descent.
+    if (n < (learned_uses_tops(fib) ? kLearnedDirectMaxTops : kLearnedDirectMax))
+        return launch_learned(fib, addrs, n, out, fallback_count, FallbackQueue{}, st);
     // the fallback queue: a counter and one entry per lookup, from the
     // stream-ordered pool (allocated and freed in stream order: no host wait)
-    hipStream_t st = static_cast<hipStream_t>(stream);
     void* scratch = nullptr;
     const size_t bytes = kQueueHeaderBytes + (size_t)n * 4;
     hipError_t e = hipMallocAsync(&scratch, bytes, st);

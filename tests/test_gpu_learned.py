@@ -232,16 +232,19 @@ def test_learned_lookup_ragged_sizes(P, key_bits):
         assert np.all(got[n:] == 0xFFFF), n
 
 
+@pytest.mark.parametrize("n", [1 << 16, (1 << 21) + 5])
 @pytest.mark.parametrize("key_bits", [0, 128])
-def test_forced_fallbacks_stay_exact(P, key_bits):
+def test_forced_fallbacks_stay_exact(P, key_bits, n):
     """Error bounds forced to zero (windows of a few positions), to "empty" and
     to the whole range.  With 64-bit key slots the leaf-tops kernel runs, with
     128-bit slots the subtree search; in both an empty segment searches the
-    whole tree (no fallback).  Every result equals the oracle's."""
+    whole tree (no fallback).  2^16 lookups run the direct kernel (failing
+    lookups descend in place), 2^21 + 5 the queued one (a fallback kernel
+    descends them).  Every result equals the oracle's."""
     fib = fib_of("tiny", 11)
     h = P.planb_build(fib.prefixes, fib.lengths, fib.next_hops, key_bits=key_bits)
     P.planb_train(h, seed=7)
-    addrs = S.tiny_traffic(fib, 1 << 16, seed=12)
+    addrs = S.tiny_traffic(fib, n, seed=12)
     want = oracle_trie("tiny", 11).lookup(addrs)
     G = len(P.planb_model_get_eps(h, 4096))
     P.planb_model_set_eps(h, np.zeros(G, np.uint32))  # windows of +-16 positions only
