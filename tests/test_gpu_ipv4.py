@@ -132,6 +132,10 @@ def test_ipv4_device_build_and_learned(P):
     o = out_u16(a4.shape[0])
     P.planb_lookup_learned(dev, to_dev(S.v4_as_128(a4)), a4.shape[0], o)
     assert np.array_equal(host_u16(o, a4.shape[0]), want)
+    m = 1 << 16  # a small call: the queue-free kernel, fallbacks descended in place
+    o2 = out_u16(m)
+    P.planb_lookup_learned(dev, to_dev(S.v4_as_128(a4[:m])), m, o2)
+    assert np.array_equal(host_u16(o2, m), want[:m])
 
 
 def test_ipv4_batches_and_multi(P):
